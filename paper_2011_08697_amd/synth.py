@@ -1,0 +1,208 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module only draws random parameters and evaluates analytic fields; it holds none of the tracking method's
+arithmetic.  Both the HIP path and the oracle consume the arrays it returns.
+
+Moving-blob fields stand in for the paper's application datasets (flow, fusion blobs, turbulent vortices, Sec. 4.6),
+which are not available.  Recipe (drawn with numpy's PCG64, vectorised over the K blobs, in this order):
+sign = -1 where random(K) < 0.5 else +1; amplitude A ~ U(0.5, 1.5); sigma ~ U(lo, hi); centre ~ U(0, n_a) per axis
+(x, then y, then z); velocity ~ U(-v, v) per axis; then, if any, the noise array from the same generator.  Values are
+evaluated in float64, blob by blob in k order, and cast to float32.  Each blob is evaluated on a window of +-ceil(8
+sigma) cells around its centre (beyond it a term is below 1.3e-14 of its amplitude).
+
+Analytic test fields from the paper: the moving minimum (Sec. 4.5, Eq. 3-4) and the spiral woven function (Sec. 4.5,
+Eq. 5).
+"""
+import math
+
+import numpy as np
+
+
+def _blob_params(rng, K, dims_sp, sigma, vmax):
+    sign = np.where(rng.random(K) < 0.5, -1.0, 1.0)
+    amp = rng.uniform(0.5, 1.5, K)
+    sig = rng.uniform(sigma[0], sigma[1], K)
+    centre = np.stack([rng.uniform(0.0, float(N), K) for N in dims_sp], axis=1)
+    if np.isscalar(vmax) or len(np.atleast_1d(vmax)) == 1:
+        vel = np.stack([rng.uniform(-float(vmax), float(vmax), K) for _ in dims_sp], axis=1)
+    else:
+        vel = np.stack([rng.uniform(-float(v), float(v), K) for v in vmax], axis=1)
+    return sign, amp, sig, centre, vel
+
+
+def _windows(c, s, N):
+    w = int(math.ceil(8.0 * s))
+    lo = max(0, int(math.floor(c)) - w)
+    hi = min(N, int(math.floor(c)) + w + 2)
+    return lo, hi
+
+
+def moving_gaussians_2d(nx, ny, nt, K, sigma=(4.0, 10.0), vmax=1.0, seed=0, noise_std=0.0):
+    """f[t][y][x] = sum_k s_k A_k exp(-|x - c_k - v_k t|^2 / (2 sigma_k^2)) (+ iid N(0, noise_std) noise)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sign, amp, sig, centre, vel = _blob_params(rng, K, (nx, ny), sigma, vmax)
+    f = np.zeros((nt, ny, nx), np.float64)
+    for t in range(nt):
+        plane = f[t]
+        for k in range(K):
+            cx = centre[k, 0] + vel[k, 0] * t
+            cy = centre[k, 1] + vel[k, 1] * t
+            x0, x1 = _windows(cx, sig[k], nx)
+            y0, y1 = _windows(cy, sig[k], ny)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            inv = 1.0 / (2.0 * sig[k] * sig[k])
+            ex = np.exp(-((np.arange(x0, x1) - cx) ** 2) * inv)
+            ey = np.exp(-((np.arange(y0, y1) - cy) ** 2) * inv)
+            plane[y0:y1, x0:x1] += (sign[k] * amp[k]) * np.outer(ey, ex)
+    if noise_std > 0:
+        f += rng.normal(0.0, noise_std, size=f.shape)
+    return f.astype(np.float32)
+
+
+def moving_gaussians_3d(nx, ny, nz, nt, K, sigma=(6.0, 16.0), vmax=1.0, seed=2):
+    """3D analogue, f[t][z][y][x], separable window per blob."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sign, amp, sig, centre, vel = _blob_params(rng, K, (nx, ny, nz), sigma, vmax)
+    f = np.zeros((nt, nz, ny, nx), np.float64)
+    for t in range(nt):
+        vol = f[t]
+        for k in range(K):
+            c = [centre[k, a] + vel[k, a] * t for a in range(3)]
+            rx = _windows(c[0], sig[k], nx)
+            ry = _windows(c[1], sig[k], ny)
+            rz = _windows(c[2], sig[k], nz)
+            if rx[0] >= rx[1] or ry[0] >= ry[1] or rz[0] >= rz[1]:
+                continue
+            inv = 1.0 / (2.0 * sig[k] * sig[k])
+            ex = np.exp(-((np.arange(*rx) - c[0]) ** 2) * inv)
+            ey = np.exp(-((np.arange(*ry) - c[1]) ** 2) * inv)
+            ez = np.exp(-((np.arange(*rz) - c[2]) ** 2) * inv)
+            vol[rz[0]:rz[1], ry[0]:ry[1], rx[0]:rx[1]] += (sign[k] * amp[k]) * (
+                ez[:, None, None] * ey[None, :, None] * ex[None, None, :])
+    return f.astype(np.float32)
+
+
+def vortex_sources_2d(nx, ny, nt, K, sigma=(16.0, 48.0), vmax=2.0, seed=4):
+    """Vector field u[t][c][y][x]: half the blobs contribute grad G (sources/sinks), half the rotated gradient
+    (-dG/dy, dG/dx) (vortices), G = s A exp(-r^2 / (2 sigma^2)); derivatives are analytic.  The blob kind is drawn
+    after the shared parameters (kind = vortex where random(K) < 0.5)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sign, amp, sig, centre, vel = _blob_params(rng, K, (nx, ny), sigma, vmax)
+    vortex = rng.random(K) < 0.5
+    u = np.zeros((nt, 2, ny, nx), np.float64)
+    for t in range(nt):
+        for k in range(K):
+            cx = centre[k, 0] + vel[k, 0] * t
+            cy = centre[k, 1] + vel[k, 1] * t
+            x0, x1 = _windows(cx, sig[k], nx)
+            y0, y1 = _windows(cy, sig[k], ny)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            inv = 1.0 / (2.0 * sig[k] * sig[k])
+            dx = np.arange(x0, x1) - cx
+            dy = np.arange(y0, y1) - cy
+            G = (sign[k] * amp[k]) * np.outer(np.exp(-(dy ** 2) * inv), np.exp(-(dx ** 2) * inv))
+            gx = -G * (dx[None, :] / (sig[k] * sig[k]))
+            gy = -G * (dy[:, None] / (sig[k] * sig[k]))
+            if vortex[k]:
+                u[t, 0, y0:y1, x0:x1] += -gy
+                u[t, 1, y0:y1, x0:x1] += gx
+            else:
+                u[t, 0, y0:y1, x0:x1] += gx
+                u[t, 1, y0:y1, x0:x1] += gy
+    return u.astype(np.float32)
+
+
+def quantise_levels(f, levels=16):
+    """Degenerate variant: the whole series mapped affinely onto [0, levels-1] and rounded to integers."""
+    f64 = f.astype(np.float64)
+    lo, hi = f64.min(), f64.max()
+    return np.rint((f64 - lo) / (hi - lo) * (levels - 1)).astype(np.float32)
+
+
+def batch_series(count=96, seed0=3, size_range=(128, 2048), nt_range=(8, 64), k_range=(16, 512),
+                 sigma=(4.0, 10.0), vmax=1.0, shape_only=False):
+    """Many independent 2D series of uneven sizes: series i uses seed seed0 + i; nx, ny ~ round(exp(U(ln lo,
+    ln hi))), nt ~ integers in nt_range (inclusive), K = clip(round(512 nx ny / 2048^2), k_range); the blobs are
+    drawn after these with the shared recipe."""
+    out = []
+    for i in range(count):
+        rng = np.random.Generator(np.random.PCG64(seed0 + i))
+        nx = int(round(math.exp(rng.uniform(math.log(size_range[0]), math.log(size_range[1])))))
+        ny = int(round(math.exp(rng.uniform(math.log(size_range[0]), math.log(size_range[1])))))
+        nt = int(rng.integers(nt_range[0], nt_range[1] + 1))
+        K = int(np.clip(round(512 * nx * ny / 2048.0 ** 2), k_range[0], k_range[1]))
+        if shape_only:
+            out.append((nx, ny, nt, K))
+            continue
+        # the blob parameters continue from the same generator
+        sign, amp, sig, centre, vel = _blob_params(rng, K, (nx, ny), sigma, vmax)
+        f = np.zeros((nt, ny, nx), np.float64)
+        for t in range(nt):
+            for k in range(K):
+                cx = centre[k, 0] + vel[k, 0] * t
+                cy = centre[k, 1] + vel[k, 1] * t
+                x0, x1 = _windows(cx, sig[k], nx)
+                y0, y1 = _windows(cy, sig[k], ny)
+                if x0 >= x1 or y0 >= y1:
+                    continue
+                inv = 1.0 / (2.0 * sig[k] * sig[k])
+                f[t, y0:y1, x0:x1] += (sign[k] * amp[k]) * np.outer(
+                    np.exp(-((np.arange(y0, y1) - cy) ** 2) * inv), np.exp(-((np.arange(x0, x1) - cx) ** 2) * inv))
+        out.append(f.astype(np.float32))
+    return out
+
+
+def moving_minimum(n, size, x0, direction, nt):
+    """Sec. 4.5, Eq. 3: f(x, t) = |x - (x0 + d t)|^2 on a size^n grid (f[t][(z)][y][x]).  With dyadic d and integer
+    x0 every value is exact in float32."""
+    axes = [np.arange(size, dtype=np.float64)] * n
+    grids = np.meshgrid(*axes, indexing="ij")  # grids[a][i_x, i_y, ...]
+    out = []
+    for t in range(nt):
+        s = np.zeros(grids[0].shape)
+        for a in range(n):
+            s += (grids[a] - (x0[a] + direction[a] * t)) ** 2
+        out.append(np.transpose(s, tuple(range(n))[::-1]))
+    return np.asarray(out, dtype=np.float32)
+
+
+def spiral_woven(size, nt, extent, dt):
+    """Sec. 4.5, Eq. 5: f = cos(x cos t - y sin t) sin(x sin t + y cos t) on [-extent, extent]^2, f[t][y][x]."""
+    xs = np.linspace(-extent, extent, size)
+    X, Y = np.meshgrid(xs, xs, indexing="xy")
+    out = []
+    for k in range(nt):
+        t = k * dt
+        out.append(np.cos(X * np.cos(t) - Y * np.sin(t)) * np.sin(X * np.sin(t) + Y * np.cos(t)))
+    return np.asarray(out, dtype=np.float32)
+
+
+# Named workloads (sizes of the paper-shaped synthetic configurations).
+CONFIGS = {
+    "c0": dict(n=2, kind=0, dims=(64, 64, 10), K=8, seed=0),
+    "c1": dict(n=2, kind=0, dims=(1024, 1024, 100), K=256, seed=1, noise_std=1e-3),
+    "c2": dict(n=3, kind=0, dims=(256, 256, 256, 16), K=512, seed=2),
+    "c4": dict(n=2, kind=1, dims=(4096, 4096, 50), K=1024, seed=4),
+}
+
+
+def make(name, nt=None, ny=None):
+    """Generate a named workload (optionally only the first nt steps / ny rows)."""
+    c = CONFIGS[name]
+    if name == "c0":
+        nx, nyy, ntt = c["dims"]
+        return moving_gaussians_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"])
+    if name in ("c1", "c1deg"):
+        c = CONFIGS["c1"]
+        nx, nyy, ntt = c["dims"]
+        f = moving_gaussians_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"], noise_std=c["noise_std"])
+        return quantise_levels(f) if name == "c1deg" else f
+    if name == "c2":
+        nx, nyy, nz, ntt = c["dims"]
+        return moving_gaussians_3d(nx, ny or nyy, nz, nt or ntt, c["K"], seed=c["seed"])
+    if name == "c4":
+        nx, nyy, ntt = c["dims"]
+        return vortex_sources_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"])
+    raise KeyError(name)
