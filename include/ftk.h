@@ -1,0 +1,180 @@
+/*
+ * ftk.h -- C ABI of libftk_mi355x.so: robust critical-point tracking on the simplicial spacetime mesh of a
+ * regular grid, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Guo et al., "FTK: A Simplicial Spacetime Meshing Framework for Robust and Scalable Feature Tracking"
+ * (IEEE TVCG).  The spacetime grid (space x time) is split into Kuhn/Freudenthal simplices (Sec. 3.3); every
+ * n-simplex is tested for a zero of the piecewise-linear vector field (Sec. 4.1, Eq. 2) with exact integer
+ * determinants under Simulation of Simplicity (Sec. 4.3, Sec. 2.4); punctured simplices receive a barycentric
+ * sublocation (Eq. 2) and a critical-point type from the spatial Jacobian (Sec. 4.1); the punctured sides of every
+ * (n+1)-simplex are united into trajectories (Alg. 1, left column).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named `field`/`step` and every array inside ftk_cp_result are HIP DEVICE pointers unless stated.
+ *   - Layouts are C order with x fastest:  scalar 2D  f[nt][ny][nx];  vector 2D  u[nt][2][ny][nx] (planar u, v
+ *     per step);  scalar 3D  f[nt][nz][ny][nx].  float32, contiguous.
+ *   - Spacetime vertex p = (x, y, [z], t) has global index g = ((t*nz + z)*ny + y)*nx + x (nz = 1 in 2D).  This
+ *     order is the vertex order of the symbolic perturbation, so it fixes which simplex receives a degenerate zero
+ *     (Sec. 4.3, Sec. 10.1).
+ *   - A punctured n-simplex is identified by face_id = g(anchor) * T + type, T = 12 (2D) or 60 (3D), where the
+ *     anchor is its lowest vertex and `type` indexes the ordered tuples (M_1..M_n) of nonempty disjoint axis masks
+ *     (bit 0 = x, then y, [z], t) in lexicographic order; its vertices are anchor, anchor+e(M_1),
+ *     anchor+e(M_1|M_2), ...  (the paper's (corner, unique type) indexing, Sec. 3.3).
+ *   - Every call is ordered on `stream`.  Calls that return results synchronise `stream` once to learn the hit
+ *     count (and once more at the end for the trajectory count).  Handles are not thread-safe; distinct handles
+ *     and distinct calls on distinct streams are independent.
+ *   - Errors: an ftk_status is returned, nothing is thrown across the ABI.  On error the result is left zeroed
+ *     (except n_hits for FTK_ERR_CAPACITY); ftk_last_error() gives a thread-local message.
+ */
+#ifndef FTK_MI355X_H
+#define FTK_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* ftk_stream_t; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  FTK_OK = 0,
+  FTK_ERR_ARG = 1,        /* bad dimensions, null pointer, unsupported kind/option */
+  FTK_ERR_NONFINITE = 2,  /* NaN or Inf in the input */
+  FTK_ERR_RANGE = 3,      /* a quantised vector component beyond the exact-arithmetic bound */
+  FTK_ERR_CAPACITY = 4,   /* more punctured simplices than the index type holds (2^32 - 2) */
+  FTK_ERR_OOM = 5,        /* an allocation failed (device memory or the caller's allocator) */
+  FTK_ERR_HIP = 6,        /* a HIP runtime call failed */
+  FTK_ERR_INVARIANT = 7,  /* a cell with 1 or >= 3 punctured sides: impossible under SoS; internal error */
+  FTK_ERR_STATE = 8       /* streaming call out of order */
+} ftk_status;
+
+typedef enum { FTK_SCALAR = 0, FTK_VECTOR = 1 } ftk_field_kind; /* scalar: the gradient is tracked */
+
+typedef enum {
+  FTK_CP_DEGENERATE = 0, FTK_CP_MIN = 1, FTK_CP_MAX = 2, FTK_CP_SADDLE = 3, FTK_CP_SADDLE1 = 4,
+  FTK_CP_SADDLE2 = 5, FTK_CP_SOURCE = 6, FTK_CP_SINK = 7, FTK_CP_REPELLING_FOCUS = 8,
+  FTK_CP_ATTRACTING_FOCUS = 9, FTK_CP_CENTER = 10
+} ftk_cp_type;
+
+/* Per-hit flag bits. */
+#define FTK_FLAG_DEGENERATE_SUBLOC 1u /* all exact cofactors zero: punctured only by the perturbation; centroid used */
+#define FTK_FLAG_FP64_FALLBACK 2u     /* the FP32 type decision was not certified and was redone in FP64 */
+#define FTK_FLAG_WIDE 4u              /* a vertex vector beyond the narrow range (2D 2^31, 3D 2^20): 128-bit path */
+
+/* Output selection bits (ftk_options.outputs). face_id is always produced. */
+#define FTK_OUT_POS 1u
+#define FTK_OUT_MU 2u
+#define FTK_OUT_TYPE 4u
+#define FTK_OUT_LABEL 8u
+#define FTK_OUT_FLAGS 16u
+#define FTK_OUT_ALL 31u
+
+/* Device allocator hooks (e.g. a framework's caching allocator).  Both must be stream-ordered on `stream`. */
+typedef void* (*ftk_alloc_fn)(size_t bytes, ftk_stream_t stream, void* ctx);
+typedef void (*ftk_free_fn)(void* ptr, ftk_stream_t stream, void* ctx);
+
+typedef struct {
+  int32_t quant_log2;  /* fixed-point scale 2^quant_log2 for the vectors; default 20; range [0, 40] */
+  int32_t precision;   /* 0: FP32 sublocation/classification with certified FP64 fallback; 1: FP64 throughout */
+  uint32_t outputs;    /* FTK_OUT_* bits; 0 means FTK_OUT_ALL */
+  int32_t tile_y;      /* rows per detection tile (0 = tuned default) */
+  int32_t slab_depth;  /* time steps per detection workgroup (0 = tuned default) */
+  ftk_alloc_fn alloc;  /* NULL: hipMallocAsync on the stream */
+  ftk_free_fn free;    /* NULL: hipFreeAsync on the stream */
+  void* alloc_ctx;
+} ftk_options;
+
+typedef struct {
+  int64_t simplices_tested; /* n-simplices tested (the throughput numerator) */
+  int64_t cells_linked;     /* (n+1)-simplices holding two punctured sides */
+  int64_t fp64_fallbacks;   /* hits whose type needed the FP64 re-evaluation */
+  int64_t degenerate_sublocations;
+  int32_t wide_path;        /* 1 if the 128-bit determinant path ran */
+  int32_t reserved;
+} ftk_stats;
+
+typedef struct {
+  int32_t n;                /* spatial dimension (2 or 3) */
+  int32_t reserved;
+  int64_t n_hits;           /* punctured n-simplices */
+  int64_t n_trajectories;   /* connected components */
+  int64_t* face_id;         /* [n_hits], strictly ascending */
+  float* pos;               /* [n_hits][n+1] spacetime position (x, y, [z], t) in grid/step units, or NULL */
+  float* mu;                /* [n_hits][n+1] barycentric coordinates of the zero (Eq. 2), or NULL */
+  uint8_t* type;            /* [n_hits] ftk_cp_type, or NULL */
+  uint8_t* flags;           /* [n_hits] FTK_FLAG_* bits, or NULL */
+  int64_t* label;           /* [n_hits] smallest face_id of the trajectory holding the hit, or NULL */
+  ftk_stats stats;
+} ftk_cp_result;
+
+typedef struct ftk_tracker ftk_tracker;
+
+/* Default options (quant_log2 = 20, precision 0, all outputs, tuned tiles, HIP stream-ordered allocator). */
+void ftk_default_options(ftk_options* opt);
+
+/*
+ * Track critical points of a 2D time-varying field (Sec. 4.1-4.3, Eq. 2, Alg. 1 left column).
+ *   field : device pointer, scalar f[nt][ny][nx] or vector u[nt][2][ny][nx] (kind), float32.
+ *   nx, ny, nt >= 2.  opt may be NULL (defaults).  out receives device arrays allocated through opt->alloc (or
+ *   hipMallocAsync); release them with ftk_result_free using the same options.
+ * Scalar input: the gradient (central differences inside, one-sided at the first/last index, float32) is
+ * quantised to integers q = rint(g * 2^quant_log2); vector input is quantised directly.  Errors:
+ * FTK_ERR_NONFINITE, FTK_ERR_RANGE (|q| >= 2^62), FTK_ERR_ARG, FTK_ERR_OOM, FTK_ERR_HIP, FTK_ERR_CAPACITY.
+ */
+ftk_status ftk_track_cp2d(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,
+                          const ftk_options* opt, ftk_stream_t stream, ftk_cp_result* out);
+
+/*
+ * Track critical points of a 3D time-varying scalar field f[nt][nz][ny][nx] through its gradient (Sec. 4.1-4.3,
+ * Alg. 1 left column with tetrahedral sides of pentachora).  kind must be FTK_SCALAR.  FTK_ERR_RANGE when a
+ * quantised component reaches 2^41.  Otherwise as ftk_track_cp2d.
+ */
+ftk_status ftk_track_cp3d(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nz,
+                          int64_t nt, const ftk_options* opt, ftk_stream_t stream, ftk_cp_result* out);
+
+/*
+ * Streaming form, after the paper's push_field_data() and its two-step sliding window of ordinal and interval
+ * elements (Sec. 3.1 "Ordinal and interval mesh elements", Sec. 8 "C++ programming interface").
+ *   ftk_cp_create: n = 2 or 3, dims = (nx, ny[, nz]); the tracker keeps the last pushed step on the device.
+ *   ftk_cp_push:   step = device pointer to one time step in the layout above (for vector input [2][ny][nx]); the
+ *                  caller may overwrite it once `stream` has passed the call.  Ordinal simplices of the step and
+ *                  interval simplices between the previous and this step are tested.
+ *   ftk_cp_finish: stitches, labels and returns the whole trajectory set, identical to the one-shot call on the
+ *                  concatenated steps.  The tracker may not be pushed to afterwards (FTK_ERR_STATE).
+ */
+ftk_status ftk_cp_create(int32_t n, const int64_t* dims, ftk_field_kind kind, const ftk_options* opt,
+                         ftk_stream_t stream, ftk_tracker** h);
+ftk_status ftk_cp_push(ftk_tracker* h, const float* step);
+ftk_status ftk_cp_finish(ftk_tracker* h, ftk_cp_result* out);
+void ftk_cp_destroy(ftk_tracker* h);
+
+/*
+ * Batched form: many independent 2D series of uneven sizes in one call.  fields[i] is a device pointer to
+ * series i (layout as ftk_track_cp2d, shared kind); nx/ny/nt are HOST arrays of n_series entries; outs is a HOST
+ * array of n_series results, each as from ftk_track_cp2d.  Detection of all series runs as one persistent launch
+ * over a device work queue of (series, row block, time slab) items.
+ */
+ftk_status ftk_track_cp2d_batched(int32_t n_series, const float* const* fields, const int64_t* nx,
+                                  const int64_t* ny, const int64_t* nt, ftk_field_kind kind,
+                                  const ftk_options* opt, ftk_stream_t stream, ftk_cp_result* outs);
+
+/* Release the device arrays of a result (with the allocator given in opt, which may be NULL). */
+void ftk_result_free(ftk_cp_result* r, const ftk_options* opt, ftk_stream_t stream);
+
+/* Number of n-simplices tested for a grid: sum over simplex types of prod_a (N_a - [axis a used]).
+ * dims_with_t = (nx, ny, [nz,] nt).  Returns -1 for bad arguments. */
+int64_t ftk_simplex_count(int32_t n, const int64_t* dims_with_t);
+
+/* Thread-local text of the last error of this thread ("" if none). */
+const char* ftk_last_error(void);
+
+/* Library version string. */
+const char* ftk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTK_MI355X_H */

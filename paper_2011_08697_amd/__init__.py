@@ -1,0 +1,255 @@
+"""Python binding of libftk_mi355x.so (critical-point tracking on the simplicial spacetime mesh, gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP library.  Device memory for outputs and
+scratch comes from PyTorch's caching allocator through the library's allocator hooks, on PyTorch's current
+stream.  If the library is missing the calls raise; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libftk_mi355x.so")
+
+TYPES = ["DEGENERATE", "MIN", "MAX", "SADDLE", "SADDLE1", "SADDLE2", "SOURCE", "SINK",
+         "REPELLING_FOCUS", "ATTRACTING_FOCUS", "CENTER"]
+STATUS = ["OK", "ERR_ARG", "ERR_NONFINITE", "ERR_RANGE", "ERR_CAPACITY", "ERR_OOM", "ERR_HIP",
+          "ERR_INVARIANT", "ERR_STATE"]
+FLAG_DEGENERATE_SUBLOC, FLAG_FP64_FALLBACK, FLAG_WIDE = 1, 2, 4
+OUT_POS, OUT_MU, OUT_TYPE, OUT_LABEL, OUT_FLAGS, OUT_ALL = 1, 2, 4, 8, 16, 31
+SCALAR, VECTOR = 0, 1
+
+EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_create", "ftk_cp_push",
+           "ftk_cp_finish", "ftk_cp_destroy", "ftk_track_cp2d_batched", "ftk_result_free", "ftk_simplex_count",
+           "ftk_last_error", "ftk_version"]
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class FtkError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = status
+        name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"{name}: {msg}")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("quant_log2", ctypes.c_int32), ("precision", ctypes.c_int32), ("outputs", ctypes.c_uint32),
+                ("tile_y", ctypes.c_int32), ("slab_depth", ctypes.c_int32),
+                ("alloc", _ALLOC_FN), ("free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("simplices_tested", ctypes.c_int64), ("cells_linked", ctypes.c_int64),
+                ("fp64_fallbacks", ctypes.c_int64), ("degenerate_sublocations", ctypes.c_int64),
+                ("wide_path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_hits", ctypes.c_int64),
+                ("n_trajectories", ctypes.c_int64), ("face_id", ctypes.c_void_p), ("pos", ctypes.c_void_p),
+                ("mu", ctypes.c_void_p), ("type", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("label", ctypes.c_void_p), ("stats", Stats)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2011_08697_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp = ctypes.c_int64, ctypes.c_void_p
+        L.ftk_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.ftk_track_cp2d.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.POINTER(Options), vp,
+                                     ctypes.POINTER(Result)]
+        L.ftk_track_cp2d.restype = ctypes.c_int
+        L.ftk_track_cp3d.argtypes = [vp, ctypes.c_int, i64, i64, i64, i64, ctypes.POINTER(Options), vp,
+                                     ctypes.POINTER(Result)]
+        L.ftk_track_cp3d.restype = ctypes.c_int
+        L.ftk_cp_create.argtypes = [ctypes.c_int32, ctypes.POINTER(i64), ctypes.c_int, ctypes.POINTER(Options), vp,
+                                    ctypes.POINTER(vp)]
+        L.ftk_cp_create.restype = ctypes.c_int
+        L.ftk_cp_push.argtypes = [vp, vp]
+        L.ftk_cp_push.restype = ctypes.c_int
+        L.ftk_cp_finish.argtypes = [vp, ctypes.POINTER(Result)]
+        L.ftk_cp_finish.restype = ctypes.c_int
+        L.ftk_cp_destroy.argtypes = [vp]
+        L.ftk_cp_destroy.restype = None
+        L.ftk_track_cp2d_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                             ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int,
+                                             ctypes.POINTER(Options), vp, ctypes.POINTER(Result)]
+        L.ftk_track_cp2d_batched.restype = ctypes.c_int
+        L.ftk_result_free.argtypes = [ctypes.POINTER(Result), ctypes.POINTER(Options), vp]
+        L.ftk_result_free.restype = None
+        L.ftk_simplex_count.argtypes = [ctypes.c_int32, ctypes.POINTER(i64)]
+        L.ftk_simplex_count.restype = i64
+        L.ftk_last_error.restype = ctypes.c_char_p
+        L.ftk_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().ftk_last_error().decode()
+
+
+def simplex_count(n, dims_with_t):
+    arr = (ctypes.c_int64 * len(dims_with_t))(*dims_with_t)
+    return lib().ftk_simplex_count(n, arr)
+
+
+class _TorchPool:
+    """Allocator hooks backed by torch's caching allocator; keeps the tensors alive by pointer."""
+
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.live = {}
+        self._alloc = _ALLOC_FN(self.alloc)
+        self._free = _FREE_FN(self.free)
+
+    def alloc(self, nbytes, stream, ctx):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
+        except Exception:
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def free(self, ptr, stream, ctx):
+        self.live.pop(ptr, None)
+
+    def take(self, ptr, dtype, shape):
+        if not ptr:
+            return None
+        t = self.live.pop(ptr)
+        n = 1
+        for s in shape:
+            n *= s
+        return t.view(dtype)[:n].view(*shape) if n else t.view(dtype)[:0].view(*shape)
+
+
+def _options(pool, quant_log2=20, precision=0, outputs=OUT_ALL, tile_y=0, slab_depth=0):
+    o = Options()
+    lib().ftk_default_options(ctypes.byref(o))
+    o.quant_log2, o.precision, o.outputs = quant_log2, precision, outputs
+    o.tile_y, o.slab_depth = tile_y, slab_depth
+    if pool is not None:
+        o.alloc, o.free = pool._alloc, pool._free
+    return o
+
+
+def _stream_handle(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _wrap(pool, r):
+    import torch
+    n, nh = r.n, int(r.n_hits)
+    out = dict(n=n, n_hits=nh, n_trajectories=int(r.n_trajectories),
+               face_id=pool.take(r.face_id, torch.int64, (nh,)),
+               pos=pool.take(r.pos, torch.float32, (nh, n + 1)),
+               mu=pool.take(r.mu, torch.float32, (nh, n + 1)),
+               type=pool.take(r.type, torch.uint8, (nh,)),
+               flags=pool.take(r.flags, torch.uint8, (nh,)),
+               label=pool.take(r.label, torch.int64, (nh,)),
+               stats={f: getattr(r.stats, f) for f, _ in Stats._fields_ if f != "reserved"})
+    return out
+
+
+def _check(st):
+    if st != 0:
+        raise FtkError(st, last_error())
+
+
+def track_cp2d(field, kind=SCALAR, **opts):
+    """field: contiguous float32 CUDA tensor [nt][ny][nx] (scalar) or [nt][2][ny][nx] (vector)."""
+    if not field.is_contiguous() or field.dtype.itemsize != 4 or not field.is_cuda:
+        raise ValueError("field must be a contiguous float32 device tensor")
+    if kind == SCALAR:
+        nt, ny, nx = field.shape
+    else:
+        nt, c, ny, nx = field.shape
+        if c != 2:
+            raise ValueError("vector field must be [nt][2][ny][nx]")
+    pool = _TorchPool(field.device)
+    o = _options(pool, **opts)
+    r = Result()
+    st = lib().ftk_track_cp2d(ctypes.c_void_p(field.data_ptr()), kind, nx, ny, nt, ctypes.byref(o),
+                              _stream_handle(field.device), ctypes.byref(r))
+    _check(st)
+    return _wrap(pool, r)
+
+
+def track_cp3d(field, **opts):
+    """field: contiguous float32 CUDA tensor [nt][nz][ny][nx] (scalar; the gradient is tracked)."""
+    if not field.is_contiguous() or field.dtype.itemsize != 4 or not field.is_cuda:
+        raise ValueError("field must be a contiguous float32 device tensor")
+    nt, nz, ny, nx = field.shape
+    pool = _TorchPool(field.device)
+    o = _options(pool, **opts)
+    r = Result()
+    st = lib().ftk_track_cp3d(ctypes.c_void_p(field.data_ptr()), SCALAR, nx, ny, nz, nt, ctypes.byref(o),
+                              _stream_handle(field.device), ctypes.byref(r))
+    _check(st)
+    return _wrap(pool, r)
+
+
+class Tracker:
+    """Streaming form: push one time step at a time, then finish()."""
+
+    def __init__(self, n, dims, kind=SCALAR, device=None, **opts):
+        import torch
+        self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.pool = _TorchPool(self.device)
+        self.opts = _options(self.pool, **opts)
+        self.h = ctypes.c_void_p()
+        arr = (ctypes.c_int64 * len(dims))(*dims)
+        self.stream = _stream_handle(self.device)
+        _check(lib().ftk_cp_create(n, arr, kind, ctypes.byref(self.opts), self.stream, ctypes.byref(self.h)))
+
+    def push(self, step):
+        if not step.is_contiguous() or not step.is_cuda:
+            raise ValueError("step must be a contiguous device tensor")
+        _check(lib().ftk_cp_push(self.h, ctypes.c_void_p(step.data_ptr())))
+
+    def finish(self):
+        r = Result()
+        _check(lib().ftk_cp_finish(self.h, ctypes.byref(r)))
+        return _wrap(self.pool, r)
+
+    def close(self):
+        if self.h:
+            lib().ftk_cp_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def track_cp2d_batched(fields, kind=SCALAR, **opts):
+    """fields: list of contiguous float32 device tensors (each as for track_cp2d)."""
+    k = len(fields)
+    if k == 0:
+        return []
+    pool = _TorchPool(fields[0].device)
+    o = _options(pool, **opts)
+    ptrs = (ctypes.c_void_p * k)(*[f.data_ptr() for f in fields])
+    nx = (ctypes.c_int64 * k)(*[f.shape[-1] for f in fields])
+    ny = (ctypes.c_int64 * k)(*[f.shape[-2] for f in fields])
+    nt = (ctypes.c_int64 * k)(*[f.shape[0] for f in fields])
+    res = (Result * k)()
+    st = lib().ftk_track_cp2d_batched(k, ptrs, nx, ny, nt, kind, ctypes.byref(o), _stream_handle(fields[0].device),
+                                      res)
+    _check(st)
+    return [_wrap(pool, res[i]) for i in range(k)]

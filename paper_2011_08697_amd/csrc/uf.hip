@@ -1,0 +1,56 @@
+// uf.hip -- GPU union-find for trajectory stitching (Alg. 1 pass 2: unite the punctured sides of every cell).
+//
+// The emission kernels initialise parent[i] to the smallest of i and its (at most two) partner hits, which already
+// encodes every link except, for hits whose two partners are both smaller, the link to the larger partner; those
+// links are queued and united here with compare-and-swap hooking (larger root under smaller root).  Labels are the
+// face id of each set's root, i.e. the smallest face id of the trajectory.
+#include "common.h"
+#include "internal.h"
+
+namespace ftk {
+
+namespace {
+
+__global__ __launch_bounds__(256) void uf_hook(unsigned* __restrict__ parent, const uint2* __restrict__ work,
+                                               const unsigned long long* __restrict__ work_count) {
+  const unsigned long long n = *work_count;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    uint2 e = work[i];
+    uf_unite(parent, e.x, e.y);
+  }
+}
+
+__global__ __launch_bounds__(256) void uf_label(unsigned* __restrict__ parent, const long long* __restrict__ face_id,
+                                                long long* __restrict__ label, long long n,
+                                                unsigned long long* __restrict__ cnt) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned roots = 0;
+  if (i < n) {
+    unsigned r = uf_find(parent, (unsigned)i);
+    if (label) label[i] = face_id[r];
+    roots = (r == (unsigned)i);
+  }
+  unsigned long long s = wave_sum64(roots);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(&cnt[CNT_TRAJ], s);
+}
+
+}  // namespace
+
+hipError_t launch_uf_hook(unsigned* parent, const uint2* work, const unsigned long long* work_count,
+                          long long max_work, hipStream_t s) {
+  long long blocks = (max_work + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  uf_hook<<<(unsigned)blocks, 256, 0, s>>>(parent, work, work_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_uf_label(unsigned* parent, const long long* face_id, long long* label, long long n,
+                           unsigned long long* cnt, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  uf_label<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(parent, face_id, label, n, cnt);
+  return hipGetLastError();
+}
+
+}  // namespace ftk
