@@ -1,0 +1,200 @@
+"""Benchmark: spacetime simplices tested per second for critical-point tracking on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1] [--no-cpu-baseline]
+
+One step = one ftk_track_cp2d/3d call over the whole series (detection of every n-simplex, compaction,
+sublocation, classification, union-find stitching, labels) with the input already resident in HBM.  Prints one
+JSON line.  The roofline entry describes the kernel with the largest share of the step, timed with HIP events that
+the library records on the call's stream (ftk_options.profile).
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+WORKLOADS = {
+    "c0": "2D scalar 64x64x10, 8 moving Gaussians, seed 0",
+    "c1": "2D scalar 1024x1024x100, 256 moving Gaussians + N(0,1e-3) noise, seed 1",
+    "c1deg": "2D scalar 1024x1024x100, c1 field rounded to 16 levels",
+    "c2": "3D scalar 256x256x256x16, 512 moving Gaussians, seed 2",
+    "c4": "2D vector 4096x4096x50, 1024 moving sources/sinks/vortices, seed 4",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=0, help="time steps of the oracle sample (0: automatic)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n * 4, "launches": 3}), flush=True)
+
+
+def source_hash(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2011_08697_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "detect2d": ["cp2d.hip", "common.h", "kuhn.h"], "emit2d": ["cp2d.hip", "common.h", "kuhn.h"],
+    "uf_label": ["uf.hip", "common.h"], "scan": ["scan.hip"],
+    "detect3d": ["cp3d.hip", "common.h", "kuhn.h"], "emit3d": ["cp3d.hip", "common.h", "kuhn.h"],
+}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches the current source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        if d.get("source_hash") != source_hash(KERNEL_SOURCES[kernel]):
+            return None
+        return float(d["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (time-slab sharding is described "
+              "in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_2011_08697_amd as F
+    from paper_2011_08697_amd import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = args.workload
+    n = 3 if wl == "c2" else 2
+    kind = 1 if wl == "c4" else 0
+    t0 = time.time()
+    field_np = synth.make(wl)
+    gen_s = time.time() - t0
+    field = torch.from_numpy(field_np).to(dev)
+    if n == 2:
+        dims = (field_np.shape[-1], field_np.shape[-2], field_np.shape[0])
+    else:
+        dims = (field_np.shape[3], field_np.shape[2], field_np.shape[1], field_np.shape[0])
+    L = F.lib()
+    stream = torch.cuda.current_stream(dev)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    opt = F.Options()
+    L.ftk_default_options(ctypes.byref(opt))
+    opt.profile = 1
+
+    def one_step():
+        r = F.Result()
+        if n == 2:
+            st = L.ftk_track_cp2d(ctypes.c_void_p(field.data_ptr()), kind, dims[0], dims[1], dims[2],
+                                  ctypes.byref(opt), sh, ctypes.byref(r))
+        else:
+            st = L.ftk_track_cp3d(ctypes.c_void_p(field.data_ptr()), 0, dims[0], dims[1], dims[2], dims[3],
+                                  ctypes.byref(opt), sh, ctypes.byref(r))
+        if st != 0:
+            raise F.FtkError(st, F.last_error())
+        out = (int(r.n_hits), int(r.n_trajectories), int(r.stats.simplices_tested),
+               r.stats.t_detect_ms, r.stats.t_scan_ms, r.stats.t_emit_ms, r.stats.t_link_ms)
+        L.ftk_result_free(ctypes.byref(r), ctypes.byref(opt), sh)
+        return out
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    phase = np.zeros(4)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        nh, ntraj, tested, td, ts, te, tl = one_step()
+        phase += (td, ts, te, tl)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = tested * args.steps / elapsed
+    phase /= args.steps
+
+    # dominant kernel and its algorithmic bytes per launch
+    V = int(np.prod(dims))
+    in_bytes = V * 4 * (n if kind == 1 else 1)
+    rec = 22 if n == 2 else 26  # face_id 8 + pos 4*(n+1) + type 1 + flags 1
+    names = ["detect%dd" % n, "scan", "emit%dd" % n, "uf_label"]
+    alg = [in_bytes, 0, rec * nh, 8 * nh]
+    k = int(np.argmax(phase))
+    kernel = names[k]
+    achieved = alg[k] / (phase[k] * 1e-3) / 1e9 if phase[k] > 0 else 0.0
+    traffic = measured_traffic(kernel, wl)
+    roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "avg_ms": round(float(phase[k]), 4),
+                "phase_ms": {nm: round(float(p), 4) for nm, p in zip(names, phase)},
+                "path_frac": round((in_bytes + (rec + 8) * nh) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline and n == 2:
+        from oracle import oracle as O
+        cores = min(16, len(os.sched_getaffinity(0)))
+        steps = args.cpu_steps or (10 if wl in ("c1", "c1deg") else 3)
+        if wl == "c0":
+            sample = field_np
+        else:
+            sample = np.ascontiguousarray(field_np[:steps])
+        t0 = time.perf_counter()
+        tr = O.track(sample, n=2, kind=kind, nthreads=cores)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(tr.simplices_tested / cpu_s, 1), "unit": "simplices/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"first {sample.shape[0]} of {field_np.shape[0]} time steps of the same field "
+                         f"({tr.simplices_tested} simplices, {tr.n_hits} hits, full detect + sublocate + stitch, "
+                         f"{cpu_s:.1f} s)"}
+
+    line = {
+        "metric": "spacetime simplices tested/s + HBM roofline frac; batched vs plain steps/s",
+        "value": round(value, 1), "unit": "simplices/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[wl], "dims": list(dims), "kind": "vector" if kind else "scalar",
+                   "n_hits": nh, "n_trajectories": ntraj, "simplices_per_step": tested,
+                   "generation_s": round(gen_s, 1)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

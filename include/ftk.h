@@ -84,6 +84,8 @@ typedef struct {
   ftk_alloc_fn alloc;  /* NULL: hipMallocAsync on the stream */
   ftk_free_fn free;    /* NULL: hipFreeAsync on the stream */
   void* alloc_ctx;
+  int32_t profile;     /* 1: record HIP events around each kernel group on `stream`; times land in stats */
+  int32_t reserved;
 } ftk_options;
 
 typedef struct {
@@ -93,6 +95,10 @@ typedef struct {
   int64_t degenerate_sublocations;
   int32_t wide_path;        /* 1 if the 128-bit determinant path ran */
   int32_t reserved;
+  float t_detect_ms;        /* with ftk_options.profile: detection kernel (pass 1) */
+  float t_scan_ms;          /* prefix sum of the per-segment hit counts */
+  float t_emit_ms;          /* emission: sublocation, classification, union-find links */
+  float t_link_ms;          /* union-find hooking and labelling (pass 2) */
 } ftk_stats;
 
 typedef struct {

@@ -36,13 +36,16 @@ class FtkError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("quant_log2", ctypes.c_int32), ("precision", ctypes.c_int32), ("outputs", ctypes.c_uint32),
                 ("tile_y", ctypes.c_int32), ("slab_depth", ctypes.c_int32),
-                ("alloc", _ALLOC_FN), ("free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
+                ("alloc", _ALLOC_FN), ("free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("simplices_tested", ctypes.c_int64), ("cells_linked", ctypes.c_int64),
                 ("fp64_fallbacks", ctypes.c_int64), ("degenerate_sublocations", ctypes.c_int64),
-                ("wide_path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("wide_path", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_detect_ms", ctypes.c_float), ("t_scan_ms", ctypes.c_float), ("t_emit_ms", ctypes.c_float),
+                ("t_link_ms", ctypes.c_float)]
 
 
 class Result(ctypes.Structure):
@@ -135,11 +138,11 @@ class _TorchPool:
         return t.view(dtype)[:n].view(*shape) if n else t.view(dtype)[:0].view(*shape)
 
 
-def _options(pool, quant_log2=20, precision=0, outputs=OUT_ALL, tile_y=0, slab_depth=0):
+def _options(pool, quant_log2=20, precision=0, outputs=OUT_ALL, tile_y=0, slab_depth=0, profile=0):
     o = Options()
     lib().ftk_default_options(ctypes.byref(o))
     o.quant_log2, o.precision, o.outputs = quant_log2, precision, outputs
-    o.tile_y, o.slab_depth = tile_y, slab_depth
+    o.tile_y, o.slab_depth, o.profile = tile_y, slab_depth, profile
     if pool is not None:
         o.alloc, o.free = pool._alloc, pool._free
     return o

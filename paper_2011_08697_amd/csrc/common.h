@@ -124,7 +124,7 @@ __device__ __forceinline__ int classify2_rule_vec(double det, double tr, double 
 
 // Binary64 evaluation in the reference order: J_c entries as ((mu0 J0 + mu1 J1) + mu2 J2), det = J00 J11 - J01 J10,
 // tr = J00 + J11, disc = tr tr - 4 det.
-__device__ __noinline__ int classify2_fp64(const double mu[3], const float J[3][4], bool vector) {
+__device__ __forceinline__ int classify2_fp64(const double mu[3], const float J[3][4], bool vector) {
   double Jc[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {

@@ -232,42 +232,14 @@ __global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __res
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Pass 1b: emission + pass 2 links.  One wavefront per row segment (t, y, x-block); block = 256 (4 segments).
+// Pass 1b: emission + pass 2 links.
+// Same tiling as detection (64 x TY anchors, marching over a slab of TT steps).  The vector field of planes t and
+// t+1 (gradient of the scalar, or the input vector) is kept in LDS with a 1-cell halo; quantised vectors and
+// Jacobians of a hit's vertices are formed from it on the fly, with the same binary32 stencils as pass 1.  Each
+// wavefront takes one row segment at a time and processes its hits hit-parallel (hit j of the segment on lane
+// j mod 64), so output writes are contiguous.
 // ---------------------------------------------------------------------------------------------------------------
 namespace {
-
-// Field samples for the stencils.
-struct Field2 {
-  const float* f;
-  int kind, nx, ny;
-  long long plane;
-  __device__ __forceinline__ float s(int x, int y, int t) const { return f[(long long)t * plane + (long long)y * nx + x]; }
-  __device__ __forceinline__ float u(int c, int x, int y, int t) const {
-    return f[((long long)t * 2 + c) * plane + (long long)y * nx + x];
-  }
-  // vector component c at (x, y, t): the gradient (scalar input) or the input vector
-  __device__ __forceinline__ float vec(int c, int x, int y, int t) const {
-    if (kind != 0) return u(c, x, y, t);
-    if (c == 0) {
-      float lo = x > 0 ? s(x - 1, y, t) : 0.0f, hi = x < nx - 1 ? s(x + 1, y, t) : 0.0f;
-      return diff3(lo, s(x, y, t), hi, x, nx);
-    }
-    float lo = y > 0 ? s(x, y - 1, t) : 0.0f, hi = y < ny - 1 ? s(x, y + 1, t) : 0.0f;
-    return diff3(lo, s(x, y, t), hi, y, ny);
-  }
-  // Jacobian J[a][b] = d v_a / d x_b (the same stencil applied to the binary32 components); J as [J00 J01 J10 J11]
-  __device__ __forceinline__ void jac(int x, int y, int t, float J[4]) const {
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      float c = vec(a, x, y, t);
-      float lo = x > 0 ? vec(a, x - 1, y, t) : 0.0f, hi = x < nx - 1 ? vec(a, x + 1, y, t) : 0.0f;
-      J[a * 2 + 0] = diff3(lo, c, hi, x, nx);
-      lo = y > 0 ? vec(a, x, y - 1, t) : 0.0f;
-      hi = y < ny - 1 ? vec(a, x, y + 1, t) : 0.0f;
-      J[a * 2 + 1] = diff3(lo, c, hi, y, ny);
-    }
-  }
-};
 
 // Exact 2x2 determinant of integer columns (a, b); 128-bit for the wide path.
 template <bool WIDE>
@@ -276,258 +248,546 @@ __device__ __forceinline__ i128 det2x(long long a0, long long a1, long long b0, 
   return (i128)a0 * b1 - (i128)a1 * b0;
 }
 
-struct Nb {
-  unsigned m;    // puncture mask of the vertex
-  unsigned off;  // hit index of its first hit
-};
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// neighbour slots of an anchor: self, -x, +x, -y, +y, -t, +t
+enum { NB_SELF = 0, NB_MX, NB_PX, NB_MY, NB_PY, NB_MT, NB_PT };
 
 }  // namespace
 
-template <bool WIDE>
-__global__ __launch_bounds__(256) void emit2d(Grid2 g, const uint16_t* __restrict__ masks,
-                                              const long long* __restrict__ seg_off, long long nseg, Out2 o,
-                                              unsigned* __restrict__ status, unsigned long long* __restrict__ cnt) {
-  const int lane = threadIdx.x & 63;
-  const long long seg = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (seg >= nseg) return;
-  const int nxt = g.nxt, nx = g.nx, ny = g.ny, nt = g.nt;
-  const long long row = seg / nxt;
-  const int xb = (int)(seg - row * nxt);
-  const int t = (int)(row / ny), y = (int)(row - (long long)t * ny);
-  const int x = xb * TX + lane;
-  const bool in = x < nx;
-  const long long plane = (long long)nx * ny;
-  const long long gidx = (long long)t * plane + (long long)y * nx + x;
-
-  const unsigned m = in ? masks[gidx] : 0u;
-  if (__ballot(m != 0) == 0) return;
-
-  // own offsets
-  const unsigned cnt_self = __popc(m);
-  const unsigned incl = wave_incl_scan(cnt_self);
-  const unsigned base_seg = (unsigned)seg_off[seg];
-  Nb self{m, base_seg + incl - cnt_self};
-  const unsigned seg_total = __shfl(incl, 63, 64);
-
-  // neighbours along x: lanes of this segment, or the adjacent segments' edge vertices
-  Nb mx{0, 0}, px{0, 0};
-  {
-    unsigned lm = __shfl_up(m, 1, 64), lo = __shfl_up(self.off, 1, 64);
-    unsigned rm = __shfl_down(m, 1, 64), ro = __shfl_down(self.off, 1, 64);
-    if (lane > 0) {
-      mx = Nb{lm, lo};
-    } else if (x > 0) {
-      unsigned pm = masks[gidx - 1];
-      mx = Nb{pm, base_seg - __popc(pm)};
-    }
-    if (lane < 63 && x + 1 < nx) {
-      px = Nb{rm, ro};
-    } else if (lane == 63 && x + 1 < nx) {
-      px = Nb{masks[gidx + 1], base_seg + seg_total};
-    }
+// Local union-find in LDS over the hits of one tile and a run of consecutive steps (a chunk); the smallest local id
+// (= smallest hit index) is the root.
+__device__ __forceinline__ unsigned lfind(unsigned* lp, unsigned x) {
+  unsigned p = lp[x];
+  while (p != x) {
+    unsigned gp = lp[p];
+    if (gp != p) lp[x] = gp;
+    x = p;
+    p = gp;
   }
-  // neighbours along y and t: whole neighbouring segments, same lanes
-  auto seg_nb = [&](long long dseg, long long dg, bool ok) -> Nb {
-    unsigned mm = 0;
-    bool valid = ok && in;
-    if (valid) mm = masks[gidx + dg];
-    unsigned inc = wave_incl_scan(mm ? __popc(mm) : 0u);
-    unsigned b = ok ? (unsigned)seg_off[seg + dseg] : 0u;
-    return Nb{mm, b + inc - __popc(mm)};
-  };
-  const long long segs_per_row = nxt;
-  Nb my = seg_nb(-segs_per_row, -(long long)nx, y > 0);
-  Nb py = seg_nb(segs_per_row, (long long)nx, y + 1 < ny);
-  Nb mt = seg_nb(-segs_per_row * ny, -plane, t > 0);
-  Nb pt = seg_nb(segs_per_row * ny, plane, t + 1 < nt);
+  return x;
+}
 
-  // neighbour selector: u = p + delta for a single-axis delta (axis bit ab, sign)
-  auto nb_plus = [&](int ab) -> Nb { return ab == 1 ? px : (ab == 2 ? py : pt); };
-  auto nb_minus = [&](int ab) -> Nb { return ab == 1 ? mx : (ab == 2 ? my : mt); };
-  auto hit_index = [&](const Nb& u, int ty) -> unsigned { return u.off + __popc(u.m & ((1u << ty) - 1u)); };
-  auto is_hit = [&](const Nb& u, int ty) -> bool { return (u.m >> ty) & 1u; };
+__device__ __forceinline__ void lunite(unsigned* lp, unsigned a, unsigned b) {
+  unsigned ra = lfind(lp, a), rb = lfind(lp, b);
+  while (ra != rb) {
+    if (ra < rb) {
+      unsigned t = ra;
+      ra = rb;
+      rb = t;
+    }
+    unsigned old = atomicCAS(&lp[ra], ra, rb);
+    if (old == ra) return;
+    ra = lfind(lp, old);
+    rb = lfind(lp, rb);
+  }
+}
 
-  Field2 F{g.f, g.kind, nx, ny, plane};
+// Edge list staging: links that leave the tile/chunk are collected in LDS and appended to the global list in
+// batches (one global atomic per batch; same-address atomics serialise at one L2 channel).
+constexpr int kEdgeStage = 768;
+
+// Wave-aggregated append of (idx, partner) for the active lanes with want == true: into the LDS stage if it has
+// room, otherwise straight to the global list.
+__device__ __forceinline__ void append_edge(bool want, unsigned idx, unsigned partner, uint2* stage, int* stage_n,
+                                            uint2* work, unsigned long long* counter) {
+  const unsigned long long bal = __ballot(want);
+  if (bal == 0) return;
+  const int lane = lane_id();
+  const int leader = __ffsll((long long)bal) - 1;
+  const int k = __popcll(bal);
+  int pos = -1;
+  unsigned long long gpos = 0;
+  if (lane == leader) {
+    int old = *(volatile int*)stage_n;
+    while (old + k <= kEdgeStage) {
+      int prev = atomicCAS(stage_n, old, old + k);
+      if (prev == old) {
+        pos = old;
+        break;
+      }
+      old = prev;
+    }
+    if (pos < 0) gpos = atomicAdd(counter, (unsigned long long)k);
+  }
+  pos = __shfl(pos, leader, 64);
+  gpos = __shfl(gpos, leader, 64);
+  if (want) {
+    const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+    const uint2 e = make_uint2(idx, partner);
+    if (pos >= 0)
+      stage[pos + rank] = e;
+    else
+      work[gpos + rank] = e;
+  }
+}
+
+// Block-wide sum of a per-thread value (256 threads), returned on thread 0.
+__device__ __forceinline__ unsigned long long block_sum256(unsigned long long v, unsigned long long* red) {
+  v = wave_sum64(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  unsigned long long s = 0;
+  if (threadIdx.x == 0) s = red[0] + red[1] + red[2] + red[3];
+  return s;
+}
+
+template <int TY, bool WIDE>
+__global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* __restrict__ masks,
+                                              const long long* __restrict__ seg_off, Out2 o,
+                                              unsigned* __restrict__ status, unsigned long long* __restrict__ cnt) {
+  constexpr int GW = TX + 3, GH = TY + 3;  // vector field: x0-1 .. x0+TX+1, y0-1 .. y0+TY+1
+  constexpr int FW = TX + 5, FH = TY + 5;  // scalar field: x0-2 .. x0+TX+2
+  constexpr int CAP = 2048;                // local union-find capacity (hits)
+  constexpr int MAXTT = 32;
+  __shared__ float fs[FH * FW];
+  __shared__ float2 gs[2][GH * GW];
+  __shared__ unsigned short s_ex[TY][64];
+  __shared__ unsigned short s_m[TY][64];
+  __shared__ unsigned s_rowtot[TY], s_rowbase[TY];
+  __shared__ unsigned short nbm[4][7][64];
+  __shared__ unsigned nbo[4][7][64];
+  __shared__ unsigned lpar[CAP];
+  __shared__ unsigned lglob[CAP];
+  __shared__ unsigned lbase[MAXTT][TY];  // local id of the first hit of (chunk step, row)
+  __shared__ unsigned segb[MAXTT][TY];   // global hit index of the first hit of (chunk step, row)
+  __shared__ int s_chunk_t0, s_chunk_n, s_flush, s_global, s_plane_lbase, s_plane_total;
+  __shared__ uint2 s_stage[kEdgeStage];
+  __shared__ int s_stage_n;
+  __shared__ unsigned long long s_stage_base;
+  __shared__ unsigned long long s_red[4];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int t0 = blockIdx.z * TT;
+  const int t1 = min(t0 + TT, g.nt);
+  const int nx = g.nx, ny = g.ny, nt = g.nt, nxt = g.nxt;
+  const long long plane = (long long)nx * ny;
+  const bool vector = g.kind != 0;
   unsigned st = 0;
   unsigned long long n_fp64 = 0, n_deg = 0, n_linked = 0;
 
-  unsigned rem = m;
-  unsigned k = 0;
-  while (rem) {
-    const int ty = __ffs(rem) - 1;
-    rem &= rem - 1;
-    const unsigned idx = self.off + k;
-    ++k;
-    const int m1 = kTri2.m[ty][0], m2 = kTri2.m[ty][1];
-    // vertices in chain order
-    int vx[3], vy[3], vt[3];
-    vx[0] = x;
-    vy[0] = y;
-    vt[0] = t;
-    vx[1] = x + (m1 & 1);
-    vy[1] = y + ((m1 >> 1) & 1);
-    vt[1] = t + ((m1 >> 2) & 1);
-    vx[2] = vx[1] + (m2 & 1);
-    vy[2] = vy[1] + ((m2 >> 1) & 1);
-    vt[2] = vt[1] + ((m2 >> 2) & 1);
-
-    // quantised vectors (same stencil and rounding as pass 1)
-    long long q[3][2];
-    bool wide = false;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        float r = quant(F.vec(c, vx[i], vy[i], vt[i]), g.qscale);
-        q[i][c] = (long long)r;
-        if (!(fabsf(r) < 2147483648.0f)) wide = true;
+  // vector field of plane t into gs[par]
+  auto load_plane = [&](int t, int par) {
+    if (!vector) {
+      const float* src = g.f + (long long)t * plane;
+      for (int e = tid; e < FH * FW; e += 256) {
+        int ly = e / FW, lx = e - ly * FW;
+        int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+        fs[e] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? src[(long long)gy * nx + gx] : 0.0f;
       }
-    }
-    // exact cofactors of (v0 v1 v2 ; 1 1 1): C_i = (-1)^i det(columns without i)
-    i128 C[3];
-    C[0] = det2x<WIDE>(q[1][0], q[1][1], q[2][0], q[2][1]);
-    C[1] = -det2x<WIDE>(q[0][0], q[0][1], q[2][0], q[2][1]);
-    C[2] = det2x<WIDE>(q[0][0], q[0][1], q[1][0], q[1][1]);
-    const i128 D = C[0] + C[1] + C[2];
-    unsigned fl = wide ? FL_WIDE : 0u;
-
-    float J[3][4];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) F.jac(vx[i], vy[i], vt[i], J[i]);
-
-    float mu32[3];
-    double mu64[3];
-    const bool degenerate = (D == 0);
-    if (degenerate) {
-      fl |= FL_DEGENERATE;
-      ++n_deg;
-    }
-    int type = -1;
-    if (g.precision == 0) {
-      if (degenerate) {
-        mu32[0] = mu32[1] = mu32[2] = 1.0f / 3.0f;
-      } else {
-        float fD = (float)D;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) mu32[i] = (float)C[i] / fD;
-      }
-      type = classify2_fp32(mu32, J, g.kind != 0);
-    }
-    if (g.precision != 0 || type < 0) {
-      if (degenerate) {
-        mu64[0] = mu64[1] = mu64[2] = 1.0 / 3.0;
-      } else {
-        double dD = (double)D;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) mu64[i] = (double)C[i] / dD;
-      }
-      type = classify2_fp64(mu64, J, g.kind != 0);
-      if (g.precision == 0) {
-        fl |= FL_FP64;
-        ++n_fp64;
-      }
-    }
-    // sublocation: x = sum mu_i p_i, in the requested precision
-    float pos[3], muo[3];
-    if (g.precision == 0) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int* vc = c == 0 ? vx : (c == 1 ? vy : vt);
-        float s = mu32[0] * (float)vc[0];
-        s = s + mu32[1] * (float)vc[1];
-        s = s + mu32[2] * (float)vc[2];
-        pos[c] = s;
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) muo[i] = mu32[i];
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int* vc = c == 0 ? vx : (c == 1 ? vy : vt);
-        double s = mu64[0] * (double)vc[0];
-        s = s + mu64[1] * (double)vc[1];
-        s = s + mu64[2] * (double)vc[2];
-        pos[c] = (float)s;
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) muo[i] = (float)mu64[i];
-    }
-
-    o.face_id[idx] = gidx * 12 + ty;
-    if (o.pos) {
-      o.pos[(size_t)idx * 3 + 0] = pos[0];
-      o.pos[(size_t)idx * 3 + 1] = pos[1];
-      o.pos[(size_t)idx * 3 + 2] = pos[2];
-    }
-    if (o.mu) {
-      o.mu[(size_t)idx * 3 + 0] = muo[0];
-      o.mu[(size_t)idx * 3 + 1] = muo[1];
-      o.mu[(size_t)idx * 3 + 2] = muo[2];
-    }
-    if (o.type) o.type[idx] = (uint8_t)type;
-    if (o.flags) o.flags[idx] = (uint8_t)fl;
-
-    // ---- pass 2 links: the (at most two) tetrahedra containing this triangle.  A tetrahedron with chain
-    // (c1, c2, c3) anchored at c has sides: drop w0 -> (c + e_c1; c2, c3), drop w1 -> (c; c1|c2, c3),
-    // drop w2 -> (c; c1, c2|c3), drop w3 -> (c; c1, c2).
-    unsigned partner[2];
-    int np = 0;
-    const int b = m1 | m2;
-    auto visit_cell = [&](bool at_minus, int ma, int c1, int c2, int c3) {
-      // at_minus: cell anchored at p - e_ma (then c1 == ma), else at p
-      const Nb base = at_minus ? nb_minus(ma) : self;
-      const Nb first = at_minus ? self : nb_plus(c1);
-      int found = 0;
-      unsigned other = 0xFFFFFFFFu;
-      const int ts[4] = {kTri2Index.idx[c2][c3], kTri2Index.idx[c1 | c2][c3], kTri2Index.idx[c1][c2 | c3],
-                         kTri2Index.idx[c1][c2]};
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const Nb& u = (s == 0) ? first : base;
-        if (is_hit(u, ts[s])) {
-          unsigned hi = hit_index(u, ts[s]);
-          ++found;
-          if (hi != idx) other = hi;
+      __syncthreads();
+      for (int e = tid; e < GH * GW; e += 256) {
+        int ly = e / GW, lx = e - ly * GW;
+        int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+          const float* r = &fs[(ly + 1) * FW + (lx + 1)];
+          v.x = diff3(r[-1], r[0], r[1], gx, nx);
+          v.y = diff3(r[-FW], r[0], r[FW], gy, ny);
         }
+        gs[par][e] = v;
       }
-      if (found != 2 || other == 0xFFFFFFFFu) {
-        st |= ST_INVARIANT;
-        return;
-      }
-      partner[np++] = other;
-      if (other > idx) ++n_linked;
-    };
-    if (__popc((unsigned)m1) == 1 && __popc((unsigned)m2) == 1) {
-      const int a = 7 & ~b;  // missing axis
-      const int pa = a == 1 ? x : (a == 2 ? y : t);
-      const int Na = a == 1 ? nx : (a == 2 ? ny : nt);
-      if (pa >= 1) visit_cell(true, a, a, m1, m2);
-      if (pa + 1 <= Na - 1) visit_cell(false, 0, m1, m2, a);
-    } else if (__popc((unsigned)m1) == 2) {
-      const int lo = m1 & -m1, hi = m1 - lo;
-      visit_cell(false, 0, lo, hi, m2);
-      visit_cell(false, 0, hi, lo, m2);
     } else {
-      const int lo = m2 & -m2, hi = m2 - lo;
-      visit_cell(false, 0, m1, lo, hi);
-      visit_cell(false, 0, m1, hi, lo);
-    }
-    unsigned par0 = idx, smaller = 0, big_small = 0;
-    for (int i = 0; i < np; ++i) {
-      if (partner[i] < par0) par0 = partner[i];
-      if (partner[i] < idx) {
-        ++smaller;
-        big_small = big_small > partner[i] ? big_small : partner[i];
+      const float* su = g.f + (long long)t * 2 * plane;
+      const float* sv = su + plane;
+      for (int e = tid; e < GH * GW; e += 256) {
+        int ly = e / GW, lx = e - ly * GW;
+        int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+          long long k = (long long)gy * nx + gx;
+          v = make_float2(su[k], sv[k]);
+        }
+        gs[par][e] = v;
       }
     }
-    o.parent[idx] = par0;
-    if (smaller == 2) {
-      unsigned long long slot = atomicAdd(&cnt[CNT_WORK], 1ull);
-      o.work[slot] = make_uint2(idx, big_small);
+  };
+
+  // write the parent of every hit of the chunk: the hit index of its local root
+  auto flush = [&]() {
+    const int n = s_chunk_n;
+    for (int li = tid; li < n; li += 256) {
+      unsigned r = lfind(lpar, (unsigned)li);
+      o.parent[lglob[li]] = lglob[r];
+    }
+  };
+
+  // move the staged edges to the global list
+  auto drain = [&]() {
+    if (tid == 0) s_stage_base = s_stage_n ? atomicAdd(&cnt[CNT_WORK], (unsigned long long)s_stage_n) : 0ull;
+    __syncthreads();
+    const int n = s_stage_n;
+    for (int i = tid; i < n; i += 256) o.work[s_stage_base + i] = s_stage[i];
+    __syncthreads();
+    if (tid == 0) s_stage_n = 0;
+  };
+
+  if (tid == 0) {
+    s_chunk_t0 = t0;
+    s_chunk_n = 0;
+    s_stage_n = 0;
+  }
+  load_plane(t0, t0 & 1);
+  for (int t = t0; t < t1; ++t) {
+    const int par = t & 1;
+    __syncthreads();
+    if (s_stage_n > kEdgeStage / 2) drain();
+    if (t + 1 < nt) load_plane(t + 1, par ^ 1);
+
+    // row masks, prefixes and totals of this step
+    for (int ly = wave; ly < TY; ly += 4) {
+      const int y = y0 + ly, x = x0 + lane;
+      unsigned m = 0;
+      if (y < ny && x < nx) m = masks[(long long)t * plane + (long long)y * nx + x];
+      const unsigned c = __popc(m);
+      const unsigned incl = wave_incl_scan(c);
+      s_m[ly][lane] = (unsigned short)m;
+      s_ex[ly][lane] = (unsigned short)(incl - c);
+      if (lane == 63) {
+        s_rowtot[ly] = incl;
+        s_rowbase[ly] = y < ny ? (unsigned)seg_off[((long long)t * ny + y) * nxt + blockIdx.x] : 0u;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned tot = 0;
+      for (int r = 0; r < TY; ++r) tot += s_rowtot[r];
+      s_plane_total = (int)tot;
+      s_flush = (s_chunk_n > 0 && (s_chunk_n + (int)tot > CAP || t - s_chunk_t0 >= MAXTT)) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_flush) {
+      flush();
+      __syncthreads();
+      if (tid == 0) {
+        s_chunk_n = 0;
+        s_chunk_t0 = t;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const int tot = s_plane_total;
+      if (tot > CAP) {  // too many hits for the local structure: this step links through the global list only
+        s_global = 1;
+        s_chunk_t0 = t + 1;
+        s_chunk_n = 0;
+      } else {
+        s_global = 0;
+        if (s_chunk_n == 0) s_chunk_t0 = t;
+        s_plane_lbase = s_chunk_n;
+        unsigned run = (unsigned)s_chunk_n;
+        for (int r = 0; r < TY; ++r) {
+          lbase[t - s_chunk_t0][r] = run;
+          segb[t - s_chunk_t0][r] = s_rowbase[r];
+          run += s_rowtot[r];
+        }
+        s_chunk_n = (int)run;
+      }
+    }
+    __syncthreads();
+    const bool plane_global = s_global != 0;
+    const int chunk_t0 = s_chunk_t0;
+    if (!plane_global)
+      for (int i = tid; i < s_plane_total; i += 256) lpar[s_plane_lbase + i] = (unsigned)(s_plane_lbase + i);
+    __syncthreads();
+
+    for (int ly = wave; ly < TY; ly += 4) {
+      const int y = y0 + ly;
+      if (y >= ny) break;
+      const unsigned total = s_rowtot[ly];
+      if (total == 0) continue;
+      const int x = x0 + lane;
+      const bool in = x < nx;
+      const long long seg = ((long long)t * ny + y) * nxt + blockIdx.x;
+      const long long gidx = (long long)t * plane + (long long)y * nx + x;
+      const unsigned m = s_m[ly][lane];
+      const unsigned ex = s_ex[ly][lane];
+      const unsigned base = s_rowbase[ly];
+      const unsigned row_lbase = plane_global ? 0u : lbase[t - chunk_t0][ly];
+
+      // neighbour masks and first-hit indices (wavefront-private LDS slots)
+      {
+        unsigned mxm = 0, mxo = 0, pxm = 0, pxo = 0;
+        if (lane > 0) {
+          mxm = s_m[ly][lane - 1];
+          mxo = base + s_ex[ly][lane - 1];
+        } else if (x > 0) {
+          mxm = masks[gidx - 1];
+          mxo = base - __popc(mxm);
+        }
+        if (x + 1 < nx) {
+          if (lane < 63) {
+            pxm = s_m[ly][lane + 1];
+            pxo = base + s_ex[ly][lane + 1];
+          } else {
+            pxm = masks[gidx + 1];
+            pxo = base + total;
+          }
+        }
+        nbm[wave][NB_SELF][lane] = (unsigned short)m;
+        nbo[wave][NB_SELF][lane] = base + ex;
+        nbm[wave][NB_MX][lane] = (unsigned short)mxm;
+        nbo[wave][NB_MX][lane] = mxo;
+        nbm[wave][NB_PX][lane] = (unsigned short)pxm;
+        nbo[wave][NB_PX][lane] = pxo;
+        auto seg_nb = [&](int slot, long long dseg, long long dg, bool ok) {
+          unsigned mm = (ok && in) ? masks[gidx + dg] : 0u;
+          unsigned inc = wave_incl_scan(__popc(mm));
+          unsigned b = ok ? (unsigned)seg_off[seg + dseg] : 0u;
+          nbm[wave][slot][lane] = (unsigned short)mm;
+          nbo[wave][slot][lane] = b + inc - __popc(mm);
+        };
+        seg_nb(NB_MY, -(long long)nxt, -(long long)nx, y > 0);
+        seg_nb(NB_PY, (long long)nxt, (long long)nx, y + 1 < ny);
+        seg_nb(NB_MT, -(long long)nxt * ny, -plane, t > 0);
+        seg_nb(NB_PT, (long long)nxt * ny, plane, t + 1 < nt);
+      }
+      wave_lds_sync();
+
+      for (unsigned j = lane; j < total; j += 64) {
+        // anchor lane: the largest L with ex[L] <= j
+        int L = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1)
+          if (s_ex[ly][L + step] <= j) L += step;
+        unsigned mm = s_m[ly][L];
+        for (unsigned k = j - s_ex[ly][L]; k > 0; --k) mm &= mm - 1;
+        const int ty = __ffs(mm) - 1;
+        const unsigned idx = base + j;
+        const int ax = x0 + L;
+        const int m1 = kTri2.m[ty][0], m2 = kTri2.m[ty][1];
+
+        // vertices (local coordinates in the LDS tile, plane offset 0/1)
+        int lx[3], lyv[3], dt[3];
+        lx[0] = L;
+        lyv[0] = ly;
+        dt[0] = 0;
+        lx[1] = L + (m1 & 1);
+        lyv[1] = ly + ((m1 >> 1) & 1);
+        dt[1] = (m1 >> 2) & 1;
+        lx[2] = lx[1] + (m2 & 1);
+        lyv[2] = lyv[1] + ((m2 >> 1) & 1);
+        dt[2] = dt[1] + ((m2 >> 2) & 1);
+
+        long long q[3][2];
+        float J[3][4];
+        bool wide = false;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const float2* G = gs[par ^ dt[i]];
+          const int c = (lyv[i] + 1) * GW + (lx[i] + 1);
+          const float2 v = G[c];
+          const float r0 = quant(v.x, g.qscale), r1 = quant(v.y, g.qscale);
+          if (!(fabsf(r0) < 2147483648.0f) || !(fabsf(r1) < 2147483648.0f)) wide = true;
+          q[i][0] = (long long)r0;
+          q[i][1] = (long long)r1;
+          const int gxv = x0 + lx[i], gyv = y0 + lyv[i];
+          const float2 xl = G[c - 1], xh = G[c + 1], yl = G[c - GW], yh = G[c + GW];
+          J[i][0] = diff3(xl.x, v.x, xh.x, gxv, nx);
+          J[i][1] = diff3(yl.x, v.x, yh.x, gyv, ny);
+          J[i][2] = diff3(xl.y, v.y, xh.y, gxv, nx);
+          J[i][3] = diff3(yl.y, v.y, yh.y, gyv, ny);
+        }
+        // exact cofactors of (v0 v1 v2 ; 1 1 1): C_i = (-1)^i det(columns without i)
+        i128 C[3];
+        C[0] = det2x<WIDE>(q[1][0], q[1][1], q[2][0], q[2][1]);
+        C[1] = -det2x<WIDE>(q[0][0], q[0][1], q[2][0], q[2][1]);
+        C[2] = det2x<WIDE>(q[0][0], q[0][1], q[1][0], q[1][1]);
+        const i128 D = C[0] + C[1] + C[2];
+        unsigned fl = wide ? FL_WIDE : 0u;
+        const bool degenerate = (D == 0);
+        if (degenerate) {
+          fl |= FL_DEGENERATE;
+          ++n_deg;
+        }
+        float mu32[3];
+        double mu64[3];
+        int type = -1;
+        if (g.precision == 0) {
+          if (degenerate) {
+            mu32[0] = mu32[1] = mu32[2] = 1.0f / 3.0f;
+          } else {
+            const float fD = (float)D;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) mu32[i] = (float)C[i] / fD;
+          }
+          type = classify2_fp32(mu32, J, vector);
+        }
+        if (g.precision != 0 || type < 0) {
+          if (degenerate) {
+            mu64[0] = mu64[1] = mu64[2] = 1.0 / 3.0;
+          } else {
+            const double dD = (double)D;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) mu64[i] = (double)C[i] / dD;
+          }
+          type = classify2_fp64(mu64, J, vector);
+          if (g.precision == 0) {
+            fl |= FL_FP64;
+            ++n_fp64;
+          }
+        }
+        float pos[3], muo[3];
+        // vertex coordinates per component: x, y, t of v0, v1, v2
+        const int cx0 = ax, cx1 = ax + (m1 & 1), cx2 = cx1 + (m2 & 1);
+        const int cy0 = y, cy1 = y + ((m1 >> 1) & 1), cy2 = cy1 + ((m2 >> 1) & 1);
+        const int ct0 = t, ct1 = t + dt[1], ct2 = t + dt[2];
+        if (g.precision == 0) {
+          float sx = mu32[0] * (float)cx0;
+          sx = sx + mu32[1] * (float)cx1;
+          sx = sx + mu32[2] * (float)cx2;
+          float sy = mu32[0] * (float)cy0;
+          sy = sy + mu32[1] * (float)cy1;
+          sy = sy + mu32[2] * (float)cy2;
+          float stt = mu32[0] * (float)ct0;
+          stt = stt + mu32[1] * (float)ct1;
+          stt = stt + mu32[2] * (float)ct2;
+          pos[0] = sx;
+          pos[1] = sy;
+          pos[2] = stt;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) muo[i] = mu32[i];
+        } else {
+          double sx = mu64[0] * (double)cx0;
+          sx = sx + mu64[1] * (double)cx1;
+          sx = sx + mu64[2] * (double)cx2;
+          double sy = mu64[0] * (double)cy0;
+          sy = sy + mu64[1] * (double)cy1;
+          sy = sy + mu64[2] * (double)cy2;
+          double stt = mu64[0] * (double)ct0;
+          stt = stt + mu64[1] * (double)ct1;
+          stt = stt + mu64[2] * (double)ct2;
+          pos[0] = (float)sx;
+          pos[1] = (float)sy;
+          pos[2] = (float)stt;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) muo[i] = (float)mu64[i];
+        }
+        const long long agid = (long long)t * plane + (long long)y * nx + ax;
+        o.face_id[idx] = agid * 12 + ty;
+        if (o.pos) {
+          o.pos[(size_t)idx * 3 + 0] = pos[0];
+          o.pos[(size_t)idx * 3 + 1] = pos[1];
+          o.pos[(size_t)idx * 3 + 2] = pos[2];
+        }
+        if (o.mu) {
+          o.mu[(size_t)idx * 3 + 0] = muo[0];
+          o.mu[(size_t)idx * 3 + 1] = muo[1];
+          o.mu[(size_t)idx * 3 + 2] = muo[2];
+        }
+        if (o.type) o.type[idx] = (uint8_t)type;
+        if (o.flags) o.flags[idx] = (uint8_t)fl;
+
+        // ---- pass 2 links: the (at most two) tetrahedra holding this triangle.  A tetrahedron with chain
+        // (c1, c2, c3) anchored at c has sides: drop w0 -> (c + e_c1; c2, c3), drop w1 -> (c; c1|c2, c3),
+        // drop w2 -> (c; c1, c2|c3), drop w3 -> (c; c1, c2).  Each link is recorded by its larger endpoint:
+        // inside this tile and chunk it goes to the LDS union-find, otherwise to the global edge list.
+        unsigned sm0 = 0, sm1 = 0;
+        int sl0 = -1, sl1 = -1;
+        int ns = 0;
+        auto visit_cell = [&](bool at_minus, int c1, int c2, int c3) {
+          const int bslot = at_minus ? (c1 == 1 ? NB_MX : (c1 == 2 ? NB_MY : NB_MT)) : NB_SELF;
+          const int fslot = at_minus ? NB_SELF : (c1 == 1 ? NB_PX : (c1 == 2 ? NB_PY : NB_PT));
+          const int bm = nbm[wave][bslot][L], fm = nbm[wave][fslot][L];
+          const unsigned bo = nbo[wave][bslot][L], fo = nbo[wave][fslot][L];
+          int found = 0, oslot = -1;
+          unsigned other = 0xFFFFFFFFu;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int tsv = s == 0 ? kTri2Index.idx[c2][c3]
+                                   : (s == 1 ? kTri2Index.idx[c1 | c2][c3]
+                                             : (s == 2 ? kTri2Index.idx[c1][c2 | c3] : kTri2Index.idx[c1][c2]));
+            const int um = s == 0 ? fm : bm;
+            const unsigned uo = s == 0 ? fo : bo;
+            if ((um >> tsv) & 1) {
+              const unsigned hi = uo + __popc((unsigned)um & ((1u << tsv) - 1u));
+              ++found;
+              if (hi != idx) {
+                other = hi;
+                oslot = s == 0 ? fslot : bslot;
+              }
+            }
+          }
+          if (found != 2 || other == 0xFFFFFFFFu) {
+            st |= ST_INVARIANT;
+            return;
+          }
+          if (other < idx) {
+            if (ns == 0) {
+              sm0 = other;
+              sl0 = oslot;
+            } else {
+              sm1 = other;
+              sl1 = oslot;
+            }
+            ++ns;
+          }
+        };
+        const int b = m1 | m2;
+        if (__popc((unsigned)m1) == 1 && __popc((unsigned)m2) == 1) {
+          const int a = 7 & ~b;  // missing axis
+          const int pa = a == 1 ? ax : (a == 2 ? y : t);
+          const int Na = a == 1 ? nx : (a == 2 ? ny : nt);
+          if (pa >= 1) visit_cell(true, a, m1, m2);
+          if (pa + 1 <= Na - 1) visit_cell(false, m1, m2, a);
+        } else if (__popc((unsigned)m1) == 2) {
+          const int lo = m1 & -m1, hi = m1 - lo;
+          visit_cell(false, lo, hi, m2);
+          visit_cell(false, hi, lo, m2);
+        } else {
+          const int lo = m2 & -m2, hi = m2 - lo;
+          visit_cell(false, m1, lo, hi);
+          visit_cell(false, m1, hi, lo);
+        }
+        n_linked += ns;
+        bool g0 = false, g1 = false;
+        if (plane_global) {
+          o.parent[idx] = idx;
+          g0 = ns > 0;
+          g1 = ns > 1;
+        } else {
+          const unsigned li = row_lbase + j;
+          lglob[li] = idx;
+          // smaller partners are anchored at p (same row), p - x, p - y or p - t; the link stays local when that
+          // anchor lies in this tile and this chunk
+          auto link = [&](unsigned other, int sl) -> bool {
+            int prow = ly, pstep = t - chunk_t0;
+            bool local = true;
+            if (sl == NB_MX) {
+              local = L > 0;
+            } else if (sl == NB_MY) {
+              local = ly > 0;
+              prow = ly - 1;
+            } else if (sl == NB_MT) {
+              local = t - 1 >= chunk_t0;
+              pstep = t - 1 - chunk_t0;
+            }
+            if (!local) return true;
+            lunite(lpar, li, lbase[pstep][prow] + (other - segb[pstep][prow]));
+            return false;
+          };
+          if (ns > 0) g0 = link(sm0, sl0);
+          if (ns > 1) g1 = link(sm1, sl1);
+        }
+        append_edge(g0, idx, sm0, s_stage, &s_stage_n, o.work, &cnt[CNT_WORK]);
+        append_edge(g1, idx, sm1, s_stage, &s_stage_n, o.work, &cnt[CNT_WORK]);
+      }
+      wave_lds_sync();
     }
   }
-  unsigned long long s1 = wave_sum64(n_fp64), s2 = wave_sum64(n_deg), s3 = wave_sum64(n_linked);
-  if (lane == 0) {
+  __syncthreads();
+  flush();
+  drain();
+  unsigned long long s1 = block_sum256(n_fp64, s_red);
+  unsigned long long s2 = block_sum256(n_deg, s_red);
+  unsigned long long s3 = block_sum256(n_linked, s_red);
+  if (tid == 0) {
     if (s1) atomicAdd(&cnt[CNT_FP64], s1);
     if (s2) atomicAdd(&cnt[CNT_DEGEN], s2);
     if (s3) atomicAdd(&cnt[CNT_LINKED], s3);
@@ -562,11 +822,13 @@ hipError_t launch_detect2d(const Grid2& g, int ty, int tt, bool wide, uint16_t* 
 
 hipError_t launch_emit2d(const Grid2& g, bool wide, const uint16_t* masks, const long long* seg_off, long long nseg,
                          const Out2& o, unsigned* status, unsigned long long* cnt, hipStream_t s) {
-  unsigned blocks = (unsigned)((nseg + 3) / 4);
+  (void)nseg;
+  constexpr int TYE = 8, TTE = 16;
+  dim3 grid((unsigned)g.nxt, (unsigned)((g.ny + TYE - 1) / TYE), (unsigned)((g.nt + TTE - 1) / TTE));
   if (wide)
-    emit2d<true><<<blocks, 256, 0, s>>>(g, masks, seg_off, nseg, o, status, cnt);
+    emit2d<TYE, true><<<grid, 256, 0, s>>>(g, TTE, masks, seg_off, o, status, cnt);
   else
-    emit2d<false><<<blocks, 256, 0, s>>>(g, masks, seg_off, nseg, o, status, cnt);
+    emit2d<TYE, false><<<grid, 256, 0, s>>>(g, TTE, masks, seg_off, o, status, cnt);
   return hipGetLastError();
 }
 

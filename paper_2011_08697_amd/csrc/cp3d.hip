@@ -1,0 +1,634 @@
+// cp3d.hip -- critical-point tracking in 3D space + time on gfx950.
+//
+// Mesh: the Kuhn subdivision of the (x, y, z, t) grid (Sec. 3.3): per vertex 15 edge, 50 triangle, 60 tetrahedron
+// (the tested faces) and 24 pentachoron (cell) types.  A tetrahedron is punctured when the four signed cofactors of
+// (v0 v1 v2 v3 ; 1 1 1 1) agree (Sec. 4.3, Eq. 2); each cofactor is, up to a fixed sign, the 3x3 determinant of the
+// vectors of one of its triangles, so one SoS sign bit per triangle (50 per vertex, a 64-bit word) is computed and
+// shared through LDS.
+//
+//   detect3d -- time-marching slab kernel over a 16 x 8 x 4 anchor tile: field plane with a 2-cell halo, gradient,
+//               quantisation, triangle sign words of the tile (+1 halo), 60 tetrahedron tests per anchor; writes a
+//               60-bit puncture mask per vertex and the hit count of every 16-vertex row segment.
+//   emit3d   -- one lane per vertex (hits are sparse in 3D): output index from the segment prefix, exact cofactors,
+//               sublocation, Hessian type, and the union-find links of the hit's two pentachora (Alg. 1 pass 2).
+#include "common.h"
+#include "internal.h"
+
+namespace ftk {
+
+namespace {
+
+constexpr int TX3 = 16, TY3 = 8, TZ3 = 4;
+constexpr int SEG3 = 16;  // row segment width (x)
+
+constexpr unsigned long long kTetUseX = types_using_axis(kTet3, 1);
+constexpr unsigned long long kTetUseY = types_using_axis(kTet3, 2);
+constexpr unsigned long long kTetUseZ = types_using_axis(kTet3, 4);
+constexpr unsigned long long kTetUseT = types_using_axis(kTet3, 8);
+
+// triangle types without the time axis (ordinal) and with it (interval)
+struct TriSplit {
+  int n_ord, n_int;
+  unsigned char ord[50], itv[50];
+};
+constexpr TriSplit build_tri_split() {
+  TriSplit r{};
+  for (int i = 0; i < kTri3.count; ++i) {
+    if ((kTri3.m[i][0] | kTri3.m[i][1]) & 8)
+      r.itv[r.n_int++] = (unsigned char)i;
+    else
+      r.ord[r.n_ord++] = (unsigned char)i;
+  }
+  return r;
+}
+constexpr TriSplit kTriSplit = build_tri_split();
+static_assert(kTriSplit.n_ord == 12 && kTriSplit.n_int == 38, "12 ordinal + 38 interval triangle types");
+
+template <bool WIDE>
+struct Q3;
+template <>
+struct Q3<false> {
+  typedef int T;
+};
+template <>
+struct Q3<true> {
+  typedef long long T;
+};
+
+template <bool WIDE>
+__device__ __forceinline__ typename Q3<WIDE>::T to_q3(float r, unsigned& st) {
+  if (!WIDE) {
+    if (!(fabsf(r) < 1048576.0f)) {  // 2^20: every 3x3 determinant fits in 64 bits
+      st |= ST_WIDE;
+      return 0;
+    }
+    return (int)r;
+  } else {
+    if (!(fabsf(r) < 2199023255552.0f)) {  // 2^41: every 3x3 determinant fits in 128 bits
+      st |= ST_RANGE;
+      return 0;
+    }
+    return (long long)r;
+  }
+}
+
+// Exact 3x3 determinant of columns a, b, c (rows = components): 64-bit when |entries| < 2^20, else 128-bit.
+template <bool WIDE, typename Q>
+__device__ __forceinline__ i128 det3x(const Q* a, const Q* b, const Q* c) {
+  if (!WIDE) {
+    long long m0 = (long long)b[1] * c[2] - (long long)b[2] * c[1];
+    long long m1 = (long long)b[0] * c[2] - (long long)b[2] * c[0];
+    long long m2 = (long long)b[0] * c[1] - (long long)b[1] * c[0];
+    return (i128)((long long)a[0] * m0 - (long long)a[1] * m1 + (long long)a[2] * m2);
+  }
+  i128 m0 = (i128)b[1] * c[2] - (i128)b[2] * c[1];
+  i128 m1 = (i128)b[0] * c[2] - (i128)b[2] * c[0];
+  i128 m2 = (i128)b[0] * c[1] - (i128)b[1] * c[0];
+  return (i128)a[0] * m0 - (i128)a[1] * m1 + (i128)a[2] * m2;
+}
+
+// SoS sign of the 3x3 determinant m[j][k] (row j = component, column k = vertex in index order), entry (j, k)
+// perturbed by eps^(2^(3k+j)).  Expanding the perturbed determinant and ordering its terms by exponent, the sign
+// is that of the first nonzero of
+//   det, C00, C10, C20, C01, -m22, m12, C11, m22, -m02, C21, -m12, m02, C02, m21, -m11, -m20, -1
+// with C_jk = (-1)^(j+k) times the 2x2 minor without row j and column k.  Returned as a bit: 1 for positive.
+// (values passed by register: columns a = m[.][0], b = m[.][1], c = m[.][2])
+__device__ __noinline__ unsigned sos3_tail(long long a0, long long a1, long long a2, long long b0, long long b1,
+                                           long long b2, long long c0, long long c1, long long c2) {
+  const i128 m00 = a0, m10 = a1, m20 = a2;
+  const i128 m01 = b0, m11 = b1, m21 = b2;
+  const i128 m02 = c0, m12 = c1, m22 = c2;
+  i128 v;
+  v = m11 * m22 - m12 * m21;          // C00
+  if (v != 0) return v > 0;
+  v = -(m01 * m22 - m02 * m21);       // C10
+  if (v != 0) return v > 0;
+  v = m01 * m12 - m02 * m11;          // C20
+  if (v != 0) return v > 0;
+  v = -(m10 * m22 - m12 * m20);       // C01
+  if (v != 0) return v > 0;
+  if (m22 != 0) return m22 < 0;       // -m22
+  if (m12 != 0) return m12 > 0;       // m12
+  v = m00 * m22 - m02 * m20;          // C11
+  if (v != 0) return v > 0;
+  // m22 == 0 here, so the next term (m22) vanishes
+  if (m02 != 0) return m02 < 0;       // -m02
+  v = -(m00 * m12 - m02 * m10);       // C21
+  if (v != 0) return v > 0;
+  // m12 == 0 and m02 == 0 here
+  v = m10 * m21 - m11 * m20;          // C02
+  if (v != 0) return v > 0;
+  if (m21 != 0) return m21 > 0;       // m21
+  if (m11 != 0) return m11 < 0;       // -m11
+  if (m20 != 0) return m20 < 0;       // -m20
+  return 0u;                          // -1
+}
+
+template <bool WIDE, typename Q>
+__device__ __forceinline__ unsigned sos3_positive(const Q* a, const Q* b, const Q* c) {
+  const i128 d = det3x<WIDE, Q>(a, b, c);
+  if (d != 0) return d > 0;
+  return sos3_tail(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2]);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------------------------
+// Pass 1: detection.  grid = (ceil(nx/16), ceil(ny/8) * ceil(nz/4), ceil(nt/TT)), block = 256.
+// ---------------------------------------------------------------------------------------------------------------
+template <bool WIDE>
+__global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64_t* __restrict__ masks,
+                                                int* __restrict__ seg_cnt, unsigned* __restrict__ status) {
+  typedef typename Q3<WIDE>::T Q;
+  constexpr int FX = TX3 + 4, FY = TY3 + 4, FZ = TZ3 + 4;  // field: x0-1 .. x0+TX+2
+  constexpr int QX = TX3 + 2, QY = TY3 + 2, QZ = TZ3 + 2;  // quantised vectors: x0 .. x0+TX+1
+  constexpr int WX = TX3 + 1, WY = TY3 + 1, WZ = TZ3 + 1;  // triangle words: x0 .. x0+TX
+  constexpr int FN = FX * FY * FZ, QN = QX * QY * QZ, WN = WX * WY * WZ;
+  __shared__ float fs[FN];
+  __shared__ Q qs[2][3][QN];
+  __shared__ unsigned long long tw[2][WN];
+
+  const int tid = threadIdx.x;
+  const int nx = g.nx, ny = g.ny, nz = g.nz, nt = g.nt;
+  const int x0 = blockIdx.x * TX3;
+  const int by = blockIdx.y % nyt, bz = blockIdx.y / nyt;
+  const int y0 = by * TY3, z0 = bz * TZ3;
+  const int t0 = blockIdx.z * TT, t1 = min(t0 + TT, nt);
+  const long long plane = (long long)nx * ny * nz;
+  unsigned st = 0;
+
+  auto load_plane = [&](int t) {
+    const float* src = g.f + (long long)t * plane;
+    for (int e = tid; e < FN; e += 256) {
+      int lx = e % FX, r = e / FX, ly = r % FY, lz = r / FY;
+      int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+      float v = 0.0f;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
+        v = src[((long long)gz * ny + gy) * nx + gx];
+        if (!isfinite(v)) st |= ST_NONFINITE;
+      }
+      fs[e] = v;
+    }
+  };
+  auto quantise_plane = [&](int par) {
+    for (int e = tid; e < QN; e += 256) {
+      int lx = e % QX, r = e / QX, ly = r % QY, lz = r / QY;
+      int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+      Q q0 = 0, q1 = 0, q2 = 0;
+      if (gx < nx && gy < ny && gz < nz) {
+        const float* c = &fs[((lz + 1) * FY + (ly + 1)) * FX + (lx + 1)];
+        float v0 = diff3(c[-1], c[0], c[1], gx, nx);
+        float v1 = diff3(c[-FX], c[0], c[FX], gy, ny);
+        float v2 = diff3(c[-FX * FY], c[0], c[FX * FY], gz, nz);
+        q0 = to_q3<WIDE>(quant(v0, g.qscale), st);
+        q1 = to_q3<WIDE>(quant(v1, g.qscale), st);
+        q2 = to_q3<WIDE>(quant(v2, g.qscale), st);
+      }
+      qs[par][0][e] = q0;
+      qs[par][1][e] = q1;
+      qs[par][2][e] = q2;
+    }
+  };
+  // q of the 16 corners of the unit 4-cube at word-anchor (lx, ly, lz): corner mask bit 0 x, 1 y, 2 z, 3 t
+  auto corner = [&](int par, int wx, int wy, int wz, int cm, Q* out) {
+    const int p = (cm >> 3) ? (par ^ 1) : par;
+    const int e = ((wz + ((cm >> 2) & 1)) * QY + (wy + ((cm >> 1) & 1))) * QX + (wx + (cm & 1));
+    out[0] = qs[p][0][e];
+    out[1] = qs[p][1][e];
+    out[2] = qs[p][2][e];
+  };
+  // ordinal triangle bits of plane par (anchors of the word region) -> tw[par] (assignment)
+  auto ordinal_tris = [&](int par) {
+    for (int e = tid; e < WN; e += 256) {
+      int wx = e % WX, r = e / WX, wy = r % WY, wz = r / WY;
+      Q c[8][3];
+#pragma unroll
+      for (int cm = 0; cm < 8; ++cm) corner(par, wx, wy, wz, cm, c[cm]);
+      unsigned long long w = 0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const int ti = kTriSplit.ord[k];
+        const int a = kTri3.m[ti][0], b = a | kTri3.m[ti][1];
+        w |= (unsigned long long)sos3_positive<WIDE, Q>(c[0], c[a], c[b]) << ti;
+      }
+      tw[par][e] = w;
+    }
+  };
+  // interval triangle bits of plane par (to par^1) -> OR into tw[par]
+  auto interval_tris = [&](int par) {
+    for (int e = tid; e < WN; e += 256) {
+      int wx = e % WX, r = e / WX, wy = r % WY, wz = r / WY;
+      Q c[16][3];
+#pragma unroll
+      for (int cm = 0; cm < 16; ++cm) corner(par, wx, wy, wz, cm, c[cm]);
+      unsigned long long w = 0;
+#pragma unroll
+      for (int k = 0; k < 38; ++k) {
+        const int ti = kTriSplit.itv[k];
+        const int a = kTri3.m[ti][0], b = a | kTri3.m[ti][1];
+        w |= (unsigned long long)sos3_positive<WIDE, Q>(c[0], c[a], c[b]) << ti;
+      }
+      tw[par][e] |= w;
+    }
+  };
+
+  load_plane(t0);
+  __syncthreads();
+  quantise_plane(t0 & 1);
+  __syncthreads();
+  ordinal_tris(t0 & 1);
+
+  for (int t = t0; t < t1; ++t) {
+    const int par = t & 1, nxp = par ^ 1;
+    const bool has_next = t + 1 < nt;
+    __syncthreads();
+    if (has_next) {
+      load_plane(t + 1);
+      __syncthreads();
+      quantise_plane(nxp);
+      __syncthreads();
+      ordinal_tris(nxp);
+      interval_tris(par);
+    }
+    __syncthreads();
+
+    // 60 tetrahedron tests for the TX x TY x TZ anchors, 2 per thread; lanes of a wave: 16 x 4 rows
+    for (int a = tid; a < TX3 * TY3 * TZ3; a += 256) {
+      const int lx = a % TX3, r = a / TX3, ly = r % TY3, lz = r / TY3;
+      const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+      unsigned long long m = 0;
+      const bool in = gx < nx && gy < ny && gz < nz;
+      if (in) {
+        const int w0 = (lz * WY + ly) * WX + lx;
+        unsigned long long W[16];
+#pragma unroll
+        for (int cm = 0; cm < 16; ++cm) {
+          // neighbour p + e(cm); only masks with at most two axes are used as M1
+          const int dz = (cm >> 2) & 1, dy = (cm >> 1) & 1, dx = cm & 1;
+          const int p = (cm >> 3) ? nxp : par;
+          W[cm] = (__popc((unsigned)cm) <= 2 && (!(cm >> 3) || has_next)) ? tw[p][w0 + (dz * WY + dy) * WX + dx] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < 60; ++k) {
+          const int m1 = kTet3.m[k][0], m2 = kTet3.m[k][1], m3 = kTet3.m[k][2];
+          // sides opposite v0..v3: (p+e(M1); M2, M3), (p; M1|M2, M3), (p; M1, M2|M3), (p; M1, M2); cofactor signs
+          // -S0, +S1, -S2, +S3: punctured iff S1 = S3 and S0, S2 differ from them
+          const unsigned long long e0 = (W[m1] >> kTri3Index.idx[m2][m3]) & 1ull;
+          const unsigned long long e1 = (W[0] >> kTri3Index.idx[m1 | m2][m3]) & 1ull;
+          const unsigned long long e2 = (W[0] >> kTri3Index.idx[m1][m2 | m3]) & 1ull;
+          const unsigned long long e3 = (W[0] >> kTri3Index.idx[m1][m2]) & 1ull;
+          m |= (((e1 == e3) & (e0 != e1) & (e2 != e1)) ? 1ull : 0ull) << k;
+        }
+        unsigned long long valid = (1ull << 60) - 1ull;
+        if (gx == nx - 1) valid &= ~kTetUseX;
+        if (gy == ny - 1) valid &= ~kTetUseY;
+        if (gz == nz - 1) valid &= ~kTetUseZ;
+        if (t == nt - 1) valid &= ~kTetUseT;
+        m &= valid;
+        masks[(((long long)t * nz + gz) * ny + gy) * nx + gx] = m;
+      }
+      // count per 16-lane row segment
+      unsigned c = (unsigned)__popcll(m);
+#pragma unroll
+      for (int d = 8; d >= 1; d >>= 1) c += __shfl_xor(c, d, 16);
+      if (lx == 0 && gy < ny && gz < nz)
+        seg_cnt[(((long long)t * nz + gz) * ny + gy) * g.nxt + blockIdx.x] = (int)c;
+    }
+  }
+  if (st) atomicOr(status, st);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// Emission + links (hits are sparse: one lane per vertex, 4 row segments per wavefront).
+// ---------------------------------------------------------------------------------------------------------------
+namespace {
+
+struct Field3 {
+  const float* f;
+  int nx, ny, nz;
+  long long plane;
+  __device__ __forceinline__ float s(int x, int y, int z, int t) const {
+    return f[(long long)t * plane + ((long long)z * ny + y) * nx + x];
+  }
+  __device__ __forceinline__ float grad(int c, int x, int y, int z, int t) const {
+    const int N = c == 0 ? nx : (c == 1 ? ny : nz);
+    const int i = c == 0 ? x : (c == 1 ? y : z);
+    const int dx = c == 0, dy = c == 1, dz = c == 2;
+    float lo = i > 0 ? s(x - dx, y - dy, z - dz, t) : 0.0f;
+    float hi = i < N - 1 ? s(x + dx, y + dy, z + dz, t) : 0.0f;
+    return diff3(lo, s(x, y, z, t), hi, i, N);
+  }
+  // J[a][b] = d grad_a / d x_b, the same stencil on the binary32 gradient, row-major 3x3
+  __device__ __forceinline__ void jac(int x, int y, int z, int t, float J[9]) const {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float c = grad(a, x, y, z, t);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int N = b == 0 ? nx : (b == 1 ? ny : nz);
+        const int i = b == 0 ? x : (b == 1 ? y : z);
+        const int dx = b == 0, dy = b == 1, dz = b == 2;
+        float lo = i > 0 ? grad(a, x - dx, y - dy, z - dz, t) : 0.0f;
+        float hi = i < N - 1 ? grad(a, x + dx, y + dy, z + dz, t) : 0.0f;
+        J[a * 3 + b] = diff3(lo, c, hi, i, N);
+      }
+    }
+  }
+};
+
+// Binary64 classification of the gradient's Jacobian (the Hessian) in the reference order: H = (J + J^T) * 0.5,
+// s1 = trace, s2 = sum of principal 2x2 minors, s3 = det (first-row expansion); Descartes' rule on (1, s1, s2, s3)
+// counts negative eigenvalues (exact for the real-rooted characteristic polynomial of a symmetric matrix).
+__device__ __noinline__ int classify3_fp64(double mu0, double mu1, double mu2, double mu3, const float* J0,
+                                           const float* J1, const float* J2, const float* J3) {
+  double Jc[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    double s = mu0 * (double)J0[e];
+    s = s + mu1 * (double)J1[e];
+    s = s + mu2 * (double)J2[e];
+    s = s + mu3 * (double)J3[e];
+    Jc[e] = s;
+  }
+  double H[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double s = Jc[a * 3 + b] + Jc[b * 3 + a];
+      H[a * 3 + b] = s * 0.5;
+    }
+  const double s1 = (H[0] + H[4]) + H[8];
+  const double m01 = H[0] * H[4] - H[1] * H[3];
+  const double m02 = H[0] * H[8] - H[2] * H[6];
+  const double m12 = H[4] * H[8] - H[5] * H[7];
+  const double s2 = (m01 + m02) + m12;
+  const double c0 = H[4] * H[8] - H[5] * H[7];
+  const double c1 = H[3] * H[8] - H[5] * H[6];
+  const double c2 = H[3] * H[7] - H[4] * H[6];
+  const double s3 = (H[0] * c0 - H[1] * c1) + H[2] * c2;
+  if (s3 == 0) return T_DEG;
+  int changes = 0;
+  bool prev_neg = false;
+  const double seq[3] = {s1, s2, s3};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (seq[i] == 0) continue;
+    const bool neg = seq[i] < 0;
+    if (neg != prev_neg) ++changes;
+    prev_neg = neg;
+  }
+  return changes == 0 ? T_MIN : (changes == 1 ? T_SADDLE1 : (changes == 2 ? T_SADDLE2 : T_MAX));
+}
+
+}  // namespace
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restrict__ masks,
+                                              const long long* __restrict__ seg_off, long long nvtx_rows, Out3 o,
+                                              unsigned* __restrict__ status, unsigned long long* __restrict__ cnt) {
+  // thread -> vertex (x fastest, 16-wide segments)
+  const int nx = g.nx, ny = g.ny, nz = g.nz, nt = g.nt, nxt = g.nxt;
+  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);  // wave -> 64 x-values of one row
+  const int lane = threadIdx.x & 63;
+  const int xblocks = (nx + 63) / 64;
+  if (row >= nvtx_rows * xblocks) return;
+  const long long r = row / xblocks;
+  const int xb = (int)(row - r * xblocks);
+  const int x = xb * 64 + lane;
+  const int y = (int)(r % ny), z = (int)((r / ny) % nz), t = (int)(r / ((long long)ny * nz));
+  const bool in = x < nx;
+  const long long plane = (long long)nx * ny * nz;
+  const long long gidx = (long long)t * plane + ((long long)z * ny + y) * nx + x;
+  const unsigned long long m = in ? masks[gidx] : 0ull;
+  if (__ballot(m != 0) == 0) return;
+  unsigned st = 0;
+  unsigned long long n_deg = 0, n_linked = 0;
+
+  // first-hit index of vertex u (global coordinates, inside the grid): segment offset + hits of the earlier
+  // vertices of its 16-vertex segment
+  auto first_hit = [&](int ux, int uy, int uz, int ut) -> unsigned {
+    const long long seg = (((long long)ut * nz + uz) * ny + uy) * nxt + ux / SEG3;
+    unsigned off = (unsigned)seg_off[seg];
+    const long long ub = (long long)ut * plane + ((long long)uz * ny + uy) * nx;
+    for (int xx = (ux / SEG3) * SEG3; xx < ux; ++xx) off += (unsigned)__popcll(masks[ub + xx]);
+    return off;
+  };
+  auto mask_at = [&](int ux, int uy, int uz, int ut) -> unsigned long long {
+    return masks[(long long)ut * plane + ((long long)uz * ny + uy) * nx + ux];
+  };
+
+  Field3 F{g.f, nx, ny, nz, plane};
+  unsigned long long rem = m;
+  if (rem) {
+    unsigned k = 0;
+    const unsigned base = first_hit(x, y, z, t);
+    while (rem) {
+      const int ty = __ffsll((long long)rem) - 1;
+      rem &= rem - 1;
+      const unsigned idx = base + k;
+      ++k;
+      const int m1 = kTet3.m[ty][0], m2 = kTet3.m[ty][1], m3 = kTet3.m[ty][2];
+      int vx[4], vy[4], vz[4], vt[4];
+      const int cm[4] = {0, m1, m1 | m2, m1 | m2 | m3};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        vx[i] = x + (cm[i] & 1);
+        vy[i] = y + ((cm[i] >> 1) & 1);
+        vz[i] = z + ((cm[i] >> 2) & 1);
+        vt[i] = t + ((cm[i] >> 3) & 1);
+      }
+      long long q[4][3];
+      bool wide = false;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float rq = quant(F.grad(c, vx[i], vy[i], vz[i], vt[i]), g.qscale);
+          if (!(fabsf(rq) < 1048576.0f)) wide = true;
+          q[i][c] = (long long)rq;
+        }
+      // exact cofactors C_i = (-1)^(3+i) det(columns without i)
+      i128 C[4];
+      C[0] = -det3x<WIDE, long long>(q[1], q[2], q[3]);
+      C[1] = det3x<WIDE, long long>(q[0], q[2], q[3]);
+      C[2] = -det3x<WIDE, long long>(q[0], q[1], q[3]);
+      C[3] = det3x<WIDE, long long>(q[0], q[1], q[2]);
+      const i128 D = (C[0] + C[1]) + (C[2] + C[3]);
+      unsigned fl = wide ? FL_WIDE : 0u;
+      double mu64[4];
+      if (D == 0) {
+        fl |= FL_DEGENERATE;
+        ++n_deg;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mu64[i] = 1.0 / 4.0;
+      } else {
+        const double dD = (double)D;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mu64[i] = (double)C[i] / dD;
+      }
+      float J[4][9];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) F.jac(vx[i], vy[i], vz[i], vt[i], J[i]);
+      const int type = classify3_fp64(mu64[0], mu64[1], mu64[2], mu64[3], J[0], J[1], J[2], J[3]);
+      float pos[4], muo[4];
+      if (g.precision == 0) {
+        float mu32[4];
+        if (D == 0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) mu32[i] = 0.25f;
+        } else {
+          const float fD = (float)D;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) mu32[i] = (float)C[i] / fD;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int* vc = c == 0 ? vx : (c == 1 ? vy : (c == 2 ? vz : vt));
+          float s = mu32[0] * (float)vc[0];
+          s = s + mu32[1] * (float)vc[1];
+          s = s + mu32[2] * (float)vc[2];
+          s = s + mu32[3] * (float)vc[3];
+          pos[c] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) muo[i] = mu32[i];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int* vc = c == 0 ? vx : (c == 1 ? vy : (c == 2 ? vz : vt));
+          double s = mu64[0] * (double)vc[0];
+          s = s + mu64[1] * (double)vc[1];
+          s = s + mu64[2] * (double)vc[2];
+          s = s + mu64[3] * (double)vc[3];
+          pos[c] = (float)s;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) muo[i] = (float)mu64[i];
+      }
+      o.face_id[idx] = gidx * 60 + ty;
+      if (o.pos)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o.pos[(size_t)idx * 4 + c] = pos[c];
+      if (o.mu)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o.mu[(size_t)idx * 4 + c] = muo[c];
+      if (o.type) o.type[idx] = (uint8_t)type;
+      if (o.flags) o.flags[idx] = (uint8_t)fl;
+
+      // ---- links: the (at most two) pentachora holding this tetrahedron.  A pentachoron with chain
+      // (c1, c2, c3, c4) anchored at c has sides: drop w0 -> (c + e_c1; c2, c3, c4), drop w1 -> (c; c1|c2, c3, c4),
+      // drop w2 -> (c; c1, c2|c3, c4), drop w3 -> (c; c1, c2, c3|c4), drop w4 -> (c; c1, c2, c3).
+      unsigned p0 = idx, p1 = idx;
+      int np = 0;
+      auto visit_cell = [&](int cx, int cy, int cz, int ct, int c1, int c2, int c3, int c4) {
+        const int fx = cx + (c1 & 1), fy = cy + ((c1 >> 1) & 1), fz = cz + ((c1 >> 2) & 1), ft = ct + ((c1 >> 3) & 1);
+        const unsigned long long bm = mask_at(cx, cy, cz, ct);
+        const unsigned long long fm = mask_at(fx, fy, fz, ft);
+        int found = 0;
+        unsigned other = 0xFFFFFFFFu;
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+          int ti;
+          if (s == 0)
+            ti = kTet3Index.idx[c2][c3][c4];
+          else if (s == 1)
+            ti = kTet3Index.idx[c1 | c2][c3][c4];
+          else if (s == 2)
+            ti = kTet3Index.idx[c1][c2 | c3][c4];
+          else if (s == 3)
+            ti = kTet3Index.idx[c1][c2][c3 | c4];
+          else
+            ti = kTet3Index.idx[c1][c2][c3];
+          const unsigned long long um = s == 0 ? fm : bm;
+          if ((um >> ti) & 1ull) {
+            ++found;
+            const unsigned hi = (s == 0 ? first_hit(fx, fy, fz, ft) : first_hit(cx, cy, cz, ct)) +
+                                (unsigned)__popcll(um & ((1ull << ti) - 1ull));
+            if (hi != idx) other = hi;
+          }
+        }
+        if (found != 2 || other == 0xFFFFFFFFu) {
+          st |= ST_INVARIANT;
+          return;
+        }
+        if (np == 0)
+          p0 = other;
+        else
+          p1 = other;
+        ++np;
+        if (other > idx) ++n_linked;
+      };
+      const int b = m1 | m2 | m3;
+      const int N[4] = {nx, ny, nz, nt};
+      const int P[4] = {x, y, z, t};
+      if (__popc((unsigned)m1) == 1 && __popc((unsigned)m2) == 1 && __popc((unsigned)m3) == 1) {
+        const int a = 15 & ~b;  // missing axis
+        const int ai = __ffs(a) - 1;
+        if (P[ai] >= 1)
+          visit_cell(x - (a & 1), y - ((a >> 1) & 1), z - ((a >> 2) & 1), t - ((a >> 3) & 1), a, m1, m2, m3);
+        if (P[ai] + 1 <= N[ai] - 1) visit_cell(x, y, z, t, m1, m2, m3, a);
+      } else if (__popc((unsigned)m1) == 2) {
+        const int lo = m1 & -m1, hi = m1 - lo;
+        visit_cell(x, y, z, t, lo, hi, m2, m3);
+        visit_cell(x, y, z, t, hi, lo, m2, m3);
+      } else if (__popc((unsigned)m2) == 2) {
+        const int lo = m2 & -m2, hi = m2 - lo;
+        visit_cell(x, y, z, t, m1, lo, hi, m3);
+        visit_cell(x, y, z, t, m1, hi, lo, m3);
+      } else {
+        const int lo = m3 & -m3, hi = m3 - lo;
+        visit_cell(x, y, z, t, m1, m2, lo, hi);
+        visit_cell(x, y, z, t, m1, m2, hi, lo);
+      }
+      unsigned par0 = idx, smaller = 0, big_small = 0;
+      if (np > 0 && p0 < idx) {
+        ++smaller;
+        par0 = p0;
+        big_small = p0;
+      }
+      if (np > 1 && p1 < idx) {
+        ++smaller;
+        if (p1 < par0) par0 = p1;
+        if (p1 > big_small) big_small = p1;
+      }
+      o.parent[idx] = par0;
+      if (smaller == 2) {
+        unsigned long long slot = atomicAdd(&cnt[CNT_WORK], 1ull);
+        o.work[slot] = make_uint2(idx, big_small);
+      }
+    }
+  }
+  unsigned long long s2 = wave_sum64(n_deg), s3 = wave_sum64(n_linked);
+  if (lane == 0) {
+    if (s2) atomicAdd(&cnt[CNT_DEGEN], s2);
+    if (s3) atomicAdd(&cnt[CNT_LINKED], s3);
+  }
+  if (st) atomicOr(status, st);
+}
+
+hipError_t launch_detect3d(const Grid3& g, int tt, bool wide, uint64_t* masks, int* seg_cnt, unsigned* status,
+                           hipStream_t s) {
+  const int nyt = (g.ny + TY3 - 1) / TY3, nzt = (g.nz + TZ3 - 1) / TZ3;
+  dim3 grid((unsigned)((g.nx + TX3 - 1) / TX3), (unsigned)(nyt * nzt), (unsigned)((g.nt + tt - 1) / tt));
+  if (wide)
+    detect3d<true><<<grid, 256, 0, s>>>(g, tt, nyt, masks, seg_cnt, status);
+  else
+    detect3d<false><<<grid, 256, 0, s>>>(g, tt, nyt, masks, seg_cnt, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const long long* seg_off, long long nseg,
+                         const Out3& o, unsigned* status, unsigned long long* cnt, hipStream_t s) {
+  (void)nseg;
+  const long long rows = (long long)g.nt * g.nz * g.ny;
+  const long long waves = rows * ((g.nx + 63) / 64);
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  if (wide)
+    emit3d<true><<<blocks, 256, 0, s>>>(g, masks, seg_off, rows, o, status, cnt);
+  else
+    emit3d<false><<<blocks, 256, 0, s>>>(g, masks, seg_off, rows, o, status, cnt);
+  return hipGetLastError();
+}
+
+}  // namespace ftk

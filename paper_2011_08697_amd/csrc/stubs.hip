@@ -4,11 +4,6 @@
 #include "../../include/ftk.h"
 
 extern "C" {
-ftk_status ftk_track_cp3d(const float*, ftk_field_kind, int64_t, int64_t, int64_t, int64_t, const ftk_options*,
-                          ftk_stream_t, ftk_cp_result* out) {
-  if (out) *out = ftk_cp_result{};
-  return FTK_ERR_ARG;
-}
 ftk_status ftk_cp_create(int32_t, const int64_t*, ftk_field_kind, const ftk_options*, ftk_stream_t, ftk_tracker** h) {
   if (h) *h = nullptr;
   return FTK_ERR_ARG;

@@ -21,18 +21,24 @@ __global__ __launch_bounds__(256) void uf_hook(unsigned* __restrict__ parent, co
   }
 }
 
+// grid-stride; one trajectory-count atomic per block
 __global__ __launch_bounds__(256) void uf_label(unsigned* __restrict__ parent, const long long* __restrict__ face_id,
                                                 long long* __restrict__ label, long long n,
                                                 unsigned long long* __restrict__ cnt) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned roots = 0;
-  if (i < n) {
+  __shared__ unsigned long long red[4];
+  unsigned long long roots = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     unsigned r = uf_find(parent, (unsigned)i);
     if (label) label[i] = face_id[r];
-    roots = (r == (unsigned)i);
+    roots += (r == (unsigned)i);
   }
-  unsigned long long s = wave_sum64(roots);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd(&cnt[CNT_TRAJ], s);
+  roots = wave_sum64(roots);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = roots;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = red[0] + red[1] + red[2] + red[3];
+    if (s) atomicAdd(&cnt[CNT_TRAJ], s);
+  }
 }
 
 }  // namespace
@@ -49,7 +55,9 @@ hipError_t launch_uf_hook(unsigned* parent, const uint2* work, const unsigned lo
 hipError_t launch_uf_label(unsigned* parent, const long long* face_id, long long* label, long long n,
                            unsigned long long* cnt, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  uf_label<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(parent, face_id, label, n, cnt);
+  long long blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  uf_label<<<(unsigned)blocks, 256, 0, s>>>(parent, face_id, label, n, cnt);
   return hipGetLastError();
 }
 

@@ -60,10 +60,13 @@ def moving_gaussians_2d(nx, ny, nt, K, sigma=(4.0, 10.0), vmax=1.0, seed=0, nois
     return f.astype(np.float32)
 
 
-def moving_gaussians_3d(nx, ny, nz, nt, K, sigma=(6.0, 16.0), vmax=1.0, seed=2):
-    """3D analogue, f[t][z][y][x], separable window per blob."""
+def moving_gaussians_3d(nx, ny, nz, nt, K, sigma=(6.0, 16.0), vmax=1.0, seed=2, device=None):
+    """3D analogue, f[t][z][y][x], separable window per blob.  With a torch device the same float64 evaluation runs
+    there (the large 3D workload would take minutes in numpy); the float32 result is returned as a numpy array."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sign, amp, sig, centre, vel = _blob_params(rng, K, (nx, ny, nz), sigma, vmax)
+    if device is not None:
+        return _gaussians_3d_torch(nx, ny, nz, nt, K, sign, amp, sig, centre, vel, device)
     f = np.zeros((nt, nz, ny, nx), np.float64)
     for t in range(nt):
         vol = f[t]
@@ -81,6 +84,28 @@ def moving_gaussians_3d(nx, ny, nz, nt, K, sigma=(6.0, 16.0), vmax=1.0, seed=2):
             vol[rz[0]:rz[1], ry[0]:ry[1], rx[0]:rx[1]] += (sign[k] * amp[k]) * (
                 ez[:, None, None] * ey[None, :, None] * ex[None, None, :])
     return f.astype(np.float32)
+
+
+def _gaussians_3d_torch(nx, ny, nz, nt, K, sign, amp, sig, centre, vel, device):
+    import torch
+    out = np.empty((nt, nz, ny, nx), np.float32)
+    for t in range(nt):
+        vol = torch.zeros((nz, ny, nx), dtype=torch.float64, device=device)
+        for k in range(K):
+            c = [centre[k, a] + vel[k, a] * t for a in range(3)]
+            rx = _windows(c[0], sig[k], nx)
+            ry = _windows(c[1], sig[k], ny)
+            rz = _windows(c[2], sig[k], nz)
+            if rx[0] >= rx[1] or ry[0] >= ry[1] or rz[0] >= rz[1]:
+                continue
+            inv = 1.0 / (2.0 * sig[k] * sig[k])
+            ex = torch.exp(-((torch.arange(*rx, dtype=torch.float64, device=device) - c[0]) ** 2) * inv)
+            ey = torch.exp(-((torch.arange(*ry, dtype=torch.float64, device=device) - c[1]) ** 2) * inv)
+            ez = torch.exp(-((torch.arange(*rz, dtype=torch.float64, device=device) - c[2]) ** 2) * inv)
+            vol[rz[0]:rz[1], ry[0]:ry[1], rx[0]:rx[1]] += (float(sign[k]) * float(amp[k])) * (
+                ez[:, None, None] * ey[None, :, None] * ex[None, None, :])
+        out[t] = vol.to(torch.float32).cpu().numpy()
+    return out
 
 
 def vortex_sources_2d(nx, ny, nt, K, sigma=(16.0, 48.0), vmax=2.0, seed=4):
@@ -188,8 +213,9 @@ CONFIGS = {
 }
 
 
-def make(name, nt=None, ny=None):
-    """Generate a named workload (optionally only the first nt steps / ny rows)."""
+def make(name, nt=None, ny=None, device=None):
+    """Generate a named workload (optionally only the first nt steps / ny rows; device: torch device for the 3D
+    field's float64 evaluation)."""
     c = CONFIGS[name]
     if name == "c0":
         nx, nyy, ntt = c["dims"]
@@ -201,7 +227,7 @@ def make(name, nt=None, ny=None):
         return quantise_levels(f) if name == "c1deg" else f
     if name == "c2":
         nx, nyy, nz, ntt = c["dims"]
-        return moving_gaussians_3d(nx, ny or nyy, nz, nt or ntt, c["K"], seed=c["seed"])
+        return moving_gaussians_3d(nx, ny or nyy, nz, nt or ntt, c["K"], seed=c["seed"], device=device)
     if name == "c4":
         nx, nyy, ntt = c["dims"]
         return vortex_sources_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"])

@@ -1,0 +1,79 @@
+"""The C ABI library loads and exports every symbol include/ftk.h declares; host-side argument checks (no GPU
+compute is launched by these tests)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2011_08697_amd as F
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "ftk.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(ftk_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(n for n in names if not n.endswith("_fn")))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 12
+    L = F.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(F.EXPORTS)
+
+
+def test_version_and_defaults():
+    L = F.lib()
+    assert b"gfx950" in L.ftk_version()
+    o = F.Options()
+    L.ftk_default_options(ctypes.byref(o))
+    assert o.quant_log2 == 20 and o.precision == 0 and o.outputs == 31
+
+
+@pytest.mark.parametrize("n,dims", [(2, (64, 64, 10)), (2, (1024, 1024, 100)), (2, (4096, 4096, 50)),
+                                    (3, (256, 256, 256, 16)), (2, (5, 3, 2)), (3, (2, 3, 4, 5))])
+def test_simplex_count_matches_oracle(n, dims):
+    assert F.simplex_count(n, dims) == O.simplex_count(n, dims)
+
+
+def test_simplex_count_rejects_bad_dims():
+    assert F.simplex_count(2, (1, 5, 5)) == -1
+    assert F.simplex_count(4, (5, 5, 5, 5, 5)) == -1
+
+
+def _call2d(field_ptr, kind, nx, ny, nt, opt=None):
+    L = F.lib()
+    r = F.Result()
+    st = L.ftk_track_cp2d(field_ptr, kind, nx, ny, nt, ctypes.byref(opt) if opt else None, None, ctypes.byref(r))
+    return st, r
+
+
+def test_argument_errors_are_reported_before_any_device_work():
+    # null field, bad kind, too-small dims and bad options are rejected on the host
+    st, _ = _call2d(None, 0, 8, 8, 4)
+    assert st == 1 and "NULL" in F.last_error()
+    st, _ = _call2d(ctypes.c_void_p(16), 5, 8, 8, 4)
+    assert st == 1
+    st, _ = _call2d(ctypes.c_void_p(16), 0, 1, 8, 4)
+    assert st == 1 and ">= 2" in F.last_error()
+    o = F.Options()
+    F.lib().ftk_default_options(ctypes.byref(o))
+    o.quant_log2 = 70
+    st, _ = _call2d(ctypes.c_void_p(16), 0, 8, 8, 4, o)
+    assert st == 1 and "quant_log2" in F.last_error()
+    o.quant_log2 = 20
+    o.tile_y = 7
+    st, _ = _call2d(ctypes.c_void_p(16), 0, 8, 8, 4, o)
+    assert st == 1
+
+
+def test_result_free_of_empty_result_is_safe():
+    r = F.Result()
+    F.lib().ftk_result_free(ctypes.byref(r), None, None)
