@@ -70,6 +70,7 @@ typedef enum {
 #define FTK_OUT_LABEL 8u
 #define FTK_OUT_FLAGS 16u
 #define FTK_OUT_ALL 31u
+#define FTK_OUT_DEFAULT 29u /* POS | TYPE | LABEL | FLAGS: the 30-byte record per hit (face_id, pos, type, flags, label) */
 
 /* Device allocator hooks (e.g. a framework's caching allocator).  Both must be stream-ordered on `stream`. */
 typedef void* (*ftk_alloc_fn)(size_t bytes, ftk_stream_t stream, void* ctx);
@@ -78,7 +79,7 @@ typedef void (*ftk_free_fn)(void* ptr, ftk_stream_t stream, void* ctx);
 typedef struct {
   int32_t quant_log2;  /* fixed-point scale 2^quant_log2 for the vectors; default 20; range [0, 40] */
   int32_t precision;   /* 0: FP32 sublocation/classification with certified FP64 fallback; 1: FP64 throughout */
-  uint32_t outputs;    /* FTK_OUT_* bits; 0 means FTK_OUT_ALL */
+  uint32_t outputs;    /* FTK_OUT_* bits; 0 means FTK_OUT_DEFAULT */
   int32_t tile_y;      /* rows per detection tile (0 = tuned default) */
   int32_t slab_depth;  /* time steps per detection workgroup (0 = tuned default) */
   ftk_alloc_fn alloc;  /* NULL: hipMallocAsync on the stream */
@@ -117,7 +118,8 @@ typedef struct {
 
 typedef struct ftk_tracker ftk_tracker;
 
-/* Default options (quant_log2 = 20, precision 0, all outputs, tuned tiles, HIP stream-ordered allocator). */
+/* Default options (quant_log2 = 20, precision 0, FTK_OUT_DEFAULT outputs, tuned tiles, HIP stream-ordered
+ * allocator). */
 void ftk_default_options(ftk_options* opt);
 
 /*

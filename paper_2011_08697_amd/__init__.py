@@ -15,7 +15,7 @@ TYPES = ["DEGENERATE", "MIN", "MAX", "SADDLE", "SADDLE1", "SADDLE2", "SOURCE", "
 STATUS = ["OK", "ERR_ARG", "ERR_NONFINITE", "ERR_RANGE", "ERR_CAPACITY", "ERR_OOM", "ERR_HIP",
           "ERR_INVARIANT", "ERR_STATE"]
 FLAG_DEGENERATE_SUBLOC, FLAG_FP64_FALLBACK, FLAG_WIDE = 1, 2, 4
-OUT_POS, OUT_MU, OUT_TYPE, OUT_LABEL, OUT_FLAGS, OUT_ALL = 1, 2, 4, 8, 16, 31
+OUT_POS, OUT_MU, OUT_TYPE, OUT_LABEL, OUT_FLAGS, OUT_ALL, OUT_DEFAULT = 1, 2, 4, 8, 16, 31, 29
 SCALAR, VECTOR = 0, 1
 
 EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_create", "ftk_cp_push",
@@ -138,7 +138,7 @@ class _TorchPool:
         return t.view(dtype)[:n].view(*shape) if n else t.view(dtype)[:0].view(*shape)
 
 
-def _options(pool, quant_log2=20, precision=0, outputs=OUT_ALL, tile_y=0, slab_depth=0, profile=0):
+def _options(pool, quant_log2=20, precision=0, outputs=OUT_DEFAULT, tile_y=0, slab_depth=0, profile=0):
     o = Options()
     lib().ftk_default_options(ctypes.byref(o))
     o.quant_log2, o.precision, o.outputs = quant_log2, precision, outputs

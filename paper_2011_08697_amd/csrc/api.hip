@@ -105,7 +105,7 @@ void resolve(const ftk_options* in, ftk_options* o) {
   ftk_default_options(o);
   if (in) {
     *o = *in;
-    if (o->outputs == 0) o->outputs = FTK_OUT_ALL;
+    if (o->outputs == 0) o->outputs = FTK_OUT_DEFAULT;
   }
 }
 
@@ -183,7 +183,7 @@ void ftk_default_options(ftk_options* opt) {
   std::memset(opt, 0, sizeof(*opt));
   opt->quant_log2 = 20;
   opt->precision = 0;
-  opt->outputs = FTK_OUT_ALL;
+  opt->outputs = FTK_OUT_DEFAULT;
 }
 
 const char* ftk_last_error(void) { return g_err.c_str(); }

@@ -77,16 +77,18 @@ __device__ __forceinline__ float quant(float v, float scale) { return rintf(v * 
 template <typename Q>
 __device__ __forceinline__ unsigned sos2_positive(Q a0, Q a1, Q b0, Q b1);
 
+// Narrow path: components are integers below 2^24 carried in binary32 (exactly).  Both products are integers below
+// 2^48 and their difference is below 2^49, so the binary64 evaluation below is the exact integer determinant.
 template <>
-__device__ __forceinline__ unsigned sos2_positive<int>(int a0, int a1, int b0, int b1) {
-  long long d = (long long)a0 * b1 - (long long)a1 * b0;
-  unsigned r = d > 0;
-  bool dz = (d == 0);
-  unsigned t1 = b1 > 0, t2 = b0 < 0, t3 = a1 < 0;
-  unsigned seq = (b1 != 0) ? t1 : ((b0 != 0) ? t2 : ((a1 != 0) ? t3 : 0u));
-  return dz ? seq : r;
+__device__ __forceinline__ unsigned sos2_positive<float>(float a0, float a1, float b0, float b1) {
+  const double p = (double)a1 * (double)b0;
+  const double d = __builtin_fma((double)a0, (double)b1, -p);
+  const unsigned r = d > 0.0;
+  const unsigned seq = (b1 != 0.0f) ? (b1 > 0.0f) : ((b0 != 0.0f) ? (b0 < 0.0f) : ((a1 != 0.0f) ? (a1 < 0.0f) : 0u));
+  return d != 0.0 ? r : seq;
 }
 
+// Wide path: 64-bit components below 2^62, 128-bit products.
 template <>
 __device__ __forceinline__ unsigned sos2_positive<long long>(long long a0, long long a1, long long b0, long long b1) {
   i128 d = (i128)a0 * b1 - (i128)a1 * b0;
@@ -214,6 +216,17 @@ __device__ __forceinline__ unsigned uf_find(unsigned* parent, unsigned x) {
     if (gp != p) __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     x = p;
     p = gp;
+  }
+  return x;
+}
+
+// Find without coherence traffic, for passes in which nothing else changes the forest: every stored parent is an
+// ancestor, so plain (L2-cached) loads reach the root.
+__device__ __forceinline__ unsigned uf_find_plain(const unsigned* __restrict__ parent, unsigned x) {
+  unsigned p = parent[x];
+  while (p != x) {
+    x = p;
+    p = parent[x];
   }
   return x;
 }

@@ -29,26 +29,29 @@ constexpr unsigned kUseX = (unsigned)types_using_axis(kTri2, 1);
 constexpr unsigned kUseY = (unsigned)types_using_axis(kTri2, 2);
 constexpr unsigned kUseT = (unsigned)types_using_axis(kTri2, 4);
 
+// Quantised components: the narrow path keeps integers below 2^24 in binary32 (exact, and every determinant and
+// cofactor of the path stays exact in binary64); the wide path keeps 64-bit integers below 2^62.
 template <bool WIDE>
 struct QType;
 template <>
 struct QType<false> {
-  typedef int T;
+  typedef float T;
 };
 template <>
 struct QType<true> {
   typedef long long T;
 };
 
-// Round-to-integer with range classification.  Narrow: |q| < 2^31.  Wide: |q| < 2^62.
+constexpr float kNarrow2 = 16777216.0f;  // 2^24
+
 template <bool WIDE>
 __device__ __forceinline__ typename QType<WIDE>::T to_q(float r, unsigned& st) {
   if (!WIDE) {
-    if (!(fabsf(r) < 2147483648.0f)) {
+    if (!(fabsf(r) < kNarrow2)) {
       st |= ST_WIDE;
-      return 0;
+      return 0.0f;
     }
-    return (int)r;
+    return r;
   } else {
     if (!(fabsf(r) < 4611686018427387904.0f)) {
       st |= ST_RANGE;
@@ -241,20 +244,66 @@ __global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __res
 // ---------------------------------------------------------------------------------------------------------------
 namespace {
 
-// Exact 2x2 determinant of integer columns (a, b); 128-bit for the wide path.
-template <bool WIDE>
-__device__ __forceinline__ i128 det2x(long long a0, long long a1, long long b0, long long b1) {
-  if (!WIDE) return (i128)(a0 * b1 - a1 * b0);  // |q| < 2^31: both products and the difference fit in 64 bits
-  return (i128)a0 * b1 - (i128)a1 * b0;
+// Side tables of the triangle types, built at compile time and copied to LDS at kernel start.
+// kTri2Pack[ty] = M1 | M2 << 4.  kTri2Cof[ty][k] describes the k-th tetrahedron holding a triangle of type ty
+// (Alg. 1 pass 2, "tet.sides(2)" read backwards): bits 0-1 existence rule (1 always, 2 when p_a >= 1, 3 when
+// p_a + 1 <= N_a - 1), bits 2-3 the axis a, then its three other sides as (anchor slot, type) in 7-bit fields.
+enum { NB_SELF = 0, NB_MX, NB_PX, NB_MY, NB_PY, NB_MT, NB_PT };
+
+struct Tri2Tables {
+  unsigned char pack[12];
+  unsigned cof[12][2];
+};
+
+constexpr int slot_minus(int ab) { return ab == 1 ? NB_MX : (ab == 2 ? NB_MY : NB_MT); }
+constexpr int slot_plus(int ab) { return ab == 1 ? NB_PX : (ab == 2 ? NB_PY : NB_PT); }
+constexpr int axis_of(int ab) { return ab == 1 ? 0 : (ab == 2 ? 1 : 2); }
+
+// A tetrahedron with chain (c1, c2, c3) anchored at c has sides: drop w0 -> (c + e_c1; c2, c3),
+// drop w1 -> (c; c1|c2, c3), drop w2 -> (c; c1, c2|c3), drop w3 -> (c; c1, c2).  at_minus: c = p - e_c1.
+constexpr unsigned cof_word(int ty, bool at_minus, int rule, int axis, int c1, int c2, int c3) {
+  const int first = at_minus ? NB_SELF : slot_plus(c1);
+  const int base = at_minus ? slot_minus(c1) : NB_SELF;
+  const int st[4] = {first, base, base, base};
+  const int tt[4] = {kTri2Index.idx[c2][c3], kTri2Index.idx[c1 | c2][c3], kTri2Index.idx[c1][c2 | c3],
+                     kTri2Index.idx[c1][c2]};
+  unsigned w = (unsigned)rule | ((unsigned)axis << 2);
+  int k = 0;
+  for (int s = 0; s < 4; ++s) {
+    if (st[s] == NB_SELF && tt[s] == ty) continue;  // the triangle itself
+    w |= (unsigned)(st[s] | (tt[s] << 3)) << (4 + 7 * k);
+    ++k;
+  }
+  return w;
 }
+
+constexpr Tri2Tables build_tri2_tables() {
+  Tri2Tables r{};
+  for (int ty = 0; ty < 12; ++ty) {
+    const int m1 = kTri2.m[ty][0], m2 = kTri2.m[ty][1];
+    r.pack[ty] = (unsigned char)(m1 | (m2 << 4));
+    if (popc_c(m1) == 1 && popc_c(m2) == 1) {
+      const int a = 7 & ~(m1 | m2);
+      r.cof[ty][0] = cof_word(ty, true, 2, axis_of(a), a, m1, m2);
+      r.cof[ty][1] = cof_word(ty, false, 3, axis_of(a), m1, m2, a);
+    } else if (popc_c(m1) == 2) {
+      const int lo = m1 & -m1, hi = m1 - lo;
+      r.cof[ty][0] = cof_word(ty, false, 1, 0, lo, hi, m2);
+      r.cof[ty][1] = cof_word(ty, false, 1, 0, hi, lo, m2);
+    } else {
+      const int lo = m2 & -m2, hi = m2 - lo;
+      r.cof[ty][0] = cof_word(ty, false, 1, 0, m1, lo, hi);
+      r.cof[ty][1] = cof_word(ty, false, 1, 0, m1, hi, lo);
+    }
+  }
+  return r;
+}
+constexpr Tri2Tables kTri2Tab = build_tri2_tables();
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
-
-// neighbour slots of an anchor: self, -x, +x, -y, +y, -t, +t
-enum { NB_SELF = 0, NB_MX, NB_PX, NB_MY, NB_PY, NB_MT, NB_PT };
 
 }  // namespace
 
@@ -288,7 +337,7 @@ __device__ __forceinline__ void lunite(unsigned* lp, unsigned a, unsigned b) {
 
 // Edge list staging: links that leave the tile/chunk are collected in LDS and appended to the global list in
 // batches (one global atomic per batch; same-address atomics serialise at one L2 channel).
-constexpr int kEdgeStage = 768;
+constexpr int kEdgeStage = 512;
 
 // Wave-aggregated append of (idx, partner) for the active lanes with want == true: into the LDS stage if it has
 // room, otherwise straight to the global list.
@@ -343,7 +392,7 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
                                               unsigned* __restrict__ status, unsigned long long* __restrict__ cnt) {
   constexpr int GW = TX + 3, GH = TY + 3;  // vector field: x0-1 .. x0+TX+1, y0-1 .. y0+TY+1
   constexpr int FW = TX + 5, FH = TY + 5;  // scalar field: x0-2 .. x0+TX+2
-  constexpr int CAP = 2048;                // local union-find capacity (hits)
+  constexpr int CAP = 1792;                // local union-find capacity (hits)
   constexpr int MAXTT = 32;
   __shared__ float fs[FH * FW];
   __shared__ float2 gs[2][GH * GW];
@@ -352,6 +401,7 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
   __shared__ unsigned s_rowtot[TY], s_rowbase[TY];
   __shared__ unsigned short nbm[4][7][64];
   __shared__ unsigned nbo[4][7][64];
+  __shared__ unsigned char s_lane[4][12 * 64];  // hit j of the current row -> anchor lane
   __shared__ unsigned lpar[CAP];
   __shared__ unsigned lglob[CAP];
   __shared__ unsigned lbase[MAXTT][TY];  // local id of the first hit of (chunk step, row)
@@ -361,6 +411,8 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
   __shared__ int s_stage_n;
   __shared__ unsigned long long s_stage_base;
   __shared__ unsigned long long s_red[4];
+  __shared__ unsigned s_pack[12];
+  __shared__ unsigned s_cof[12][2];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
@@ -371,6 +423,12 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
   const bool vector = g.kind != 0;
   unsigned st = 0;
   unsigned long long n_fp64 = 0, n_deg = 0, n_linked = 0;
+
+  if (tid < 12) {
+    s_pack[tid] = kTri2Tab.pack[tid];
+    s_cof[tid][0] = kTri2Tab.cof[tid][0];
+    s_cof[tid][1] = kTri2Tab.cof[tid][1];
+  }
 
   // vector field of plane t into gs[par]
   auto load_plane = [&](int t, int par) {
@@ -417,7 +475,6 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
       o.parent[lglob[li]] = lglob[r];
     }
   };
-
   // move the staged edges to the global list
   auto drain = [&]() {
     if (tid == 0) s_stage_base = s_stage_n ? atomicAdd(&cnt[CNT_WORK], (unsigned long long)s_stage_n) : 0ull;
@@ -511,7 +568,7 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
       const unsigned base = s_rowbase[ly];
       const unsigned row_lbase = plane_global ? 0u : lbase[t - chunk_t0][ly];
 
-      // neighbour masks and first-hit indices (wavefront-private LDS slots)
+      // neighbour masks and first-hit indices (wavefront-private LDS slots); hit -> lane map
       {
         unsigned mxm = 0, mxo = 0, pxm = 0, pxo = 0;
         if (lane > 0) {
@@ -547,47 +604,39 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
         seg_nb(NB_PY, (long long)nxt, (long long)nx, y + 1 < ny);
         seg_nb(NB_MT, -(long long)nxt * ny, -plane, t > 0);
         seg_nb(NB_PT, (long long)nxt * ny, plane, t + 1 < nt);
+        const unsigned c_self = __popc(m);
+        for (unsigned k = 0; k < c_self; ++k) s_lane[wave][ex + k] = (unsigned char)lane;
       }
       wave_lds_sync();
 
       for (unsigned j = lane; j < total; j += 64) {
-        // anchor lane: the largest L with ex[L] <= j
-        int L = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1)
-          if (s_ex[ly][L + step] <= j) L += step;
+        const int L = s_lane[wave][j];
         unsigned mm = s_m[ly][L];
         for (unsigned k = j - s_ex[ly][L]; k > 0; --k) mm &= mm - 1;
         const int ty = __ffs(mm) - 1;
         const unsigned idx = base + j;
         const int ax = x0 + L;
-        const int m1 = kTri2.m[ty][0], m2 = kTri2.m[ty][1];
+        const unsigned pk = s_pack[ty];
+        const int m1 = pk & 15, m2 = pk >> 4;
+        // vertex offsets along x, y, t of v1 and v2
+        const int dx1 = m1 & 1, dy1 = (m1 >> 1) & 1, dt1 = (m1 >> 2) & 1;
+        const int dx2 = dx1 + (m2 & 1), dy2 = dy1 + ((m2 >> 1) & 1), dt2 = dt1 + ((m2 >> 2) & 1);
+        const int lxs[3] = {L, L + dx1, L + dx2};
+        const int lys[3] = {ly, ly + dy1, ly + dy2};
+        const int dts[3] = {0, dt1, dt2};
 
-        // vertices (local coordinates in the LDS tile, plane offset 0/1)
-        int lx[3], lyv[3], dt[3];
-        lx[0] = L;
-        lyv[0] = ly;
-        dt[0] = 0;
-        lx[1] = L + (m1 & 1);
-        lyv[1] = ly + ((m1 >> 1) & 1);
-        dt[1] = (m1 >> 2) & 1;
-        lx[2] = lx[1] + (m2 & 1);
-        lyv[2] = lyv[1] + ((m2 >> 1) & 1);
-        dt[2] = dt[1] + ((m2 >> 2) & 1);
-
-        long long q[3][2];
+        float qf[3][2];
         float J[3][4];
         bool wide = false;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          const float2* G = gs[par ^ dt[i]];
-          const int c = (lyv[i] + 1) * GW + (lx[i] + 1);
+          const float2* G = gs[par ^ dts[i]];
+          const int c = (lys[i] + 1) * GW + (lxs[i] + 1);
           const float2 v = G[c];
-          const float r0 = quant(v.x, g.qscale), r1 = quant(v.y, g.qscale);
-          if (!(fabsf(r0) < 2147483648.0f) || !(fabsf(r1) < 2147483648.0f)) wide = true;
-          q[i][0] = (long long)r0;
-          q[i][1] = (long long)r1;
-          const int gxv = x0 + lx[i], gyv = y0 + lyv[i];
+          qf[i][0] = quant(v.x, g.qscale);
+          qf[i][1] = quant(v.y, g.qscale);
+          if (!(fabsf(qf[i][0]) < 2147483648.0f) || !(fabsf(qf[i][1]) < 2147483648.0f)) wide = true;
+          const int gxv = x0 + lxs[i], gyv = y0 + lys[i];
           const float2 xl = G[c - 1], xh = G[c + 1], yl = G[c - GW], yh = G[c + GW];
           J[i][0] = diff3(xl.x, v.x, xh.x, gxv, nx);
           J[i][1] = diff3(yl.x, v.x, yh.x, gyv, ny);
@@ -595,13 +644,37 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
           J[i][3] = diff3(yl.y, v.y, yh.y, gyv, ny);
         }
         // exact cofactors of (v0 v1 v2 ; 1 1 1): C_i = (-1)^i det(columns without i)
-        i128 C[3];
-        C[0] = det2x<WIDE>(q[1][0], q[1][1], q[2][0], q[2][1]);
-        C[1] = -det2x<WIDE>(q[0][0], q[0][1], q[2][0], q[2][1]);
-        C[2] = det2x<WIDE>(q[0][0], q[0][1], q[1][0], q[1][1]);
-        const i128 D = C[0] + C[1] + C[2];
+        double Cd[3], Dd;
+        bool degenerate;
+        if (!WIDE) {
+          // |q| < 2^24: every cofactor is an integer below 2^49 and D below 2^51, exact in binary64
+          auto det2d = [](float a0, float a1, float b0, float b1) {
+            const double p = (double)a1 * (double)b0;
+            return __builtin_fma((double)a0, (double)b1, -p);
+          };
+          Cd[0] = det2d(qf[1][0], qf[1][1], qf[2][0], qf[2][1]);
+          Cd[1] = -det2d(qf[0][0], qf[0][1], qf[2][0], qf[2][1]);
+          Cd[2] = det2d(qf[0][0], qf[0][1], qf[1][0], qf[1][1]);
+          Dd = (Cd[0] + Cd[1]) + Cd[2];
+          degenerate = (Dd == 0.0);
+        } else {
+          long long q[3][2];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            q[i][0] = (long long)qf[i][0];
+            q[i][1] = (long long)qf[i][1];
+          }
+          i128 C[3];
+          C[0] = (i128)q[1][0] * q[2][1] - (i128)q[1][1] * q[2][0];
+          C[1] = -((i128)q[0][0] * q[2][1] - (i128)q[0][1] * q[2][0]);
+          C[2] = (i128)q[0][0] * q[1][1] - (i128)q[0][1] * q[1][0];
+          const i128 D = C[0] + C[1] + C[2];
+          degenerate = (D == 0);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) Cd[i] = (double)C[i];
+          Dd = (double)D;
+        }
         unsigned fl = wide ? FL_WIDE : 0u;
-        const bool degenerate = (D == 0);
         if (degenerate) {
           fl |= FL_DEGENERATE;
           ++n_deg;
@@ -613,9 +686,9 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
           if (degenerate) {
             mu32[0] = mu32[1] = mu32[2] = 1.0f / 3.0f;
           } else {
-            const float fD = (float)D;
+            const float fD = (float)Dd;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) mu32[i] = (float)C[i] / fD;
+            for (int i = 0; i < 3; ++i) mu32[i] = (float)Cd[i] / fD;
           }
           type = classify2_fp32(mu32, J, vector);
         }
@@ -623,9 +696,8 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
           if (degenerate) {
             mu64[0] = mu64[1] = mu64[2] = 1.0 / 3.0;
           } else {
-            const double dD = (double)D;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) mu64[i] = (double)C[i] / dD;
+            for (int i = 0; i < 3; ++i) mu64[i] = Cd[i] / Dd;
           }
           type = classify2_fp64(mu64, J, vector);
           if (g.precision == 0) {
@@ -634,35 +706,33 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
           }
         }
         float pos[3], muo[3];
-        // vertex coordinates per component: x, y, t of v0, v1, v2
-        const int cx0 = ax, cx1 = ax + (m1 & 1), cx2 = cx1 + (m2 & 1);
-        const int cy0 = y, cy1 = y + ((m1 >> 1) & 1), cy2 = cy1 + ((m2 >> 1) & 1);
-        const int ct0 = t, ct1 = t + dt[1], ct2 = t + dt[2];
+        const float cx0 = (float)ax, cy0 = (float)y, ct0 = (float)t;
         if (g.precision == 0) {
-          float sx = mu32[0] * (float)cx0;
-          sx = sx + mu32[1] * (float)cx1;
-          sx = sx + mu32[2] * (float)cx2;
-          float sy = mu32[0] * (float)cy0;
-          sy = sy + mu32[1] * (float)cy1;
-          sy = sy + mu32[2] * (float)cy2;
-          float stt = mu32[0] * (float)ct0;
-          stt = stt + mu32[1] * (float)ct1;
-          stt = stt + mu32[2] * (float)ct2;
+          float sx = mu32[0] * cx0;
+          sx = sx + mu32[1] * (cx0 + dx1);
+          sx = sx + mu32[2] * (cx0 + dx2);
+          float sy = mu32[0] * cy0;
+          sy = sy + mu32[1] * (cy0 + dy1);
+          sy = sy + mu32[2] * (cy0 + dy2);
+          float stt = mu32[0] * ct0;
+          stt = stt + mu32[1] * (ct0 + dt1);
+          stt = stt + mu32[2] * (ct0 + dt2);
           pos[0] = sx;
           pos[1] = sy;
           pos[2] = stt;
 #pragma unroll
           for (int i = 0; i < 3; ++i) muo[i] = mu32[i];
         } else {
-          double sx = mu64[0] * (double)cx0;
-          sx = sx + mu64[1] * (double)cx1;
-          sx = sx + mu64[2] * (double)cx2;
-          double sy = mu64[0] * (double)cy0;
-          sy = sy + mu64[1] * (double)cy1;
-          sy = sy + mu64[2] * (double)cy2;
-          double stt = mu64[0] * (double)ct0;
-          stt = stt + mu64[1] * (double)ct1;
-          stt = stt + mu64[2] * (double)ct2;
+          const double X = ax, Y = y, T = t;
+          double sx = mu64[0] * X;
+          sx = sx + mu64[1] * (X + dx1);
+          sx = sx + mu64[2] * (X + dx2);
+          double sy = mu64[0] * Y;
+          sy = sy + mu64[1] * (Y + dy1);
+          sy = sy + mu64[2] * (Y + dy2);
+          double stt = mu64[0] * T;
+          stt = stt + mu64[1] * (T + dt1);
+          stt = stt + mu64[2] * (T + dt2);
           pos[0] = (float)sx;
           pos[1] = (float)sy;
           pos[2] = (float)stt;
@@ -684,39 +754,37 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
         if (o.type) o.type[idx] = (uint8_t)type;
         if (o.flags) o.flags[idx] = (uint8_t)fl;
 
-        // ---- pass 2 links: the (at most two) tetrahedra holding this triangle.  A tetrahedron with chain
-        // (c1, c2, c3) anchored at c has sides: drop w0 -> (c + e_c1; c2, c3), drop w1 -> (c; c1|c2, c3),
-        // drop w2 -> (c; c1, c2|c3), drop w3 -> (c; c1, c2).  Each link is recorded by its larger endpoint:
-        // inside this tile and chunk it goes to the LDS union-find, otherwise to the global edge list.
+        // ---- pass 2 links: each of the (at most two) tetrahedra holding this triangle has exactly one other
+        // punctured side.  Each link is recorded by its larger endpoint: inside this tile and chunk it goes to the
+        // LDS union-find, otherwise to the global edge list.
         unsigned sm0 = 0, sm1 = 0;
         int sl0 = -1, sl1 = -1;
         int ns = 0;
-        auto visit_cell = [&](bool at_minus, int c1, int c2, int c3) {
-          const int bslot = at_minus ? (c1 == 1 ? NB_MX : (c1 == 2 ? NB_MY : NB_MT)) : NB_SELF;
-          const int fslot = at_minus ? NB_SELF : (c1 == 1 ? NB_PX : (c1 == 2 ? NB_PY : NB_PT));
-          const int bm = nbm[wave][bslot][L], fm = nbm[wave][fslot][L];
-          const unsigned bo = nbo[wave][bslot][L], fo = nbo[wave][fslot][L];
-          int found = 0, oslot = -1;
-          unsigned other = 0xFFFFFFFFu;
+        const int P3[3] = {ax, y, t};
+        const int N3[3] = {nx, ny, nt};
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int tsv = s == 0 ? kTri2Index.idx[c2][c3]
-                                   : (s == 1 ? kTri2Index.idx[c1 | c2][c3]
-                                             : (s == 2 ? kTri2Index.idx[c1][c2 | c3] : kTri2Index.idx[c1][c2]));
-            const int um = s == 0 ? fm : bm;
-            const unsigned uo = s == 0 ? fo : bo;
-            if ((um >> tsv) & 1) {
-              const unsigned hi = uo + __popc((unsigned)um & ((1u << tsv) - 1u));
+        for (int k = 0; k < 2; ++k) {
+          const unsigned w = s_cof[ty][k];
+          const int rule = w & 3, axis = (w >> 2) & 3;
+          const int pa = axis == 0 ? P3[0] : (axis == 1 ? P3[1] : P3[2]);
+          const int Na = axis == 0 ? N3[0] : (axis == 1 ? N3[1] : N3[2]);
+          if ((rule == 2 && pa < 1) || (rule == 3 && pa + 1 > Na - 1)) continue;  // the cell leaves the grid
+          int found = 0, oslot = -1;
+          unsigned other = 0;
+#pragma unroll
+          for (int sdx = 0; sdx < 3; ++sdx) {
+            const unsigned f = (w >> (4 + 7 * sdx)) & 127u;
+            const int slot = f & 7, tt = f >> 3;
+            const unsigned um = nbm[wave][slot][L];
+            if ((um >> tt) & 1u) {
               ++found;
-              if (hi != idx) {
-                other = hi;
-                oslot = s == 0 ? fslot : bslot;
-              }
+              other = nbo[wave][slot][L] + __popc(um & ((1u << tt) - 1u));
+              oslot = slot;
             }
           }
-          if (found != 2 || other == 0xFFFFFFFFu) {
+          if (found != 1) {
             st |= ST_INVARIANT;
-            return;
+            continue;
           }
           if (other < idx) {
             if (ns == 0) {
@@ -728,22 +796,6 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
             }
             ++ns;
           }
-        };
-        const int b = m1 | m2;
-        if (__popc((unsigned)m1) == 1 && __popc((unsigned)m2) == 1) {
-          const int a = 7 & ~b;  // missing axis
-          const int pa = a == 1 ? ax : (a == 2 ? y : t);
-          const int Na = a == 1 ? nx : (a == 2 ? ny : nt);
-          if (pa >= 1) visit_cell(true, a, m1, m2);
-          if (pa + 1 <= Na - 1) visit_cell(false, m1, m2, a);
-        } else if (__popc((unsigned)m1) == 2) {
-          const int lo = m1 & -m1, hi = m1 - lo;
-          visit_cell(false, lo, hi, m2);
-          visit_cell(false, hi, lo, m2);
-        } else {
-          const int lo = m2 & -m2, hi = m2 - lo;
-          visit_cell(false, m1, lo, hi);
-          visit_cell(false, m1, hi, lo);
         }
         n_linked += ns;
         bool g0 = false, g1 = false;

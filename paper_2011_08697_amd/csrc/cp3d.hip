@@ -48,7 +48,7 @@ template <bool WIDE>
 struct Q3;
 template <>
 struct Q3<false> {
-  typedef int T;
+  typedef float T;  // integers below 2^20, exact in binary32
 };
 template <>
 struct Q3<true> {
@@ -60,9 +60,9 @@ __device__ __forceinline__ typename Q3<WIDE>::T to_q3(float r, unsigned& st) {
   if (!WIDE) {
     if (!(fabsf(r) < 1048576.0f)) {  // 2^20: every 3x3 determinant fits in 64 bits
       st |= ST_WIDE;
-      return 0;
+      return 0.0f;
     }
-    return (int)r;
+    return r;
   } else {
     if (!(fabsf(r) < 2199023255552.0f)) {  // 2^41: every 3x3 determinant fits in 128 bits
       st |= ST_RANGE;
@@ -131,6 +131,42 @@ __device__ __forceinline__ unsigned sos3_positive(const Q* a, const Q* b, const 
   return sos3_tail(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2]);
 }
 
+// Exact 64-bit evaluation (narrow entries below 2^20: minors below 2^41, terms below 2^61), then SoS.
+__device__ __noinline__ unsigned sos3_exact_narrow(float a0, float a1, float a2, float b0, float b1, float b2,
+                                                   float c0, float c1, float c2) {
+  const long long A0 = (long long)a0, A1 = (long long)a1, A2 = (long long)a2;
+  const long long B0 = (long long)b0, B1 = (long long)b1, B2 = (long long)b2;
+  const long long C0 = (long long)c0, C1 = (long long)c1, C2 = (long long)c2;
+  const long long m0 = B1 * C2 - B2 * C1, m1 = B0 * C2 - B2 * C0, m2 = B0 * C1 - B1 * C0;
+  const long long d = A0 * m0 - A1 * m1 + A2 * m2;
+  if (d != 0) return d > 0;
+  return sos3_tail(A0, A1, A2, B0, B1, B2, C0, C1, C2);
+}
+
+// Narrow sign of det(a, b, c): the 2x2 minors are exact in binary64 (integers below 2^41); the three products and
+// two sums carry at most 3u (sum |p_i|) of rounding error (u = 2^-53), so |s| > 4e-16 sum |p_i| fixes the sign;
+// otherwise (including every vanishing determinant) the exact integer evaluation and SoS decide.
+__device__ __forceinline__ unsigned sos3_positive_narrow(float fa0, float fa1, float fa2, float fb0, float fb1,
+                                                         float fb2, float fc0, float fc1, float fc2) {
+  const double b0 = fb0, b1 = fb1, b2 = fb2, c0 = fc0, c1 = fc1, c2 = fc2;
+  const double m0 = __builtin_fma(b1, c2, -(b2 * c1));
+  const double m1 = __builtin_fma(b0, c2, -(b2 * c0));
+  const double m2 = __builtin_fma(b0, c1, -(b1 * c0));
+  const double p0 = (double)fa0 * m0, p1 = (double)fa1 * m1, p2 = (double)fa2 * m2;
+  const double sdet = (p0 - p1) + p2;
+  const double bound = ((fabs(p0) + fabs(p1)) + fabs(p2)) * 4e-16;
+  if (fabs(sdet) > bound) return sdet > 0.0;
+  return sos3_exact_narrow(fa0, fa1, fa2, fb0, fb1, fb2, fc0, fc1, fc2);
+}
+
+template <bool WIDE, typename Q>
+__device__ __forceinline__ unsigned tri_sign(const Q* a, const Q* b, const Q* c) {
+  if constexpr (!WIDE)
+    return sos3_positive_narrow(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2]);
+  else
+    return sos3_positive<true, Q>(a, b, c);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -147,8 +183,18 @@ __global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64
   __shared__ float fs[FN];
   __shared__ Q qs[2][3][QN];
   __shared__ unsigned long long tw[2][WN];
+  __shared__ unsigned s_tri[50];
+  __shared__ int s_cdelta[16];
 
   const int tid = threadIdx.x;
+  if (tid < 50) {
+    const int k = tid;
+    const int ti = k < 12 ? kTriSplit.ord[k] : kTriSplit.itv[k - 12];
+    const int ca = kTri3.m[ti][0], cb = ca | kTri3.m[ti][1];
+    s_tri[k] = (unsigned)ti | ((unsigned)ca << 8) | ((unsigned)cb << 12);
+  }
+  if (tid < 16) s_cdelta[tid] = (((tid >> 2) & 1) * QY + ((tid >> 1) & 1)) * QX + (tid & 1);
+  __syncthreads();
   const int nx = g.nx, ny = g.ny, nz = g.nz, nt = g.nt;
   const int x0 = blockIdx.x * TX3;
   const int by = blockIdx.y % nyt, bz = blockIdx.y / nyt;
@@ -189,48 +235,36 @@ __global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64
       qs[par][2][e] = q2;
     }
   };
-  // q of the 16 corners of the unit 4-cube at word-anchor (lx, ly, lz): corner mask bit 0 x, 1 y, 2 z, 3 t
-  auto corner = [&](int par, int wx, int wy, int wz, int cm, Q* out) {
-    const int p = (cm >> 3) ? (par ^ 1) : par;
-    const int e = ((wz + ((cm >> 2) & 1)) * QY + (wy + ((cm >> 1) & 1))) * QX + (wx + (cm & 1));
-    out[0] = qs[p][0][e];
-    out[1] = qs[p][1][e];
-    out[2] = qs[p][2][e];
-  };
-  // ordinal triangle bits of plane par (anchors of the word region) -> tw[par] (assignment)
-  auto ordinal_tris = [&](int par) {
+  // Triangle sign words.  Triangle type ti = (M1, M2) anchored at p has vertices at the unit 4-cube corners
+  // 0, a = M1, b = M1|M2 (corner bit 0 x, 1 y, 2 z, 3 t; a corner with the t bit lies in the next plane).
+  // s_tri[k] = ti | a << 8 | b << 12, ordinal types first (k < 12), then interval ones.
+  auto tris = [&](int par, int kbeg, int kend, bool assign) {
+    const Q* q0p = qs[par][0];
     for (int e = tid; e < WN; e += 256) {
-      int wx = e % WX, r = e / WX, wy = r % WY, wz = r / WY;
-      Q c[8][3];
-#pragma unroll
-      for (int cm = 0; cm < 8; ++cm) corner(par, wx, wy, wz, cm, c[cm]);
+      const int wx = e % WX, r = e / WX, wy = r % WY, wz = r / WY;
+      const int base = (wz * QY + wy) * QX + wx;
+      const Q a0 = qs[par][0][base], a1 = qs[par][1][base], a2 = qs[par][2][base];
       unsigned long long w = 0;
-#pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        const int ti = kTriSplit.ord[k];
-        const int a = kTri3.m[ti][0], b = a | kTri3.m[ti][1];
-        w |= (unsigned long long)sos3_positive<WIDE, Q>(c[0], c[a], c[b]) << ti;
+#pragma unroll 2
+      for (int k = kbeg; k < kend; ++k) {
+        const unsigned tk = s_tri[k];
+        const int ti = tk & 63, ca = (tk >> 8) & 15, cb = (tk >> 12) & 15;
+        const int ia = base + s_cdelta[ca], ib = base + s_cdelta[cb];
+        const int pa = (ca >> 3) ? (par ^ 1) : par, pb = (cb >> 3) ? (par ^ 1) : par;
+        const Q qa[3] = {qs[pa][0][ia], qs[pa][1][ia], qs[pa][2][ia]};
+        const Q qb[3] = {qs[pb][0][ib], qs[pb][1][ib], qs[pb][2][ib]};
+        const Q q0[3] = {a0, a1, a2};
+        w |= (unsigned long long)tri_sign<WIDE, Q>(q0, qa, qb) << ti;
       }
-      tw[par][e] = w;
+      if (assign)
+        tw[par][e] = w;
+      else
+        tw[par][e] |= w;
     }
+    (void)q0p;
   };
-  // interval triangle bits of plane par (to par^1) -> OR into tw[par]
-  auto interval_tris = [&](int par) {
-    for (int e = tid; e < WN; e += 256) {
-      int wx = e % WX, r = e / WX, wy = r % WY, wz = r / WY;
-      Q c[16][3];
-#pragma unroll
-      for (int cm = 0; cm < 16; ++cm) corner(par, wx, wy, wz, cm, c[cm]);
-      unsigned long long w = 0;
-#pragma unroll
-      for (int k = 0; k < 38; ++k) {
-        const int ti = kTriSplit.itv[k];
-        const int a = kTri3.m[ti][0], b = a | kTri3.m[ti][1];
-        w |= (unsigned long long)sos3_positive<WIDE, Q>(c[0], c[a], c[b]) << ti;
-      }
-      tw[par][e] |= w;
-    }
-  };
+  auto ordinal_tris = [&](int par) { tris(par, 0, 12, true); };
+  auto interval_tris = [&](int par) { tris(par, 12, 50, false); };
 
   load_plane(t0);
   __syncthreads();

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void uf_label(unsigned* __restrict__ parent, c
   __shared__ unsigned long long red[4];
   unsigned long long roots = 0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    unsigned r = uf_find(parent, (unsigned)i);
+    unsigned r = uf_find_plain(parent, (unsigned)i);
     if (label) label[i] = face_id[r];
     roots += (r == (unsigned)i);
   }

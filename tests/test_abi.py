@@ -34,7 +34,7 @@ def test_version_and_defaults():
     assert b"gfx950" in L.ftk_version()
     o = F.Options()
     L.ftk_default_options(ctypes.byref(o))
-    assert o.quant_log2 == 20 and o.precision == 0 and o.outputs == 31
+    assert o.quant_log2 == 20 and o.precision == 0 and o.outputs == 29
 
 
 @pytest.mark.parametrize("n,dims", [(2, (64, 64, 10)), (2, (1024, 1024, 100)), (2, (4096, 4096, 50)),

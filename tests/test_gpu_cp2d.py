@@ -144,3 +144,10 @@ def test_full_size_c1_sampled():
         r = O.trace(f, int(fid[i]), max_steps=200000)
         assert r["closed"] != -1
         assert r["min_face"] == g["label"][i]
+
+
+def test_all_outputs_with_mu():
+    f = synth.moving_gaussians_2d(150, 90, 7, 9, seed=12, noise_std=1e-3)
+    g = run(f, outputs=F.OUT_ALL)
+    assert g["mu"] is not None
+    assert_full_parity(g, O.track(f))
