@@ -115,9 +115,9 @@ def main():
     L = F.lib()
     stream = torch.cuda.current_stream(dev)
     sh = ctypes.c_void_p(stream.cuda_stream)
-    opt = F.Options()
-    L.ftk_default_options(ctypes.byref(opt))
-    opt.profile = 1
+    # outputs come from torch's caching allocator through the library's allocator hooks (as for any torch user)
+    pool = F._TorchPool(dev)
+    opt = F._options(pool, profile=1)
 
     def one_step():
         r = F.Result()
@@ -131,7 +131,7 @@ def main():
             raise F.FtkError(st, F.last_error())
         out = (int(r.n_hits), int(r.n_trajectories), int(r.stats.simplices_tested),
                r.stats.t_detect_ms, r.stats.t_scan_ms, r.stats.t_emit_ms, r.stats.t_link_ms)
-        L.ftk_result_free(ctypes.byref(r), ctypes.byref(opt), sh)
+        L.ftk_result_free(ctypes.byref(r), ctypes.byref(opt), sh)  # returns the output tensors to torch's cache
         return out
 
     for _ in range(args.warmup):

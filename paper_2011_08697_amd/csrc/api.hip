@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/ftk.h"
 #include "common.h"
@@ -49,20 +51,88 @@ struct Alloc {
   }
 };
 
-// Scratch list released on scope exit.
+// Scratch memory: a small cache of device blocks reused across calls (stream-ordered allocation costs tens of
+// microseconds per call on this runtime).  A block is handed back only after the call has synchronised its
+// stream, so no kernel can still be using it.
+struct CachedBlock {
+  void* p;
+  size_t size;
+  int dev;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+
+void* cache_get(size_t bytes, size_t* got) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  bytes = (bytes + 4095) & ~size_t(4095);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_cache.size(); ++i) {
+      const CachedBlock& b = g_cache[i];
+      if (b.dev == dev && b.size >= bytes && b.size <= 2 * bytes + (64u << 20) &&
+          (best < 0 || b.size < g_cache[best].size))
+        best = i;
+    }
+    if (best >= 0) {
+      CachedBlock b = g_cache[best];
+      g_cache.erase(g_cache.begin() + best);
+      *got = b.size;
+      return b.p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    // release cached blocks of this device and retry once
+    std::vector<CachedBlock> drop;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      for (auto it = g_cache.begin(); it != g_cache.end();)
+        if (it->dev == dev) {
+          drop.push_back(*it);
+          it = g_cache.erase(it);
+        } else {
+          ++it;
+        }
+    }
+    for (auto& b : drop) (void)hipFree(b.p);
+    p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  }
+  *got = bytes;
+  return p;
+}
+
+void cache_put(void* p, size_t size) {
+  if (!p) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.push_back(CachedBlock{p, size, dev});
+}
+
+// Scratch list released (to the cache) on scope exit.  Callers synchronise their stream before returning.
 struct Scratch {
   const Alloc& al;
   void* p[16];
+  size_t sz[16];
   int n = 0;
   explicit Scratch(const Alloc& a) : al(a) {}
   template <typename T>
   T* get(size_t count) {
-    void* q = al.get(count * sizeof(T));
-    if (q) p[n++] = q;
+    size_t got = 0;
+    void* q = cache_get(count * sizeof(T) + 16, &got);
+    if (q) {
+      p[n] = q;
+      sz[n] = got;
+      ++n;
+    }
     return (T*)q;
   }
   ~Scratch() {
-    for (int i = n - 1; i >= 0; --i) al.put(p[i]);
+    if (n > 0) (void)hipStreamSynchronize(al.s);  // no-op on the normal path (already synchronised)
+    for (int i = n - 1; i >= 0; --i) cache_put(p[i], sz[i]);
   }
 };
 
@@ -256,6 +326,10 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
   g.nxt = (int)((nx + 63) / 64);
   g.qscale = std::ldexp(1.0f, o.quant_log2);
   g.precision = o.precision;
+  g.t_begin = 0;
+  g.t_end = (int)nt;
+  g.f_ring = 0;
+  g.m_ring = 0;
   const long long V = (long long)nx * ny * nt;
   const long long nseg = (long long)nt * ny * g.nxt;
 
@@ -321,6 +395,8 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
     return fail(FTK_ERR_OOM, "output allocation failed (%lld hits)", nh);
   }
   Out2 od;
+  od.gbase = 0;
+  od.label = (long long*)r.label;
   od.face_id = (long long*)r.face_id;
   od.pos = r.pos;
   od.mu = r.mu;
@@ -485,6 +561,531 @@ ftk_status track3d_impl(const float* field, int64_t nx, int64_t ny, int64_t nz, 
   return FTK_OK;
 }
 
+// ---------------------------------------------------------------------------------------------------------------
+// 2D batched: all series in one persistent launch per stage, concatenated scratch, one global union-find.
+// ---------------------------------------------------------------------------------------------------------------
+__global__ void gather_bases(const long long* __restrict__ seg_off, const long long* __restrict__ seg_start, int nser,
+                             const long long* __restrict__ total, long long* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nser) out[i] = seg_off[seg_start[i]];
+  if (i == nser) out[i] = *total;
+}
+
+ftk_status track2d_batched_impl(int nser, const float* const* fields, const int64_t* nx, const int64_t* ny,
+                                const int64_t* nt, ftk_field_kind kind, const ftk_options& o, hipStream_t s,
+                                ftk_cp_result* outs) {
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
+  constexpr int TYD = 16, TYE = 8;
+  const int ttd = o.slab_depth ? o.slab_depth : 16;
+  std::vector<Series2> ser(nser);
+  std::vector<long long> mask_off(nser), seg_start(nser);
+  std::vector<int> pre_d(nser + 1), pre_e(nser + 1);
+  long long Vtot = 0, Stot = 0;
+  pre_d[0] = pre_e[0] = 0;
+  for (int i = 0; i < nser; ++i) {
+    Grid2& g = ser[i].g;
+    g.f = fields[i];
+    g.kind = (int)kind;
+    g.nx = (int)nx[i];
+    g.ny = (int)ny[i];
+    g.nt = (int)nt[i];
+    g.nxt = (int)((nx[i] + 63) / 64);
+    g.qscale = std::ldexp(1.0f, o.quant_log2);
+    g.precision = o.precision;
+    g.t_begin = 0;
+    g.t_end = g.nt;
+    g.f_ring = 0;
+    g.m_ring = 0;
+    mask_off[i] = Vtot;
+    seg_start[i] = Stot;
+    Vtot += (long long)nx[i] * ny[i] * nt[i];
+    Stot += (long long)nt[i] * ny[i] * g.nxt;
+    const int tt = ttd < g.nt ? ttd : g.nt;
+    pre_d[i + 1] = pre_d[i] + g.nxt * (int)((g.ny + TYD - 1) / TYD) * (int)((g.nt + tt - 1) / tt);
+    pre_e[i + 1] = pre_e[i] + g.nxt * (int)((g.ny + TYE - 1) / TYE) * (int)((g.nt + 16 - 1) / 16);
+  }
+  uint16_t* masks = sc.get<uint16_t>((size_t)Vtot);
+  int* seg_cnt = sc.get<int>((size_t)Stot);
+  long long* seg_off = sc.get<long long>((size_t)Stot);
+  long long* scan_tmp = sc.get<long long>(scan_tmp_elems(Stot));
+  Ctl* dctl = sc.get<Ctl>(1);
+  Series2* dser = sc.get<Series2>((size_t)nser);
+  int* dpre = sc.get<int>((size_t)(2 * nser + 4));
+  long long* dseg_start = sc.get<long long>((size_t)nser);
+  long long* dbases = sc.get<long long>((size_t)nser + 1);
+  unsigned long long* dcnt = sc.get<unsigned long long>((size_t)nser * CNT_N);
+  int* dctr = sc.get<int>(4);
+  if (!masks || !seg_cnt || !seg_off || !scan_tmp || !dctl || !dser || !dpre || !dseg_start || !dbases || !dcnt ||
+      !dctr)
+    return fail(FTK_ERR_OOM, "scratch allocation failed");
+  for (int i = 0; i < nser; ++i) {
+    ser[i].masks = masks + mask_off[i];
+    ser[i].seg_cnt = seg_cnt + seg_start[i];
+    ser[i].seg_off = seg_off + seg_start[i];
+    ser[i].cnt = dcnt + (size_t)i * CNT_N;
+    ser[i].wide = 0;
+    std::memset(&ser[i].o, 0, sizeof(Out2));
+  }
+  HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+  HIP_TRY(hipMemsetAsync(dcnt, 0, sizeof(unsigned long long) * CNT_N * nser, s));
+  HIP_TRY(hipMemsetAsync(dctr, 0, sizeof(int) * 4, s));
+  HIP_TRY(hipMemcpyAsync(dser, ser.data(), sizeof(Series2) * nser, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dpre, pre_d.data(), sizeof(int) * (nser + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dpre + nser + 1, pre_e.data(), sizeof(int) * (nser + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dseg_start, seg_start.data(), sizeof(long long) * nser, hipMemcpyHostToDevice, s));
+  Phases ph;
+  ph.init(o.profile != 0, s);
+  bool wide = false;
+  Ctl h;
+  std::vector<long long> bases(nser + 1);
+  for (int pass = 0; pass < 2; ++pass) {
+    ph.mark(0);
+    HIP_TRY(launch_detect2d_batched(dser, dpre, nser, pre_d[nser], ttd, wide, dctr, &dctl->status, s));
+    ph.mark(1);
+    HIP_TRY(launch_scan(seg_cnt, seg_off, Stot, &dctl->total, scan_tmp, s));
+    gather_bases<<<(nser + 256) / 256, 256, 0, s>>>(seg_off, dseg_start, nser, &dctl->total, dbases);
+    HIP_TRY(hipGetLastError());
+    ph.mark(2);
+    HIP_TRY(hipMemcpyAsync(bases.data(), dbases, sizeof(long long) * (nser + 1), hipMemcpyDeviceToHost, s));
+    ftk_status st = read_ctl(&h, dctl, s);
+    if (st) return st;
+    if (h.status & ST_NONFINITE) return decode_status(h.status);
+    if (!(h.status & ST_WIDE) || wide) break;
+    wide = true;
+    HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+    HIP_TRY(hipMemsetAsync(dctr, 0, sizeof(int) * 4, s));
+  }
+  ftk_status st = decode_status(h.status);
+  if (st) return st;
+  const long long total = h.total;
+  if (total > 0xFFFFFFFELL) return fail(FTK_ERR_CAPACITY, "%lld punctured simplices in the batch exceed 2^32 - 2", total);
+  unsigned* parent = sc.get<unsigned>((size_t)total);
+  uint2* work = sc.get<uint2>((size_t)total * 2);
+  unsigned* dgb = sc.get<unsigned>((size_t)nser + 1);
+  if (!parent || !work || !dgb) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  std::vector<unsigned> gb(nser + 1);
+  const unsigned outs_mask = o.outputs;
+  bool oom = false;
+  for (int i = 0; i < nser; ++i) {
+    const long long nh = bases[i + 1] - bases[i];
+    gb[i] = (unsigned)bases[i];
+    ftk_cp_result& r = outs[i];
+    std::memset(&r, 0, sizeof(r));
+    r.n = 2;
+    r.n_hits = nh;
+    r.face_id = (int64_t*)al.get(sizeof(int64_t) * nh);
+    if (outs_mask & FTK_OUT_POS) r.pos = (float*)al.get(sizeof(float) * 3 * nh);
+    if (outs_mask & FTK_OUT_MU) r.mu = (float*)al.get(sizeof(float) * 3 * nh);
+    if (outs_mask & FTK_OUT_TYPE) r.type = (uint8_t*)al.get(nh);
+    if (outs_mask & FTK_OUT_FLAGS) r.flags = (uint8_t*)al.get(nh);
+    if (outs_mask & FTK_OUT_LABEL) r.label = (int64_t*)al.get(sizeof(int64_t) * nh);
+    oom = oom || !r.face_id || ((outs_mask & FTK_OUT_POS) && !r.pos) || ((outs_mask & FTK_OUT_MU) && !r.mu) ||
+          ((outs_mask & FTK_OUT_TYPE) && !r.type) || ((outs_mask & FTK_OUT_FLAGS) && !r.flags) ||
+          ((outs_mask & FTK_OUT_LABEL) && !r.label);
+    Out2& od = ser[i].o;
+    od.gbase = (unsigned)bases[i];
+    od.face_id = (long long*)r.face_id;
+    od.pos = r.pos;
+    od.mu = r.mu;
+    od.type = r.type;
+    od.flags = r.flags;
+    od.label = (long long*)r.label;
+    od.parent = parent;
+    od.work = work;
+    ser[i].wide = wide ? 1 : 0;
+  }
+  gb[nser] = (unsigned)total;
+  auto free_all = [&]() {
+    for (int i = 0; i < nser; ++i) ftk_result_free(&outs[i], &o, (ftk_stream_t)s);
+  };
+  if (oom) {
+    free_all();
+    return fail(FTK_ERR_OOM, "output allocation failed");
+  }
+  HIP_TRY(hipMemcpyAsync(dser, ser.data(), sizeof(Series2) * nser, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dgb, gb.data(), sizeof(unsigned) * (nser + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(dctr, 0, sizeof(int) * 4, s));
+  ph.mark(3);
+  hipError_t he = hipSuccess;
+  if (total > 0) {
+    he = launch_emit2d_batched(dser, dpre + nser + 1, nser, pre_e[nser], dctr, &dctl->status, &dctl->cnt[CNT_WORK],
+                               s);
+    ph.mark(4);
+    if (he == hipSuccess) he = launch_uf_hook(parent, work, &dctl->cnt[CNT_WORK], 2 * total, s);
+    if (he == hipSuccess) he = launch_uf_label_batched(parent, dser, dgb, nser, total, s);
+  } else {
+    ph.mark(4);
+  }
+  ph.mark(5);
+  if (he != hipSuccess) {
+    free_all();
+    return fail(FTK_ERR_HIP, "kernel launch: %s", hipGetErrorString(he));
+  }
+  std::vector<unsigned long long> hc((size_t)nser * CNT_N);
+  HIP_TRY(hipMemcpyAsync(hc.data(), dcnt, sizeof(unsigned long long) * CNT_N * nser, hipMemcpyDeviceToHost, s));
+  st = read_ctl(&h, dctl, s);
+  if (!st) st = decode_status(h.status);
+  if (st) {
+    free_all();
+    return st;
+  }
+  for (int i = 0; i < nser; ++i) {
+    ftk_cp_result& r = outs[i];
+    const unsigned long long* c = &hc[(size_t)i * CNT_N];
+    r.n_trajectories = (long long)c[CNT_TRAJ];
+    int64_t dims[3] = {nx[i], ny[i], nt[i]};
+    r.stats.simplices_tested = count_tested(2, dims);
+    r.stats.cells_linked = (long long)c[CNT_LINKED];
+    r.stats.fp64_fallbacks = (long long)c[CNT_FP64];
+    r.stats.degenerate_sublocations = (long long)c[CNT_DEGEN];
+    r.stats.wide_path = wide ? 1 : 0;
+    if (i == 0) {
+      r.stats.t_detect_ms = ph.ms(0, 1);
+      r.stats.t_scan_ms = ph.ms(1, 2);
+      r.stats.t_emit_ms = ph.ms(3, 4);
+      r.stats.t_link_ms = ph.ms(4, 5);
+    }
+  }
+  return FTK_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// Streaming (Sec. 3.1 "Ordinal and interval mesh elements": every simplex is visited with a sliding window of two
+// time steps).  2D: the tracker keeps the last three steps in a ring; pushing step s detects the anchors of step
+// s-1 (its ordinal simplices and the interval ones towards s) and emits step s-2, whose +t neighbour masks now
+// exist.  finish() closes the series and runs the global union-find passes.  3D: the steps are accumulated on the
+// device and the one-shot path runs at finish().
+// ---------------------------------------------------------------------------------------------------------------
+__global__ void add_plane_base(long long* __restrict__ off, long long n, const long long* __restrict__ running) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) off[i] += *running;
+}
+__global__ void bump_running(long long* running, const long long* plane_total) { *running += *plane_total; }
+
+}  // namespace ftk
+
+struct ftk_tracker {
+  int n = 2;
+  int64_t nx = 0, ny = 0, nz = 1;
+  ftk_field_kind kind = FTK_SCALAR;
+  ftk_options o{};
+  hipStream_t s = nullptr;
+  int steps = 0;
+  int state = 0;  // 0 open, 1 finished, 2 failed
+  size_t step_elems = 0;
+  // 2D window
+  float* fring = nullptr;
+  uint16_t* mring = nullptr;
+  int* cring = nullptr;
+  long long* oring = nullptr;
+  long long* scan_tmp = nullptr;
+  void* dctl = nullptr;
+  long long* dplane = nullptr;
+  long long nseg_plane = 0;
+  int plane_wide[3] = {0, 0, 0};
+  std::vector<long long> total_after;  // hits through step p
+  long long emitted = 0;               // hits of the emitted steps
+  // outputs and union-find scratch (grown on demand)
+  long long cap = 0;
+  long long* face_id = nullptr;
+  float* pos = nullptr;
+  float* mu = nullptr;
+  uint8_t* type = nullptr;
+  uint8_t* flags = nullptr;
+  unsigned* parent = nullptr;
+  uint2* work = nullptr;
+  // 3D accumulation
+  float* all = nullptr;
+  size_t all_cap_steps = 0;
+};
+
+namespace ftk {
+
+static Alloc tracker_alloc(ftk_tracker* h) { return make_alloc(h->o, h->s); }
+
+static void tracker_free_all(ftk_tracker* h) {
+  const Alloc al = tracker_alloc(h);
+  (void)hipStreamSynchronize(h->s);
+  void* ps[] = {h->fring, h->mring, h->cring, h->oring, h->scan_tmp, h->dctl, h->dplane, h->face_id, h->pos,
+                h->mu, h->type, h->flags, h->parent, h->work, h->all};
+  for (void* p : ps) al.put(p);
+  h->fring = nullptr;
+  h->mring = nullptr;
+  h->cring = nullptr;
+  h->oring = nullptr;
+  h->scan_tmp = nullptr;
+  h->dctl = nullptr;
+  h->dplane = nullptr;
+  h->face_id = nullptr;
+  h->pos = h->mu = nullptr;
+  h->type = h->flags = nullptr;
+  h->parent = nullptr;
+  h->work = nullptr;
+  h->all = nullptr;
+}
+
+// Grow the output and union-find arrays to hold `need` hits, keeping the first `keep` entries.
+static ftk_status tracker_reserve(ftk_tracker* h, long long need, long long keep) {
+  if (need <= h->cap) return FTK_OK;
+  const Alloc al = tracker_alloc(h);
+  long long nc = h->cap ? h->cap : 1024;
+  while (nc < need) nc = nc + nc / 2 + 1024;
+  const unsigned outs = h->o.outputs;
+  auto grow = [&](void** p, size_t elem, bool want) -> bool {
+    if (!want) return true;
+    void* q = al.get(elem * (size_t)nc);
+    if (!q) return false;
+    if (*p && keep > 0 && hipMemcpyAsync(q, *p, elem * (size_t)keep, hipMemcpyDeviceToDevice, h->s) != hipSuccess)
+      return false;
+    al.put(*p);
+    *p = q;
+    return true;
+  };
+  bool ok = grow((void**)&h->face_id, 8, true) && grow((void**)&h->pos, 12, (outs & FTK_OUT_POS) != 0) &&
+            grow((void**)&h->mu, 12, (outs & FTK_OUT_MU) != 0) && grow((void**)&h->type, 1, (outs & FTK_OUT_TYPE) != 0) &&
+            grow((void**)&h->flags, 1, (outs & FTK_OUT_FLAGS) != 0) && grow((void**)&h->parent, 4, true);
+  if (ok) {
+    // the edge list is rebuilt from the device counter, keep all of it
+    void* q = al.get(sizeof(uint2) * 2 * (size_t)nc);
+    if (!q) {
+      ok = false;
+    } else {
+      if (h->work && hipMemcpyAsync(q, h->work, sizeof(uint2) * 2 * (size_t)h->cap, hipMemcpyDeviceToDevice, h->s) !=
+                         hipSuccess)
+        ok = false;
+      al.put(h->work);
+      h->work = (uint2*)q;
+    }
+  }
+  if (!ok) return fail(FTK_ERR_OOM, "streaming output allocation failed (%lld hits)", need);
+  h->cap = nc;
+  return FTK_OK;
+}
+
+static Grid2 tracker_grid(ftk_tracker* h, int t_begin, int nt) {
+  Grid2 g;
+  g.f = h->fring;
+  g.kind = (int)h->kind;
+  g.nx = (int)h->nx;
+  g.ny = (int)h->ny;
+  g.nt = nt;
+  g.nxt = (int)((h->nx + 63) / 64);
+  g.qscale = std::ldexp(1.0f, h->o.quant_log2);
+  g.precision = h->o.precision;
+  g.t_begin = t_begin;
+  g.t_end = t_begin + 1;
+  g.f_ring = 3;
+  g.m_ring = 3;
+  return g;
+}
+
+constexpr int kOpenNt = 1 << 29;  // "series still open": no step is the last one
+
+// Detection + offsets of step p (anchors at p), nt = kOpenNt while open.
+static ftk_status tracker_detect(ftk_tracker* h, int p, int nt) {
+  Ctl* dctl = (Ctl*)h->dctl;
+  Grid2 g = tracker_grid(h, p, nt);
+  const int slot = p % 3;
+  int* cnt = h->cring + (size_t)slot * h->nseg_plane;
+  long long* off = h->oring + (size_t)slot * h->nseg_plane;
+  int ty = h->o.tile_y ? h->o.tile_y : 16;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool wide = pass == 1;
+    HIP_TRY(hipMemsetAsync(&dctl->status, 0, sizeof(unsigned), h->s));
+    HIP_TRY(launch_detect2d(g, ty, 1, wide, h->mring, h->cring, &dctl->status, h->s));
+    unsigned st = 0;
+    HIP_TRY(hipMemcpyAsync(&st, &dctl->status, sizeof(unsigned), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipStreamSynchronize(h->s));
+    if (st & ST_NONFINITE) return decode_status(st);
+    if (st & ST_RANGE) return decode_status(st);
+    if (!(st & ST_WIDE)) {
+      h->plane_wide[slot] = wide ? 1 : 0;
+      break;
+    }
+  }
+  HIP_TRY(launch_scan(cnt, off, h->nseg_plane, h->dplane, h->scan_tmp, h->s));
+  add_plane_base<<<(unsigned)((h->nseg_plane + 255) / 256), 256, 0, h->s>>>(off, h->nseg_plane, &dctl->total);
+  bump_running<<<1, 1, 0, h->s>>>(&dctl->total, h->dplane);
+  HIP_TRY(hipGetLastError());
+  long long tot = 0;
+  HIP_TRY(hipMemcpyAsync(&tot, &dctl->total, sizeof(long long), hipMemcpyDeviceToHost, h->s));
+  HIP_TRY(hipStreamSynchronize(h->s));
+  if (tot > 0xFFFFFFFELL) return fail(FTK_ERR_CAPACITY, "%lld punctured simplices exceed 2^32 - 2", tot);
+  h->total_after.push_back(tot);
+  return tracker_reserve(h, tot, h->emitted);
+}
+
+static ftk_status tracker_emit(ftk_tracker* h, int e, int nt) {
+  Ctl* dctl = (Ctl*)h->dctl;
+  Grid2 g = tracker_grid(h, e, nt);
+  Out2 od;
+  od.gbase = 0;
+  od.face_id = h->face_id;
+  od.pos = h->pos;
+  od.mu = h->mu;
+  od.type = h->type;
+  od.flags = h->flags;
+  od.parent = h->parent;
+  od.work = h->work;
+  od.label = nullptr;
+  HIP_TRY(launch_emit2d_steps(g, h->plane_wide[e % 3] != 0, h->mring, h->oring, od, &dctl->status, dctl->cnt, h->s));
+  h->emitted = h->total_after[e];
+  return FTK_OK;
+}
+
+}  // namespace ftk
+
+extern "C" ftk_status ftk_cp_create(int32_t n, const int64_t* dims, ftk_field_kind kind, const ftk_options* opt,
+                                    ftk_stream_t stream, ftk_tracker** out) {
+  g_err.clear();
+  if (!out) return fail(FTK_ERR_ARG, "tracker pointer is NULL");
+  *out = nullptr;
+  if ((n != 2 && n != 3) || !dims) return fail(FTK_ERR_ARG, "n must be 2 or 3 and dims given");
+  for (int a = 0; a < n; ++a)
+    if (dims[a] < 2 || dims[a] > (1 << 28)) return fail(FTK_ERR_ARG, "every spatial dimension must be in [2, 2^28]");
+  if (n == 3 && kind != FTK_SCALAR) return fail(FTK_ERR_ARG, "3D tracking takes a scalar field");
+  if (kind != FTK_SCALAR && kind != FTK_VECTOR) return fail(FTK_ERR_ARG, "bad kind");
+  ftk_options o;
+  resolve(opt, &o);
+  ftk_status st = ftk::validate_options(o);
+  if (st) return st;
+  ftk_tracker* h = new ftk_tracker();
+  h->n = n;
+  h->nx = dims[0];
+  h->ny = dims[1];
+  h->nz = n == 3 ? dims[2] : 1;
+  h->kind = kind;
+  h->o = o;
+  h->s = (hipStream_t)stream;
+  h->step_elems = (size_t)h->nx * h->ny * h->nz * (kind == FTK_VECTOR ? 2 : 1);
+  if (n == 2) {
+    const Alloc al = ftk::tracker_alloc(h);
+    const long long plane = h->nx * h->ny;
+    h->nseg_plane = h->ny * ((h->nx + 63) / 64);
+    h->fring = (float*)al.get(sizeof(float) * 3 * h->step_elems);
+    h->mring = (uint16_t*)al.get(sizeof(uint16_t) * 3 * plane);
+    h->cring = (int*)al.get(sizeof(int) * 3 * h->nseg_plane);
+    h->oring = (long long*)al.get(sizeof(long long) * 3 * h->nseg_plane);
+    h->scan_tmp = (long long*)al.get(sizeof(long long) * ftk::scan_tmp_elems(h->nseg_plane));
+    h->dctl = al.get(sizeof(Ctl));
+    h->dplane = (long long*)al.get(sizeof(long long));
+    if (!h->fring || !h->mring || !h->cring || !h->oring || !h->scan_tmp || !h->dctl || !h->dplane) {
+      ftk::tracker_free_all(h);
+      delete h;
+      return fail(FTK_ERR_OOM, "tracker allocation failed");
+    }
+    if (hipMemsetAsync(h->dctl, 0, sizeof(Ctl), h->s) != hipSuccess) {
+      ftk::tracker_free_all(h);
+      delete h;
+      return fail(FTK_ERR_HIP, "hipMemsetAsync failed");
+    }
+  }
+  *out = h;
+  return FTK_OK;
+}
+
+extern "C" ftk_status ftk_cp_push(ftk_tracker* h, const float* step) {
+  g_err.clear();
+  if (!h) return fail(FTK_ERR_ARG, "tracker is NULL");
+  if (h->state != 0) return fail(FTK_ERR_STATE, "tracker already finished or failed");
+  if (!step) return fail(FTK_ERR_ARG, "step is NULL");
+  if (h->steps >= (1 << 28)) return fail(FTK_ERR_ARG, "too many steps");
+  const Alloc al = ftk::tracker_alloc(h);
+  const size_t bytes = sizeof(float) * h->step_elems;
+  if (h->n == 3) {
+    if ((size_t)h->steps == h->all_cap_steps) {
+      size_t nc = h->all_cap_steps ? h->all_cap_steps * 2 : 8;
+      float* q = (float*)al.get(bytes * nc);
+      if (!q) return fail(FTK_ERR_OOM, "tracker allocation failed");
+      if (h->all) {
+        HIP_TRY(hipMemcpyAsync(q, h->all, bytes * h->steps, hipMemcpyDeviceToDevice, h->s));
+        al.put(h->all);
+      }
+      h->all = q;
+      h->all_cap_steps = nc;
+    }
+    HIP_TRY(hipMemcpyAsync((char*)h->all + bytes * h->steps, step, bytes, hipMemcpyDeviceToDevice, h->s));
+    ++h->steps;
+    return FTK_OK;
+  }
+  const int s = h->steps;
+  HIP_TRY(hipMemcpyAsync(h->fring + (size_t)(s % 3) * h->step_elems, step, bytes, hipMemcpyDeviceToDevice, h->s));
+  ftk_status st = FTK_OK;
+  if (s >= 1) st = ftk::tracker_detect(h, s - 1, ftk::kOpenNt);
+  if (!st && s >= 2) st = ftk::tracker_emit(h, s - 2, ftk::kOpenNt);
+  if (st) {
+    h->state = 2;
+    return st;
+  }
+  HIP_TRY(hipStreamSynchronize(h->s));  // the caller may reuse `step` on return
+  ++h->steps;
+  return FTK_OK;
+}
+
+extern "C" ftk_status ftk_cp_finish(ftk_tracker* h, ftk_cp_result* out) {
+  g_err.clear();
+  if (!h || !out) return fail(FTK_ERR_ARG, "tracker or result is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (h->state != 0) return fail(FTK_ERR_STATE, "tracker already finished or failed");
+  if (h->steps < 2) return fail(FTK_ERR_STATE, "at least two steps must be pushed");
+  h->state = 1;
+  if (h->n == 3) {
+    ftk_status st = ftk::track3d_impl(h->all, h->nx, h->ny, h->nz, h->steps, h->o, h->s, out);
+    return st;
+  }
+  const int N = h->steps;
+  Ctl* dctl = (Ctl*)h->dctl;
+  ftk_status st = ftk::tracker_detect(h, N - 1, N);
+  if (!st) st = ftk::tracker_emit(h, N - 2, N);
+  if (!st) st = ftk::tracker_emit(h, N - 1, N);
+  if (st) return st;
+  const long long nh = h->total_after[N - 1];
+  const Alloc al = ftk::tracker_alloc(h);
+  long long* label = nullptr;
+  if ((h->o.outputs & FTK_OUT_LABEL) && !(label = (long long*)al.get(sizeof(long long) * (nh ? nh : 1))))
+    return fail(FTK_ERR_OOM, "label allocation failed");
+  if (nh > 0) {
+    HIP_TRY(ftk::launch_uf_hook(h->parent, h->work, &dctl->cnt[ftk::CNT_WORK], 2 * h->cap, h->s));
+    HIP_TRY(ftk::launch_uf_label(h->parent, h->face_id, label, nh, dctl->cnt, h->s));
+  }
+  Ctl hc;
+  st = read_ctl(&hc, dctl, h->s);
+  if (!st) st = decode_status(hc.status);
+  if (st) {
+    al.put(label);
+    return st;
+  }
+  ftk_cp_result& r = *out;
+  r.n = 2;
+  r.n_hits = nh;
+  r.n_trajectories = (long long)hc.cnt[ftk::CNT_TRAJ];
+  r.face_id = (int64_t*)h->face_id;
+  r.pos = h->pos;
+  r.mu = h->mu;
+  r.type = h->type;
+  r.flags = h->flags;
+  r.label = (int64_t*)label;
+  h->face_id = nullptr;
+  h->pos = h->mu = nullptr;
+  h->type = h->flags = nullptr;
+  int64_t dims[3] = {h->nx, h->ny, N};
+  r.stats.simplices_tested = count_tested(2, dims);
+  r.stats.cells_linked = (long long)hc.cnt[ftk::CNT_LINKED];
+  r.stats.fp64_fallbacks = (long long)hc.cnt[ftk::CNT_FP64];
+  r.stats.degenerate_sublocations = (long long)hc.cnt[ftk::CNT_DEGEN];
+  r.stats.wide_path = (h->plane_wide[0] | h->plane_wide[1] | h->plane_wide[2]) ? 1 : 0;
+  return FTK_OK;
+}
+
+extern "C" void ftk_cp_destroy(ftk_tracker* h) {
+  if (!h) return;
+  ftk::tracker_free_all(h);
+  delete h;
+}
+
+namespace ftk {
+
 }  // namespace ftk
 
 extern "C" ftk_status ftk_track_cp3d(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nz,
@@ -505,6 +1106,27 @@ extern "C" ftk_status ftk_track_cp3d(const float* field, ftk_field_kind kind, in
   ftk_status st = ftk::validate_options(o);
   if (st) return st;
   return ftk::track3d_impl(field, nx, ny, nz, nt, o, (hipStream_t)stream, out);
+}
+
+extern "C" ftk_status ftk_track_cp2d_batched(int32_t n_series, const float* const* fields, const int64_t* nx,
+                                             const int64_t* ny, const int64_t* nt, ftk_field_kind kind,
+                                             const ftk_options* opt, ftk_stream_t stream, ftk_cp_result* outs) {
+  g_err.clear();
+  if (n_series <= 0 || !fields || !nx || !ny || !nt || !outs) return fail(FTK_ERR_ARG, "bad batch arguments");
+  if (n_series > 16384) return fail(FTK_ERR_ARG, "at most 16384 series per batch");
+  if (kind != FTK_SCALAR && kind != FTK_VECTOR) return fail(FTK_ERR_ARG, "kind must be FTK_SCALAR or FTK_VECTOR");
+  for (int i = 0; i < n_series; ++i) {
+    std::memset(&outs[i], 0, sizeof(outs[i]));
+    if (!fields[i]) return fail(FTK_ERR_ARG, "series %d: field is NULL", i);
+    if (nx[i] < 2 || ny[i] < 2 || nt[i] < 2) return fail(FTK_ERR_ARG, "series %d: every dimension must be >= 2", i);
+    if (nx[i] > (1 << 30) || ny[i] > (1 << 30) || nt[i] > (1 << 30) || nx[i] * ny[i] * nt[i] > (1ll << 40))
+      return fail(FTK_ERR_ARG, "series %d: grid too large", i);
+  }
+  ftk_options o;
+  resolve(opt, &o);
+  ftk_status st = ftk::validate_options(o);
+  if (st) return st;
+  return ftk::track2d_batched_impl(n_series, fields, nx, ny, nt, kind, o, (hipStream_t)stream, outs);
 }
 
 extern "C" ftk_status ftk_track_cp2d(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,

@@ -57,11 +57,14 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 // Stencils (Sec. 4.3 central differences; one-sided at the first and last index).  Binary32, fixed order; the
 // library is compiled without floating-point contraction, so these are bit-reproducible.
 // ---------------------------------------------------------------------------------------------------------------
+// Branch-free: at the first index (hi - mid), at the last (mid - lo), inside (hi - lo) * 0.5 -- the same binary32
+// operations as the three-way definition, so every kernel computes bit-identical values.
 __device__ __forceinline__ float diff3(float lo, float mid, float hi, int i, int N) {
-  if (i == 0) return hi - mid;
-  if (i == N - 1) return mid - lo;
-  float d = hi - lo;
-  return d * 0.5f;
+  const bool first = (i == 0), last = (i == N - 1);
+  const float a = first ? mid : lo;
+  const float b = last ? mid : hi;
+  const float d = b - a;
+  return (first || last) ? d : d * 0.5f;
 }
 
 // Quantisation to the integer lattice: round half to even of v * 2^s (exact scaling).  Returns the rounded value
@@ -103,7 +106,9 @@ __device__ __forceinline__ unsigned sos2_positive<long long>(long long a0, long 
 // Classification (Sec. 4.1): types from the spatial Jacobian interpolated at the zero, J_c = sum mu_i J(v_i).
 // Reference semantics are binary64 in a fixed order; the FP32 evaluation is accepted only when every sign it
 // decides is certified: |value32| > E32 + E64, where E32 and E64 bound the distance of the binary32 and binary64
-// evaluations from the exact value (mu carries three roundings: two conversions and a division).
+// evaluations from the exact value.  mu32 carries at most 5u of relative error (conversions of C_i and D, a 1-ulp
+// hardware reciprocal, one product), the interpolation three more roundings: the entry bound 10u * sum mu |J_i|
+// covers both with margin (u = 2^-24; the binary64 side uses u = 2^-53).
 // ---------------------------------------------------------------------------------------------------------------
 constexpr float kU32 = 5.9604645e-08f;  // 2^-24
 constexpr float kU64 = 1.1102230e-16f;  // 2^-53

@@ -23,6 +23,7 @@ namespace ftk {
 namespace {
 
 constexpr int TX = 64;
+constexpr int kEmitTT = 16;  // steps per emission workgroup
 
 // triangle types using each axis (validity masks at the last index of an axis)
 constexpr unsigned kUseX = (unsigned)types_using_axis(kTri2, 1);
@@ -61,6 +62,9 @@ __device__ __forceinline__ typename QType<WIDE>::T to_q(float r, unsigned& st) {
   }
 }
 
+__device__ __forceinline__ int fpl(const Grid2& g, int t) { return g.f_ring ? t % g.f_ring : t; }
+__device__ __forceinline__ int mpl(const Grid2& g, int t) { return g.m_ring ? t % g.m_ring : t; }
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -68,8 +72,9 @@ __device__ __forceinline__ typename QType<WIDE>::T to_q(float r, unsigned& st) {
 // grid = (ceil(nx / 64), ceil(ny / TY), ceil(nt / TT)), block = 256.
 // ---------------------------------------------------------------------------------------------------------------
 template <int TY, bool WIDE>
-__global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __restrict__ masks,
-                                                int* __restrict__ seg_cnt, unsigned* __restrict__ status) {
+__device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, int by, int bz,
+                                              uint16_t* __restrict__ masks, int* __restrict__ seg_cnt,
+                                              unsigned* __restrict__ status) {
   typedef typename QType<WIDE>::T Q;
   constexpr int FW = TX + 4, FH = TY + 4;  // field plane + 2-cell halo (x0-1 .. x0+TX+2)
   constexpr int QW = TX + 2, QH = TY + 2;  // quantised vectors (x0 .. x0+TX+1)
@@ -79,9 +84,9 @@ __global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __res
   __shared__ uint8_t ew[2][EH * EW];
 
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  const int t0 = blockIdx.z * TT;
-  const int t1 = min(t0 + TT, g.nt);
+  const int x0 = bx * TX, y0 = by * TY;
+  const int t0 = g.t_begin + bz * TT;
+  const int t1 = min(t0 + TT, g.t_end);
   const int nx = g.nx, ny = g.ny, nt = g.nt;
   const long long plane = (long long)nx * ny;
   unsigned st = 0;
@@ -89,7 +94,7 @@ __global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __res
   // Load plane t into fs (scalar: FH x FW with halo; vector: both components over the QH x QW region).
   auto load_plane = [&](int t) {
     if (g.kind == 0) {
-      const float* src = g.f + (long long)t * plane;
+      const float* src = g.f + (long long)fpl(g, t) * plane;
       for (int e = tid; e < FH * FW; e += 256) {
         int ly = e / FW, lx = e - ly * FW;
         int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __res
       }
     } else {
       for (int c = 0; c < 2; ++c) {
-        const float* src = g.f + ((long long)t * 2 + c) * plane;
+        const float* src = g.f + ((long long)fpl(g, t) * 2 + c) * plane;
         for (int e = tid; e < QH * QW; e += 256) {
           int ly = e / QW, lx = e - ly * QW;
           int gx = x0 + lx, gy = y0 + ly;
@@ -225,13 +230,19 @@ __global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __res
         if (gy == ny - 1) valid &= ~kUseY;
         if (t == nt - 1) valid &= ~kUseT;
         m &= valid;
-        masks[((long long)t * ny + gy) * nx + gx] = (uint16_t)m;
+        masks[((long long)mpl(g, t) * ny + gy) * nx + gx] = (uint16_t)m;
       }
       unsigned c = wave_sum(__popc(m));
-      if (lane == 0 && gy < ny) seg_cnt[((long long)t * ny + gy) * gridDim.x + blockIdx.x] = (int)c;
+      if (lane == 0 && gy < ny) seg_cnt[((long long)mpl(g, t) * ny + gy) * g.nxt + bx] = (int)c;
     }
   }
   if (st) atomicOr(status, st);
+}
+
+template <int TY, bool WIDE>
+__global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __restrict__ masks,
+                                                int* __restrict__ seg_cnt, unsigned* __restrict__ status) {
+  detect2d_tile<TY, WIDE>(g, TT, blockIdx.x, blockIdx.y, blockIdx.z, masks, seg_cnt, status);
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -387,9 +398,11 @@ __device__ __forceinline__ unsigned long long block_sum256(unsigned long long v,
 }
 
 template <int TY, bool WIDE>
-__global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* __restrict__ masks,
-                                              const long long* __restrict__ seg_off, Out2 o,
-                                              unsigned* __restrict__ status, unsigned long long* __restrict__ cnt) {
+__device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int by, int bz,
+                                            const uint16_t* __restrict__ masks, const long long* __restrict__ seg_off,
+                                            const Out2& o, unsigned* __restrict__ status,
+                                            unsigned long long* __restrict__ cnt,
+                                            unsigned long long* __restrict__ work_cnt) {
   constexpr int GW = TX + 3, GH = TY + 3;  // vector field: x0-1 .. x0+TX+1, y0-1 .. y0+TY+1
   constexpr int FW = TX + 5, FH = TY + 5;  // scalar field: x0-2 .. x0+TX+2
   constexpr int CAP = 1792;                // local union-find capacity (hits)
@@ -415,9 +428,9 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
   __shared__ unsigned s_cof[12][2];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  const int t0 = blockIdx.z * TT;
-  const int t1 = min(t0 + TT, g.nt);
+  const int x0 = bx * TX, y0 = by * TY;
+  const int t0 = g.t_begin + bz * TT;
+  const int t1 = min(t0 + TT, g.t_end);
   const int nx = g.nx, ny = g.ny, nt = g.nt, nxt = g.nxt;
   const long long plane = (long long)nx * ny;
   const bool vector = g.kind != 0;
@@ -433,7 +446,7 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
   // vector field of plane t into gs[par]
   auto load_plane = [&](int t, int par) {
     if (!vector) {
-      const float* src = g.f + (long long)t * plane;
+      const float* src = g.f + (long long)fpl(g, t) * plane;
       for (int e = tid; e < FH * FW; e += 256) {
         int ly = e / FW, lx = e - ly * FW;
         int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
@@ -452,7 +465,7 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
         gs[par][e] = v;
       }
     } else {
-      const float* su = g.f + (long long)t * 2 * plane;
+      const float* su = g.f + (long long)fpl(g, t) * 2 * plane;
       const float* sv = su + plane;
       for (int e = tid; e < GH * GW; e += 256) {
         int ly = e / GW, lx = e - ly * GW;
@@ -477,7 +490,7 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
   };
   // move the staged edges to the global list
   auto drain = [&]() {
-    if (tid == 0) s_stage_base = s_stage_n ? atomicAdd(&cnt[CNT_WORK], (unsigned long long)s_stage_n) : 0ull;
+    if (tid == 0) s_stage_base = s_stage_n ? atomicAdd(work_cnt, (unsigned long long)s_stage_n) : 0ull;
     __syncthreads();
     const int n = s_stage_n;
     for (int i = tid; i < n; i += 256) o.work[s_stage_base + i] = s_stage[i];
@@ -501,14 +514,14 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
     for (int ly = wave; ly < TY; ly += 4) {
       const int y = y0 + ly, x = x0 + lane;
       unsigned m = 0;
-      if (y < ny && x < nx) m = masks[(long long)t * plane + (long long)y * nx + x];
+      if (y < ny && x < nx) m = masks[(long long)mpl(g, t) * plane + (long long)y * nx + x];
       const unsigned c = __popc(m);
       const unsigned incl = wave_incl_scan(c);
       s_m[ly][lane] = (unsigned short)m;
       s_ex[ly][lane] = (unsigned short)(incl - c);
       if (lane == 63) {
         s_rowtot[ly] = incl;
-        s_rowbase[ly] = y < ny ? (unsigned)seg_off[((long long)t * ny + y) * nxt + blockIdx.x] : 0u;
+        s_rowbase[ly] = y < ny ? (unsigned)seg_off[((long long)mpl(g, t) * ny + y) * nxt + bx] : 0u;
       }
     }
     __syncthreads();
@@ -561,8 +574,7 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
       if (total == 0) continue;
       const int x = x0 + lane;
       const bool in = x < nx;
-      const long long seg = ((long long)t * ny + y) * nxt + blockIdx.x;
-      const long long gidx = (long long)t * plane + (long long)y * nx + x;
+      const long long gidx = (long long)mpl(g, t) * plane + (long long)y * nx + x;  // mask index
       const unsigned m = s_m[ly][lane];
       const unsigned ex = s_ex[ly][lane];
       const unsigned base = s_rowbase[ly];
@@ -593,17 +605,19 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
         nbo[wave][NB_MX][lane] = mxo;
         nbm[wave][NB_PX][lane] = (unsigned short)pxm;
         nbo[wave][NB_PX][lane] = pxo;
-        auto seg_nb = [&](int slot, long long dseg, long long dg, bool ok) {
-          unsigned mm = (ok && in) ? masks[gidx + dg] : 0u;
+        // neighbour row segment (step tt, row yy) at the same lanes
+        auto seg_nb = [&](int slot, int tt, int yy, bool ok) {
+          const long long mp = ok ? (long long)mpl(g, tt) : 0;
+          unsigned mm = (ok && in) ? masks[(mp * ny + yy) * nx + x] : 0u;
           unsigned inc = wave_incl_scan(__popc(mm));
-          unsigned b = ok ? (unsigned)seg_off[seg + dseg] : 0u;
+          unsigned b = ok ? (unsigned)seg_off[(mp * ny + yy) * nxt + bx] : 0u;
           nbm[wave][slot][lane] = (unsigned short)mm;
           nbo[wave][slot][lane] = b + inc - __popc(mm);
         };
-        seg_nb(NB_MY, -(long long)nxt, -(long long)nx, y > 0);
-        seg_nb(NB_PY, (long long)nxt, (long long)nx, y + 1 < ny);
-        seg_nb(NB_MT, -(long long)nxt * ny, -plane, t > 0);
-        seg_nb(NB_PT, (long long)nxt * ny, plane, t + 1 < nt);
+        seg_nb(NB_MY, t, y - 1, y > 0);
+        seg_nb(NB_PY, t, y + 1, y + 1 < ny);
+        seg_nb(NB_MT, t - 1, y, t > 0);
+        seg_nb(NB_PT, t + 1, y, t + 1 < nt);
         const unsigned c_self = __popc(m);
         for (unsigned k = 0; k < c_self; ++k) s_lane[wave][ex + k] = (unsigned char)lane;
       }
@@ -686,9 +700,10 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
           if (degenerate) {
             mu32[0] = mu32[1] = mu32[2] = 1.0f / 3.0f;
           } else {
-            const float fD = (float)Dd;
+            // hardware reciprocal (1 ulp): mu carries at most five roundings, inside the classifier's bound
+            const float rD = __builtin_amdgcn_rcpf((float)Dd);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) mu32[i] = (float)Cd[i] / fD;
+            for (int i = 0; i < 3; ++i) mu32[i] = (float)Cd[i] * rD;
           }
           type = classify2_fp32(mu32, J, vector);
         }
@@ -740,19 +755,20 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
           for (int i = 0; i < 3; ++i) muo[i] = (float)mu64[i];
         }
         const long long agid = (long long)t * plane + (long long)y * nx + ax;
-        o.face_id[idx] = agid * 12 + ty;
+        const size_t oi = idx - o.gbase;
+        o.face_id[oi] = agid * 12 + ty;
         if (o.pos) {
-          o.pos[(size_t)idx * 3 + 0] = pos[0];
-          o.pos[(size_t)idx * 3 + 1] = pos[1];
-          o.pos[(size_t)idx * 3 + 2] = pos[2];
+          o.pos[oi * 3 + 0] = pos[0];
+          o.pos[oi * 3 + 1] = pos[1];
+          o.pos[oi * 3 + 2] = pos[2];
         }
         if (o.mu) {
-          o.mu[(size_t)idx * 3 + 0] = muo[0];
-          o.mu[(size_t)idx * 3 + 1] = muo[1];
-          o.mu[(size_t)idx * 3 + 2] = muo[2];
+          o.mu[oi * 3 + 0] = muo[0];
+          o.mu[oi * 3 + 1] = muo[1];
+          o.mu[oi * 3 + 2] = muo[2];
         }
-        if (o.type) o.type[idx] = (uint8_t)type;
-        if (o.flags) o.flags[idx] = (uint8_t)fl;
+        if (o.type) o.type[oi] = (uint8_t)type;
+        if (o.flags) o.flags[oi] = (uint8_t)fl;
 
         // ---- pass 2 links: each of the (at most two) tetrahedra holding this triangle has exactly one other
         // punctured side.  Each link is recorded by its larger endpoint: inside this tile and chunk it goes to the
@@ -827,8 +843,8 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
           if (ns > 0) g0 = link(sm0, sl0);
           if (ns > 1) g1 = link(sm1, sl1);
         }
-        append_edge(g0, idx, sm0, s_stage, &s_stage_n, o.work, &cnt[CNT_WORK]);
-        append_edge(g1, idx, sm1, s_stage, &s_stage_n, o.work, &cnt[CNT_WORK]);
+        append_edge(g0, idx, sm0, s_stage, &s_stage_n, o.work, work_cnt);
+        append_edge(g1, idx, sm1, s_stage, &s_stage_n, o.work, work_cnt);
       }
       wave_lds_sync();
     }
@@ -847,12 +863,113 @@ __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* _
   if (st) atomicOr(status, st);
 }
 
+template <int TY, bool WIDE>
+__global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* __restrict__ masks,
+                                              const long long* __restrict__ seg_off, Out2 o,
+                                              unsigned* __restrict__ status, unsigned long long* __restrict__ cnt) {
+  emit2d_tile<TY, WIDE>(g, TT, blockIdx.x, blockIdx.y, blockIdx.z, masks, seg_off, o, status, cnt, &cnt[CNT_WORK]);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// Batched form: one persistent launch per stage for many independent series.  Workgroups pull (series, tile) items
+// from a device counter; the item -> series map is a binary search over the per-series item prefix.
+// ---------------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ int take_item(int* counter, int total, int* s_item) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
+  __syncthreads();
+  const int it = *s_item;
+  return it < total ? it : -1;
+}
+
+__device__ __forceinline__ int series_of(const int* prefix, int nser, int item) {
+  int lo = 0, hi = nser;  // prefix[lo] <= item < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <int TY, bool WIDE>
+__global__ __launch_bounds__(256) void detect2d_batched(const Series2* __restrict__ S, const int* __restrict__ prefix,
+                                                        int nser, int TT, int* counter, unsigned* status) {
+  __shared__ int s_item;
+  const int total = prefix[nser];
+  for (;;) {
+    const int it = take_item(counter, total, &s_item);
+    if (it < 0) break;
+    const int s = series_of(prefix, nser, it);
+    const Grid2 g = S[s].g;
+    const int local = it - prefix[s];
+    const int tx = g.nxt, tyn = (g.ny + TY - 1) / TY;
+    const int bx = local % tx, by = (local / tx) % tyn, bz = local / (tx * tyn);
+    detect2d_tile<TY, WIDE>(g, TT, bx, by, bz, S[s].masks, S[s].seg_cnt, status);
+  }
+}
+
+template <int TY, bool WIDE>
+__global__ __launch_bounds__(256) void emit2d_batched(const Series2* __restrict__ S, const int* __restrict__ prefix,
+                                                      int nser, int TT, int* counter, unsigned* status,
+                                                      unsigned long long* work_cnt) {
+  __shared__ int s_item;
+  const int total = prefix[nser];
+  for (;;) {
+    const int it = take_item(counter, total, &s_item);
+    if (it < 0) break;
+    const int s = series_of(prefix, nser, it);
+    const Grid2 g = S[s].g;
+    const Out2 o = S[s].o;
+    const int local = it - prefix[s];
+    const int tx = g.nxt, tyn = (g.ny + TY - 1) / TY;
+    const int bx = local % tx, by = (local / tx) % tyn, bz = local / (tx * tyn);
+    if (S[s].wide)
+      emit2d_tile<TY, true>(g, TT, bx, by, bz, S[s].masks, S[s].seg_off, o, status, S[s].cnt, work_cnt);
+    else
+      emit2d_tile<TY, false>(g, TT, bx, by, bz, S[s].masks, S[s].seg_off, o, status, S[s].cnt, work_cnt);
+  }
+}
+
+// Emission of single steps (streaming): one step per launch, local union-find per step.
+hipError_t launch_emit2d_steps(const Grid2& g, bool wide, const uint16_t* masks, const long long* seg_off,
+                               const Out2& o, unsigned* status, unsigned long long* cnt, hipStream_t s) {
+  constexpr int TYE = 8;
+  dim3 grid((unsigned)g.nxt, (unsigned)((g.ny + TYE - 1) / TYE), (unsigned)(g.t_end - g.t_begin));
+  if (wide)
+    emit2d<TYE, true><<<grid, 256, 0, s>>>(g, 1, masks, seg_off, o, status, cnt);
+  else
+    emit2d<TYE, false><<<grid, 256, 0, s>>>(g, 1, masks, seg_off, o, status, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_detect2d_batched(const Series2* S, const int* prefix, int nser, int total_items, int tt, bool wide,
+                                   int* counter, unsigned* status, hipStream_t s) {
+  int blocks = total_items < 2048 ? total_items : 2048;
+  if (blocks < 1) blocks = 1;
+  if (wide)
+    detect2d_batched<16, true><<<blocks, 256, 0, s>>>(S, prefix, nser, tt, counter, status);
+  else
+    detect2d_batched<16, false><<<blocks, 256, 0, s>>>(S, prefix, nser, tt, counter, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit2d_batched(const Series2* S, const int* prefix, int nser, int total_items, int* counter,
+                                 unsigned* status, unsigned long long* work_cnt, hipStream_t s) {
+  int blocks = total_items < 1536 ? total_items : 1536;
+  if (blocks < 1) blocks = 1;
+  emit2d_batched<8, false><<<blocks, 256, 0, s>>>(S, prefix, nser, kEmitTT, counter, status, work_cnt);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------------------------------------------
 hipError_t launch_detect2d(const Grid2& g, int ty, int tt, bool wide, uint16_t* masks, int* seg_cnt,
                            unsigned* status, hipStream_t s) {
-  dim3 grid((unsigned)g.nxt, (unsigned)((g.ny + ty - 1) / ty), (unsigned)((g.nt + tt - 1) / tt));
+  dim3 grid((unsigned)g.nxt, (unsigned)((g.ny + ty - 1) / ty), (unsigned)((g.t_end - g.t_begin + tt - 1) / tt));
   if (ty == 8) {
     if (wide)
       detect2d<8, true><<<grid, 256, 0, s>>>(g, tt, masks, seg_cnt, status);
@@ -875,8 +992,8 @@ hipError_t launch_detect2d(const Grid2& g, int ty, int tt, bool wide, uint16_t* 
 hipError_t launch_emit2d(const Grid2& g, bool wide, const uint16_t* masks, const long long* seg_off, long long nseg,
                          const Out2& o, unsigned* status, unsigned long long* cnt, hipStream_t s) {
   (void)nseg;
-  constexpr int TYE = 8, TTE = 16;
-  dim3 grid((unsigned)g.nxt, (unsigned)((g.ny + TYE - 1) / TYE), (unsigned)((g.nt + TTE - 1) / TTE));
+  constexpr int TYE = 8, TTE = kEmitTT;
+  dim3 grid((unsigned)g.nxt, (unsigned)((g.ny + TYE - 1) / TYE), (unsigned)((g.t_end - g.t_begin + TTE - 1) / TTE));
   if (wide)
     emit2d<TYE, true><<<grid, 256, 0, s>>>(g, TTE, masks, seg_off, o, status, cnt);
   else

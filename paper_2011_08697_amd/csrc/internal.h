@@ -9,21 +9,38 @@ namespace ftk {
 struct Grid2 {
   const float* f;
   int kind;       // 0 scalar, 1 vector (planar [t][2][y][x])
-  int nx, ny, nt;
+  int nx, ny, nt; // nt: number of steps of the series (a large value while a stream is still open)
   int nxt;        // row segments per row: ceil(nx / 64)
   float qscale;   // 2^quant_log2
   int precision;  // 0 FP32 + certified FP64 fallback, 1 FP64
+  int t_begin, t_end;  // anchors processed by a launch: steps [t_begin, t_end)
+  int f_ring;     // field planes stored as a ring of f_ring steps (step t at slot t % f_ring); 0: plane t at t
+  int m_ring;     // same for the puncture masks and the per-segment counts/offsets
 };
 
 // 2D outputs (device pointers; pos/mu/type/flags may be null).
 struct Out2 {
+  unsigned gbase;    // global hit index of this series' first hit (outputs are indexed by global - gbase)
   long long* face_id;
   float* pos;
   float* mu;
   uint8_t* type;
   uint8_t* flags;
-  unsigned* parent;  // union-find forest over hit indices
-  uint2* work;       // extra union edges (hit, smaller partner)
+  unsigned* parent;  // union-find forest over global hit indices
+  uint2* work;       // union edges that leave a tile/chunk (global hit, smaller partner)
+  long long* label;  // labels (read by the batched label pass)
+};
+
+// One series of a batched call (device copy read by the persistent kernels).
+struct Series2 {
+  Grid2 g;
+  Out2 o;
+  uint16_t* masks;
+  int* seg_cnt;
+  long long* seg_off;
+  unsigned long long* cnt;  // per-series counters (CNT_*)
+  int wide;
+  int pad;
 };
 
 // 3D problem description.
@@ -49,6 +66,16 @@ hipError_t launch_detect2d(const Grid2& g, int ty, int tt, bool wide, uint16_t* 
                            unsigned* status, hipStream_t s);
 hipError_t launch_emit2d(const Grid2& g, bool wide, const uint16_t* masks, const long long* seg_off, long long nseg,
                          const Out2& o, unsigned* status, unsigned long long* cnt, hipStream_t s);
+
+hipError_t launch_emit2d_steps(const Grid2& g, bool wide, const uint16_t* masks, const long long* seg_off,
+                               const Out2& o, unsigned* status, unsigned long long* cnt, hipStream_t s);
+hipError_t launch_detect2d_batched(const Series2* S, const int* prefix, int nser, int total_items, int tt, bool wide,
+                                   int* counter, unsigned* status, hipStream_t s);
+hipError_t launch_emit2d_batched(const Series2* S, const int* prefix, int nser, int total_items, int* counter,
+                                 unsigned* status, unsigned long long* work_cnt, hipStream_t s);
+// Labels for concatenated series: hit i belongs to the series s with gbase[s] <= i < gbase[s+1].
+hipError_t launch_uf_label_batched(unsigned* parent, const Series2* S, const unsigned* gbase, int nser, long long n,
+                                   hipStream_t s);
 
 hipError_t launch_detect3d(const Grid3& g, int tt, bool wide, uint64_t* masks, int* seg_cnt, unsigned* status,
                            hipStream_t s);

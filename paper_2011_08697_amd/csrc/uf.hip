@@ -41,7 +41,39 @@ __global__ __launch_bounds__(256) void uf_label(unsigned* __restrict__ parent, c
   }
 }
 
+// Batched labels: the series of hit i by binary search over the series' first global indices (in LDS).
+__global__ __launch_bounds__(256) void uf_label_batched(unsigned* __restrict__ parent, const Series2* __restrict__ S,
+                                                        const unsigned* __restrict__ gbase, int nser, long long n) {
+  extern __shared__ unsigned s_base[];
+  for (int i = threadIdx.x; i <= nser; i += blockDim.x) s_base[i] = gbase[i];
+  __syncthreads();
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    int lo = 0, hi = nser;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_base[mid] <= (unsigned)i)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const unsigned b = s_base[lo];
+    const unsigned r = uf_find_plain(parent, (unsigned)i);
+    const Out2& o = S[lo].o;
+    if (o.label) o.label[i - b] = o.face_id[r - b];
+    if (r == (unsigned)i) atomicAdd(&S[lo].cnt[CNT_TRAJ], 1ull);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_uf_label_batched(unsigned* parent, const Series2* S, const unsigned* gbase, int nser, long long n,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  uf_label_batched<<<(unsigned)blocks, 256, (nser + 1) * sizeof(unsigned), s>>>(parent, S, gbase, nser, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_uf_hook(unsigned* parent, const uint2* work, const unsigned long long* work_count,
                           long long max_work, hipStream_t s) {

@@ -37,10 +37,13 @@ def _windows(c, s, N):
     return lo, hi
 
 
-def moving_gaussians_2d(nx, ny, nt, K, sigma=(4.0, 10.0), vmax=1.0, seed=0, noise_std=0.0):
-    """f[t][y][x] = sum_k s_k A_k exp(-|x - c_k - v_k t|^2 / (2 sigma_k^2)) (+ iid N(0, noise_std) noise)."""
+def moving_gaussians_2d(nx, ny, nt, K, sigma=(4.0, 10.0), vmax=1.0, seed=0, noise_std=0.0, device=None):
+    """f[t][y][x] = sum_k s_k A_k exp(-|x - c_k - v_k t|^2 / (2 sigma_k^2)) (+ iid N(0, noise_std) noise).
+    With a torch device (and no noise) the same float64 evaluation runs there and a float32 numpy array returns."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sign, amp, sig, centre, vel = _blob_params(rng, K, (nx, ny), sigma, vmax)
+    if device is not None and noise_std == 0:
+        return _gaussians_2d_torch(nx, ny, nt, K, sign, amp, sig, centre, vel, device)
     f = np.zeros((nt, ny, nx), np.float64)
     for t in range(nt):
         plane = f[t]
@@ -84,6 +87,26 @@ def moving_gaussians_3d(nx, ny, nz, nt, K, sigma=(6.0, 16.0), vmax=1.0, seed=2, 
             vol[rz[0]:rz[1], ry[0]:ry[1], rx[0]:rx[1]] += (sign[k] * amp[k]) * (
                 ez[:, None, None] * ey[None, :, None] * ex[None, None, :])
     return f.astype(np.float32)
+
+
+def _gaussians_2d_torch(nx, ny, nt, K, sign, amp, sig, centre, vel, device):
+    import torch
+    out = np.empty((nt, ny, nx), np.float32)
+    for t in range(nt):
+        plane = torch.zeros((ny, nx), dtype=torch.float64, device=device)
+        for k in range(K):
+            cx = centre[k, 0] + vel[k, 0] * t
+            cy = centre[k, 1] + vel[k, 1] * t
+            x0, x1 = _windows(cx, sig[k], nx)
+            y0, y1 = _windows(cy, sig[k], ny)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            inv = 1.0 / (2.0 * sig[k] * sig[k])
+            ex = torch.exp(-((torch.arange(x0, x1, dtype=torch.float64, device=device) - cx) ** 2) * inv)
+            ey = torch.exp(-((torch.arange(y0, y1, dtype=torch.float64, device=device) - cy) ** 2) * inv)
+            plane[y0:y1, x0:x1] += (float(sign[k]) * float(amp[k])) * (ey[:, None] * ex[None, :])
+        out[t] = plane.to(torch.float32).cpu().numpy()
+    return out
 
 
 def _gaussians_3d_torch(nx, ny, nz, nt, K, sign, amp, sig, centre, vel, device):
@@ -147,7 +170,7 @@ def quantise_levels(f, levels=16):
 
 
 def batch_series(count=96, seed0=3, size_range=(128, 2048), nt_range=(8, 64), k_range=(16, 512),
-                 sigma=(4.0, 10.0), vmax=1.0, shape_only=False):
+                 sigma=(4.0, 10.0), vmax=1.0, shape_only=False, device=None):
     """Many independent 2D series of uneven sizes: series i uses seed seed0 + i; nx, ny ~ round(exp(U(ln lo,
     ln hi))), nt ~ integers in nt_range (inclusive), K = clip(round(512 nx ny / 2048^2), k_range); the blobs are
     drawn after these with the shared recipe."""
@@ -163,6 +186,9 @@ def batch_series(count=96, seed0=3, size_range=(128, 2048), nt_range=(8, 64), k_
             continue
         # the blob parameters continue from the same generator
         sign, amp, sig, centre, vel = _blob_params(rng, K, (nx, ny), sigma, vmax)
+        if device is not None:
+            out.append(_gaussians_2d_torch(nx, ny, nt, K, sign, amp, sig, centre, vel, device))
+            continue
         f = np.zeros((nt, ny, nx), np.float64)
         for t in range(nt):
             for k in range(K):
