@@ -83,6 +83,26 @@ def measured_traffic(kernel, workload):
         return None
 
 
+def precision_report(F, field_np, field, kind, n, sample=20000):
+    """FP32 sublocation/classification of sampled hits against the binary64 oracle (per-result errors)."""
+    import numpy as np
+    from oracle import oracle as O
+    r = F.track_cp2d(field, kind=kind)
+    fid = r["face_id"].cpu().numpy()
+    pos = r["pos"].cpu().numpy().astype(np.float64)
+    typ = r["type"].cpu().numpy()
+    flg = r["flags"].cpu().numpy()
+    rng = np.random.default_rng(0)
+    idx = rng.choice(len(fid), min(sample, len(fid)), replace=False)
+    ev = O.eval_faces(field_np, fid[idx], n=n, kind=kind)
+    err = np.abs(pos[idx] - ev["pos"]) / np.maximum(1.0, np.abs(ev["pos"]))
+    return {"hits": int(len(fid)), "sampled": int(len(idx)), "punctured_agree": bool(np.all(ev["punctured"] == 1)),
+            "type_agree": float(np.mean(typ[idx] == ev["type"])), "pos_rel_err_max": float(err.max()),
+            "pos_rel_err_mean": float(err.mean()), "tolerance": 1e-5,
+            "fp64_fallback_frac": float(np.mean((flg & 2) != 0)),
+            "degenerate_frac": float(np.mean((flg & 1) != 0))}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -105,7 +125,7 @@ def main():
     n = 3 if wl == "c2" else 2
     kind = 1 if wl == "c4" else 0
     t0 = time.time()
-    field_np = synth.make(wl)
+    field_np = synth.make(wl, device=dev if wl in ("c2", "c4") else None)
     gen_s = time.time() - t0
     field = torch.from_numpy(field_np).to(dev)
     if n == 2:
@@ -182,6 +202,10 @@ def main():
                          f"({tr.simplices_tested} simplices, {tr.n_hits} hits, full detect + sublocate + stitch, "
                          f"{cpu_s:.1f} s)"}
 
+    precision = None
+    if wl == "c4":
+        precision = precision_report(F, field_np, field, kind, n)
+
     line = {
         "metric": "spacetime simplices tested/s + HBM roofline frac; batched vs plain steps/s",
         "value": round(value, 1), "unit": "simplices/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -193,6 +217,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if precision is not None:
+        line["precision"] = precision
     print(json.dumps(line), flush=True)
 
 

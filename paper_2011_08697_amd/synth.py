@@ -131,13 +131,15 @@ def _gaussians_3d_torch(nx, ny, nz, nt, K, sign, amp, sig, centre, vel, device):
     return out
 
 
-def vortex_sources_2d(nx, ny, nt, K, sigma=(16.0, 48.0), vmax=2.0, seed=4):
+def vortex_sources_2d(nx, ny, nt, K, sigma=(16.0, 48.0), vmax=2.0, seed=4, device=None):
     """Vector field u[t][c][y][x]: half the blobs contribute grad G (sources/sinks), half the rotated gradient
     (-dG/dy, dG/dx) (vortices), G = s A exp(-r^2 / (2 sigma^2)); derivatives are analytic.  The blob kind is drawn
     after the shared parameters (kind = vortex where random(K) < 0.5)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sign, amp, sig, centre, vel = _blob_params(rng, K, (nx, ny), sigma, vmax)
     vortex = rng.random(K) < 0.5
+    if device is not None:
+        return _vortex_sources_torch(nx, ny, nt, K, sign, amp, sig, centre, vel, vortex, device)
     u = np.zeros((nt, 2, ny, nx), np.float64)
     for t in range(nt):
         for k in range(K):
@@ -160,6 +162,34 @@ def vortex_sources_2d(nx, ny, nt, K, sigma=(16.0, 48.0), vmax=2.0, seed=4):
                 u[t, 0, y0:y1, x0:x1] += gx
                 u[t, 1, y0:y1, x0:x1] += gy
     return u.astype(np.float32)
+
+
+def _vortex_sources_torch(nx, ny, nt, K, sign, amp, sig, centre, vel, vortex, device):
+    import torch
+    out = np.empty((nt, 2, ny, nx), np.float32)
+    for t in range(nt):
+        u = torch.zeros((2, ny, nx), dtype=torch.float64, device=device)
+        for k in range(K):
+            cx = centre[k, 0] + vel[k, 0] * t
+            cy = centre[k, 1] + vel[k, 1] * t
+            x0, x1 = _windows(cx, sig[k], nx)
+            y0, y1 = _windows(cy, sig[k], ny)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            inv = 1.0 / (2.0 * sig[k] * sig[k])
+            dx = torch.arange(x0, x1, dtype=torch.float64, device=device) - cx
+            dy = torch.arange(y0, y1, dtype=torch.float64, device=device) - cy
+            G = (float(sign[k]) * float(amp[k])) * (torch.exp(-(dy ** 2) * inv)[:, None] * torch.exp(-(dx ** 2) * inv)[None, :])
+            gx = -G * (dx[None, :] / (sig[k] * sig[k]))
+            gy = -G * (dy[:, None] / (sig[k] * sig[k]))
+            if vortex[k]:
+                u[0, y0:y1, x0:x1] += -gy
+                u[1, y0:y1, x0:x1] += gx
+            else:
+                u[0, y0:y1, x0:x1] += gx
+                u[1, y0:y1, x0:x1] += gy
+        out[t] = u.to(torch.float32).cpu().numpy()
+    return out
 
 
 def quantise_levels(f, levels=16):
@@ -256,5 +286,5 @@ def make(name, nt=None, ny=None, device=None):
         return moving_gaussians_3d(nx, ny or nyy, nz, nt or ntt, c["K"], seed=c["seed"], device=device)
     if name == "c4":
         nx, nyy, ntt = c["dims"]
-        return vortex_sources_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"])
+        return vortex_sources_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"], device=device)
     raise KeyError(name)
