@@ -26,6 +26,7 @@ WORKLOADS = {
     "c1deg": "2D scalar 1024x1024x100, c1 field rounded to 16 levels",
     "c2": "3D scalar 256x256x256x16, 512 moving Gaussians, seed 2",
     "c4": "2D vector 4096x4096x50, 1024 moving sources/sinks/vortices, seed 4",
+    "c3": "96 uneven 2D scalar series (nx, ny log-uniform 128-2048, 8-64 steps), seeds 3+i; batched vs plain",
 }
 
 
@@ -83,6 +84,52 @@ def measured_traffic(kernel, workload):
         return None
 
 
+def bench_batched(args, F, synth, dev):
+    """Batched form (one persistent launch per stage for all 96 series) against 96 plain calls."""
+    import numpy as np
+    import torch
+    t0 = time.time()
+    fields = synth.batch_series(count=96, seed0=3, device=dev)
+    gen_s = time.time() - t0
+    ts = [torch.from_numpy(f).to(dev) for f in fields]
+    steps_total = sum(f.shape[0] for f in fields)
+    tested = sum(F.simplex_count(2, (f.shape[2], f.shape[1], f.shape[0])) for f in fields)
+
+    def batched():
+        res = F.track_cp2d_batched(ts)
+        return sum(r["n_hits"] for r in res)
+
+    def plain():
+        return sum(F.track_cp2d(t)["n_hits"] for t in ts)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            nh = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / args.steps, nh
+
+    tb, nhb = timed(batched)
+    tp, nhp = timed(plain)
+    assert nhb == nhp
+    line = {
+        "metric": "spacetime simplices tested/s + HBM roofline frac; batched vs plain steps/s",
+        "value": round(tested / tb, 1), "unit": "simplices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c3"], "series": len(fields), "time_steps_total": steps_total,
+                   "vertices_total": int(sum(f.size for f in fields)), "n_hits": nhb, "generation_s": round(gen_s, 1)},
+        "batched": {"steps_per_s": round(steps_total / tb, 1), "ms_per_batch": round(tb * 1e3, 3)},
+        "plain": {"steps_per_s": round(steps_total / tp, 1), "ms_per_batch": round(tp * 1e3, 3)},
+        "batched_over_plain": round(tp / tb, 3),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def precision_report(F, field_np, field, kind, n, sample=20000):
     """FP32 sublocation/classification of sampled hits against the binary64 oracle (per-result errors)."""
     import numpy as np
@@ -122,6 +169,8 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     wl = args.workload
+    if wl == "c3":
+        return bench_batched(args, F, synth, dev)
     n = 3 if wl == "c2" else 2
     kind = 1 if wl == "c4" else 0
     t0 = time.time()
@@ -150,7 +199,8 @@ def main():
         if st != 0:
             raise F.FtkError(st, F.last_error())
         out = (int(r.n_hits), int(r.n_trajectories), int(r.stats.simplices_tested),
-               r.stats.t_detect_ms, r.stats.t_scan_ms, r.stats.t_emit_ms, r.stats.t_link_ms)
+               r.stats.t_detect_ms, r.stats.t_scan_ms, r.stats.t_emit_ms, r.stats.t_link_ms,
+               int(r.stats.fp64_fallbacks), int(r.stats.degenerate_sublocations))
         L.ftk_result_free(ctypes.byref(r), ctypes.byref(opt), sh)  # returns the output tensors to torch's cache
         return out
 
@@ -160,7 +210,7 @@ def main():
     phase = np.zeros(4)
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        nh, ntraj, tested, td, ts, te, tl = one_step()
+        nh, ntraj, tested, td, ts, te, tl, n_fp64, n_degen = one_step()
         phase += (td, ts, te, tl)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -213,6 +263,7 @@ def main():
         "dtype": "int64", "data": "synthetic",
         "config": {"workload": WORKLOADS[wl], "dims": list(dims), "kind": "vector" if kind else "scalar",
                    "n_hits": nh, "n_trajectories": ntraj, "simplices_per_step": tested,
+                   "fp64_fallbacks": n_fp64, "degenerate_sublocations": n_degen,
                    "generation_s": round(gen_s, 1)},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -407,7 +407,7 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
   hipError_t he = hipSuccess;
   ph.mark(3);
   if (nh > 0) {
-    he = launch_emit2d(g, wide, masks, seg_off, nseg, od, &dctl->status, dctl->cnt, s);
+    he = launch_emit2d(g, wide, masks, seg_cnt, seg_off, od, &dctl->status, dctl->cnt, s);
     ph.mark(4);
     if (he == hipSuccess) he = launch_uf_hook(parent, work, &dctl->cnt[CNT_WORK], 2 * nh, s);
     if (he == hipSuccess) he = launch_uf_label(parent, od.face_id, (long long*)r.label, nh, dctl->cnt, s);
@@ -709,8 +709,8 @@ ftk_status track2d_batched_impl(int nser, const float* const* fields, const int6
   ph.mark(3);
   hipError_t he = hipSuccess;
   if (total > 0) {
-    he = launch_emit2d_batched(dser, dpre + nser + 1, nser, pre_e[nser], dctr, &dctl->status, &dctl->cnt[CNT_WORK],
-                               s);
+    he = launch_emit2d_batched(dser, dpre + nser + 1, nser, pre_e[nser], wide, dctr, &dctl->status,
+                               &dctl->cnt[CNT_WORK], s);
     ph.mark(4);
     if (he == hipSuccess) he = launch_uf_hook(parent, work, &dctl->cnt[CNT_WORK], 2 * total, s);
     if (he == hipSuccess) he = launch_uf_label_batched(parent, dser, dgb, nser, total, s);
@@ -929,7 +929,7 @@ static ftk_status tracker_emit(ftk_tracker* h, int e, int nt) {
   od.parent = h->parent;
   od.work = h->work;
   od.label = nullptr;
-  HIP_TRY(launch_emit2d_steps(g, h->plane_wide[e % 3] != 0, h->mring, h->oring, od, &dctl->status, dctl->cnt, h->s));
+  HIP_TRY(launch_emit2d_steps(g, h->plane_wide[e % 3] != 0, h->mring, h->cring, h->oring, od, &dctl->status, dctl->cnt, h->s));
   h->emitted = h->total_after[e];
   return FTK_OK;
 }

@@ -91,6 +91,13 @@ __device__ __forceinline__ unsigned sos2_positive<float>(float a0, float a1, flo
   return d != 0.0 ? r : seq;
 }
 
+// The same on values already converted to binary64 (exact integers below 2^24).
+__device__ __forceinline__ unsigned sos2_positive_d(double a0, double a1, double b0, double b1) {
+  const double d = __builtin_fma(a0, b1, -(a1 * b0));
+  const unsigned seq = (b1 != 0.0) ? (b1 > 0.0) : ((b0 != 0.0) ? (b0 < 0.0) : ((a1 != 0.0) ? (a1 < 0.0) : 0u));
+  return d != 0.0 ? (unsigned)(d > 0.0) : seq;
+}
+
 // Wide path: 64-bit components below 2^62, 128-bit products.
 template <>
 __device__ __forceinline__ unsigned sos2_positive<long long>(long long a0, long long a1, long long b0, long long b1) {

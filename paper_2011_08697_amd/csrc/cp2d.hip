@@ -45,6 +45,25 @@ struct QType<true> {
 
 constexpr float kNarrow2 = 16777216.0f;  // 2^24
 
+// Bit-gather tables for the 12 triangle tests: t[0][w] bit k = edge-word bit (M1 - 1) (edge v0 v1), t[1][w] bit k =
+// bit (M1|M2 - 1) (edge v0 v2), t[1 + n][w] bit k = bit (M2 - 1) for the types with M1 = n (edge v1 v2, read from
+// the word of the neighbour p + e(n)).
+struct Tri2Lut {
+  unsigned short t[8][128];
+};
+constexpr Tri2Lut build_tri2_lut() {
+  Tri2Lut r{};
+  for (int w = 0; w < 128; ++w)
+    for (int k = 0; k < 12; ++k) {
+      const int m1 = kTri2.m[k][0], m2 = kTri2.m[k][1];
+      if ((w >> (m1 - 1)) & 1) r.t[0][w] |= (unsigned short)(1u << k);
+      if ((w >> ((m1 | m2) - 1)) & 1) r.t[1][w] |= (unsigned short)(1u << k);
+      if ((w >> (m2 - 1)) & 1) r.t[1 + m1][w] |= (unsigned short)(1u << k);
+    }
+  return r;
+}
+constexpr Tri2Lut kTri2Lut = build_tri2_lut();
+
 template <bool WIDE>
 __device__ __forceinline__ typename QType<WIDE>::T to_q(float r, unsigned& st) {
   if (!WIDE) {
@@ -176,6 +195,31 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
     }
   };
 
+  // Narrow variant: one pass per position computes the ordinal edges of step t+1 (masks x, y, xy) and the interval
+  // edges t -> t+1 (masks t, xt, yt, xyt) from five vertex vectors converted to binary64 once.
+  auto fused_edges = [&](int par) {
+    const int nxp = par ^ 1;
+    for (int e = tid; e < EH * EW; e += 256) {
+      const int ly = e / EW, lx = e - ly * EW;
+      const int qa = ly * QW + lx;
+      const double a0 = (double)qs[par][0][qa], a1 = (double)qs[par][1][qa];
+      const double b0 = (double)qs[nxp][0][qa], b1 = (double)qs[nxp][1][qa];
+      const double c0 = (double)qs[nxp][0][qa + 1], c1 = (double)qs[nxp][1][qa + 1];
+      const double d0 = (double)qs[nxp][0][qa + QW], d1 = (double)qs[nxp][1][qa + QW];
+      const double f0 = (double)qs[nxp][0][qa + QW + 1], f1 = (double)qs[nxp][1][qa + QW + 1];
+      const unsigned o = sos2_positive_d(b0, b1, c0, c1) | (sos2_positive_d(b0, b1, d0, d1) << 1) |
+                         (sos2_positive_d(b0, b1, f0, f1) << 2);
+      const unsigned w = (sos2_positive_d(a0, a1, b0, b1) << 3) | (sos2_positive_d(a0, a1, c0, c1) << 4) |
+                         (sos2_positive_d(a0, a1, d0, d1) << 5) | (sos2_positive_d(a0, a1, f0, f1) << 6);
+      ew[nxp][e] = (uint8_t)o;
+      ew[par][e] |= (uint8_t)w;
+    }
+  };
+
+  // triangle lookup tables (LDS copy of the compile-time tables)
+  __shared__ unsigned short s_lut[8][128];
+  for (int i = tid; i < 8 * 128; i += 256) s_lut[i >> 7][i & 127] = kTri2Lut.t[i >> 7][i & 127];
+
   // prologue: plane t0
   load_plane(t0);
   __syncthreads();
@@ -194,8 +238,12 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
       __syncthreads();
       quantise_plane(nxp);
       __syncthreads();
-      ordinal_edges(nxp);
-      interval_edges(par);
+      if constexpr (!WIDE) {
+        fused_edges(par);
+      } else {
+        ordinal_edges(nxp);
+        interval_edges(par);
+      }
     }
     __syncthreads();
 
@@ -207,24 +255,15 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
         const int a = ly * EW + lane;
         // word of the anchor and of its neighbours p + e(M1): plane t for M1 in {x, y, xy}, plane t+1 (ordinal
         // bits only) for M1 in {t, xt, yt}
-        unsigned W[7];
-        W[0] = ew[par][a];
-        W[1] = ew[par][a + 1];
-        W[2] = ew[par][a + EW];
-        W[3] = ew[par][a + EW + 1];
-        W[4] = has_next ? ew[nxp][a] : 0u;
-        W[5] = has_next ? ew[nxp][a + 1] : 0u;
-        W[6] = has_next ? ew[nxp][a + EW] : 0u;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          const int m1 = kTri2.m[k][0], m2 = kTri2.m[k][1];
-          // sides opposite v0, v1, v2: edges (v1 v2) = (p + e(M1), M2), (v0 v2) = (p, M1|M2), (v0 v1) = (p, M1);
-          // cofactor signs are +S(v1v2), -S(v0v2), +S(v0v1): punctured iff S(v1v2) = S(v0v1) != S(v0v2)
-          const unsigned e0 = (W[m1] >> (m2 - 1)) & 1u;
-          const unsigned e1 = (W[0] >> ((m1 | m2) - 1)) & 1u;
-          const unsigned e2 = (W[0] >> (m1 - 1)) & 1u;
-          m |= ((e0 == e2) & (e1 != e0)) << k;
-        }
+        // sides opposite v0, v1, v2 of triangle (M1, M2): edges (v1 v2) = (p + e(M1), M2), (v0 v2) = (p, M1|M2),
+        // (v0 v1) = (p, M1); cofactor signs +S(v1v2), -S(v0v2), +S(v0v1): punctured iff S(v1v2) = S(v0v1) != S(v0v2).
+        // The 12 tests run bit-parallel: E0/E1/E2 gather, for every type, the sign bit of its edge opposite
+        // v0/v1/v2 through 128-entry tables indexed by the 7-bit edge words.
+        const unsigned W0 = ew[par][a];
+        unsigned E0 = s_lut[2][ew[par][a + 1]] | s_lut[3][ew[par][a + EW]] | s_lut[4][ew[par][a + EW + 1]];
+        if (has_next) E0 |= s_lut[5][ew[nxp][a]] | s_lut[6][ew[nxp][a + 1]] | s_lut[7][ew[nxp][a + EW]];
+        const unsigned E1 = s_lut[1][W0], E2 = s_lut[0][W0];
+        m = ~(E0 ^ E2) & (E1 ^ E0) & 0xFFFu;
         unsigned valid = 0xFFFu;
         if (gx == nx - 1) valid &= ~kUseX;
         if (gy == ny - 1) valid &= ~kUseY;
@@ -399,27 +438,28 @@ __device__ __forceinline__ unsigned long long block_sum256(unsigned long long v,
 
 template <int TY, bool WIDE>
 __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int by, int bz,
-                                            const uint16_t* __restrict__ masks, const long long* __restrict__ seg_off,
-                                            const Out2& o, unsigned* __restrict__ status,
+                                            const uint16_t* __restrict__ masks, const int* __restrict__ seg_cnt,
+                                            const long long* __restrict__ seg_off, const Out2& o,
+                                            unsigned* __restrict__ status,
                                             unsigned long long* __restrict__ cnt,
                                             unsigned long long* __restrict__ work_cnt) {
   constexpr int GW = TX + 3, GH = TY + 3;  // vector field: x0-1 .. x0+TX+1, y0-1 .. y0+TY+1
   constexpr int FW = TX + 5, FH = TY + 5;  // scalar field: x0-2 .. x0+TX+2
   constexpr int CAP = 1792;                // local union-find capacity (hits)
-  constexpr int MAXTT = 32;
+  constexpr int MAXTT = kEmitTT;           // step tables (TT <= kEmitTT)
   __shared__ float fs[FH * FW];
   __shared__ float2 gs[2][GH * GW];
   __shared__ unsigned short s_ex[TY][64];
   __shared__ unsigned short s_m[TY][64];
-  __shared__ unsigned s_rowtot[TY], s_rowbase[TY];
   __shared__ unsigned short nbm[4][7][64];
   __shared__ unsigned nbo[4][7][64];
   __shared__ unsigned char s_lane[4][12 * 64];  // hit j of the current row -> anchor lane
   __shared__ unsigned lpar[CAP];
   __shared__ unsigned lglob[CAP];
-  __shared__ unsigned lbase[MAXTT][TY];  // local id of the first hit of (chunk step, row)
-  __shared__ unsigned segb[MAXTT][TY];   // global hit index of the first hit of (chunk step, row)
+  __shared__ unsigned lbase[MAXTT][TY];  // local id of the first hit of (step t - t0, row)
+  __shared__ unsigned s_rc[MAXTT][TY], s_ro[MAXTT][TY];  // hits and first hit index of (step t - t0, row)
   __shared__ int s_chunk_t0, s_chunk_n, s_flush, s_global, s_plane_lbase, s_plane_total;
+  __shared__ int s_have[2];  // step held by each field buffer (-1: none)
   __shared__ uint2 s_stage[kEdgeStage];
   __shared__ int s_stage_n;
   __shared__ unsigned long long s_stage_base;
@@ -502,13 +542,33 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
     s_chunk_t0 = t0;
     s_chunk_n = 0;
     s_stage_n = 0;
+    s_have[0] = s_have[1] = -1;
   }
-  load_plane(t0, t0 & 1);
+  // hit counts and offsets of this tile's row segments for all its steps, read once: empty steps are skipped
+  // without touching their masks
+  for (int i = tid; i < (t1 - t0) * TY; i += 256) {
+    const int dt = i / TY, r = i - dt * TY, y = y0 + r;
+    unsigned c = 0, b = 0;
+    if (y < ny) {
+      const long long k = ((long long)mpl(g, t0 + dt) * ny + y) * nxt + bx;
+      c = (unsigned)seg_cnt[k];
+      b = (unsigned)seg_off[k];
+    }
+    s_rc[dt][r] = c;
+    s_ro[dt][r] = b;
+  }
+  __syncthreads();
+
   for (int t = t0; t < t1; ++t) {
     const int par = t & 1;
+    {
+      unsigned tot = 0;
+#pragma unroll
+      for (int r = 0; r < TY; ++r) tot += s_rc[t - t0][r];
+      if (tot == 0) continue;  // uniform
+    }
     __syncthreads();
     if (s_stage_n > kEdgeStage / 2) drain();
-    if (t + 1 < nt) load_plane(t + 1, par ^ 1);
 
     // row masks, prefixes and totals of this step
     for (int ly = wave; ly < TY; ly += 4) {
@@ -519,15 +579,11 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       const unsigned incl = wave_incl_scan(c);
       s_m[ly][lane] = (unsigned short)m;
       s_ex[ly][lane] = (unsigned short)(incl - c);
-      if (lane == 63) {
-        s_rowtot[ly] = incl;
-        s_rowbase[ly] = y < ny ? (unsigned)seg_off[((long long)mpl(g, t) * ny + y) * nxt + bx] : 0u;
-      }
     }
     __syncthreads();
     if (tid == 0) {
       unsigned tot = 0;
-      for (int r = 0; r < TY; ++r) tot += s_rowtot[r];
+      for (int r = 0; r < TY; ++r) tot += s_rc[t - t0][r];
       s_plane_total = (int)tot;
       s_flush = (s_chunk_n > 0 && (s_chunk_n + (int)tot > CAP || t - s_chunk_t0 >= MAXTT)) ? 1 : 0;
     }
@@ -553,9 +609,8 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
         s_plane_lbase = s_chunk_n;
         unsigned run = (unsigned)s_chunk_n;
         for (int r = 0; r < TY; ++r) {
-          lbase[t - s_chunk_t0][r] = run;
-          segb[t - s_chunk_t0][r] = s_rowbase[r];
-          run += s_rowtot[r];
+          lbase[t - t0][r] = run;
+          run += s_rc[t - t0][r];
         }
         s_chunk_n = (int)run;
       }
@@ -563,22 +618,34 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
     __syncthreads();
     const bool plane_global = s_global != 0;
     const int chunk_t0 = s_chunk_t0;
+    if (s_plane_total == 0) continue;  // uniform: nothing anchored in this tile at this step
     if (!plane_global)
       for (int i = tid; i < s_plane_total; i += 256) lpar[s_plane_lbase + i] = (unsigned)(s_plane_lbase + i);
+    // the vector field of steps t and t+1, loaded only for steps that hold hits
+    if (s_have[par] != t) {
+      load_plane(t, par);
+      __syncthreads();
+      if (tid == 0) s_have[par] = t;
+    }
+    if (t + 1 < nt && s_have[par ^ 1] != t + 1) {
+      load_plane(t + 1, par ^ 1);
+      __syncthreads();
+      if (tid == 0) s_have[par ^ 1] = t + 1;
+    }
     __syncthreads();
 
     for (int ly = wave; ly < TY; ly += 4) {
       const int y = y0 + ly;
       if (y >= ny) break;
-      const unsigned total = s_rowtot[ly];
+      const unsigned total = s_rc[t - t0][ly];
       if (total == 0) continue;
       const int x = x0 + lane;
       const bool in = x < nx;
       const long long gidx = (long long)mpl(g, t) * plane + (long long)y * nx + x;  // mask index
       const unsigned m = s_m[ly][lane];
       const unsigned ex = s_ex[ly][lane];
-      const unsigned base = s_rowbase[ly];
-      const unsigned row_lbase = plane_global ? 0u : lbase[t - chunk_t0][ly];
+      const unsigned base = s_ro[t - t0][ly];
+      const unsigned row_lbase = plane_global ? 0u : lbase[t - t0][ly];
 
       // neighbour masks and first-hit indices (wavefront-private LDS slots); hit -> lane map
       {
@@ -825,7 +892,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           // smaller partners are anchored at p (same row), p - x, p - y or p - t; the link stays local when that
           // anchor lies in this tile and this chunk
           auto link = [&](unsigned other, int sl) -> bool {
-            int prow = ly, pstep = t - chunk_t0;
+            int prow = ly, pstep = t - t0;
             bool local = true;
             if (sl == NB_MX) {
               local = L > 0;
@@ -834,10 +901,10 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
               prow = ly - 1;
             } else if (sl == NB_MT) {
               local = t - 1 >= chunk_t0;
-              pstep = t - 1 - chunk_t0;
+              pstep = t - 1 - t0;
             }
             if (!local) return true;
-            lunite(lpar, li, lbase[pstep][prow] + (other - segb[pstep][prow]));
+            lunite(lpar, li, lbase[pstep][prow] + (other - s_ro[pstep][prow]));
             return false;
           };
           if (ns > 0) g0 = link(sm0, sl0);
@@ -865,9 +932,11 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
 
 template <int TY, bool WIDE>
 __global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* __restrict__ masks,
-                                              const long long* __restrict__ seg_off, Out2 o,
-                                              unsigned* __restrict__ status, unsigned long long* __restrict__ cnt) {
-  emit2d_tile<TY, WIDE>(g, TT, blockIdx.x, blockIdx.y, blockIdx.z, masks, seg_off, o, status, cnt, &cnt[CNT_WORK]);
+                                              const int* __restrict__ seg_cnt, const long long* __restrict__ seg_off,
+                                              Out2 o, unsigned* __restrict__ status,
+                                              unsigned long long* __restrict__ cnt) {
+  emit2d_tile<TY, WIDE>(g, TT, blockIdx.x, blockIdx.y, blockIdx.z, masks, seg_cnt, seg_off, o, status, cnt,
+                        &cnt[CNT_WORK]);
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -926,22 +995,21 @@ __global__ __launch_bounds__(256) void emit2d_batched(const Series2* __restrict_
     const int local = it - prefix[s];
     const int tx = g.nxt, tyn = (g.ny + TY - 1) / TY;
     const int bx = local % tx, by = (local / tx) % tyn, bz = local / (tx * tyn);
-    if (S[s].wide)
-      emit2d_tile<TY, true>(g, TT, bx, by, bz, S[s].masks, S[s].seg_off, o, status, S[s].cnt, work_cnt);
-    else
-      emit2d_tile<TY, false>(g, TT, bx, by, bz, S[s].masks, S[s].seg_off, o, status, S[s].cnt, work_cnt);
+    emit2d_tile<TY, WIDE>(g, TT, bx, by, bz, S[s].masks, S[s].seg_cnt, S[s].seg_off, o, status, S[s].cnt,
+                          work_cnt);
   }
 }
 
 // Emission of single steps (streaming): one step per launch, local union-find per step.
-hipError_t launch_emit2d_steps(const Grid2& g, bool wide, const uint16_t* masks, const long long* seg_off,
-                               const Out2& o, unsigned* status, unsigned long long* cnt, hipStream_t s) {
+hipError_t launch_emit2d_steps(const Grid2& g, bool wide, const uint16_t* masks, const int* seg_cnt,
+                               const long long* seg_off, const Out2& o, unsigned* status, unsigned long long* cnt,
+                               hipStream_t s) {
   constexpr int TYE = 8;
   dim3 grid((unsigned)g.nxt, (unsigned)((g.ny + TYE - 1) / TYE), (unsigned)(g.t_end - g.t_begin));
   if (wide)
-    emit2d<TYE, true><<<grid, 256, 0, s>>>(g, 1, masks, seg_off, o, status, cnt);
+    emit2d<TYE, true><<<grid, 256, 0, s>>>(g, 1, masks, seg_cnt, seg_off, o, status, cnt);
   else
-    emit2d<TYE, false><<<grid, 256, 0, s>>>(g, 1, masks, seg_off, o, status, cnt);
+    emit2d<TYE, false><<<grid, 256, 0, s>>>(g, 1, masks, seg_cnt, seg_off, o, status, cnt);
   return hipGetLastError();
 }
 
@@ -956,11 +1024,14 @@ hipError_t launch_detect2d_batched(const Series2* S, const int* prefix, int nser
   return hipGetLastError();
 }
 
-hipError_t launch_emit2d_batched(const Series2* S, const int* prefix, int nser, int total_items, int* counter,
-                                 unsigned* status, unsigned long long* work_cnt, hipStream_t s) {
+hipError_t launch_emit2d_batched(const Series2* S, const int* prefix, int nser, int total_items, bool wide,
+                                 int* counter, unsigned* status, unsigned long long* work_cnt, hipStream_t s) {
   int blocks = total_items < 1536 ? total_items : 1536;
   if (blocks < 1) blocks = 1;
-  emit2d_batched<8, false><<<blocks, 256, 0, s>>>(S, prefix, nser, kEmitTT, counter, status, work_cnt);
+  if (wide)
+    emit2d_batched<8, true><<<blocks, 256, 0, s>>>(S, prefix, nser, kEmitTT, counter, status, work_cnt);
+  else
+    emit2d_batched<8, false><<<blocks, 256, 0, s>>>(S, prefix, nser, kEmitTT, counter, status, work_cnt);
   return hipGetLastError();
 }
 
@@ -989,15 +1060,16 @@ hipError_t launch_detect2d(const Grid2& g, int ty, int tt, bool wide, uint16_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_emit2d(const Grid2& g, bool wide, const uint16_t* masks, const long long* seg_off, long long nseg,
-                         const Out2& o, unsigned* status, unsigned long long* cnt, hipStream_t s) {
-  (void)nseg;
+hipError_t launch_emit2d(const Grid2& g, bool wide, const uint16_t* masks, const int* seg_cnt,
+                         const long long* seg_off, const Out2& o, unsigned* status, unsigned long long* cnt,
+                         hipStream_t s) {
   constexpr int TYE = 8, TTE = kEmitTT;
+  static_assert(TTE <= 32, "steps per emission tile exceed the tile's step tables");
   dim3 grid((unsigned)g.nxt, (unsigned)((g.ny + TYE - 1) / TYE), (unsigned)((g.t_end - g.t_begin + TTE - 1) / TTE));
   if (wide)
-    emit2d<TYE, true><<<grid, 256, 0, s>>>(g, TTE, masks, seg_off, o, status, cnt);
+    emit2d<TYE, true><<<grid, 256, 0, s>>>(g, TTE, masks, seg_cnt, seg_off, o, status, cnt);
   else
-    emit2d<TYE, false><<<grid, 256, 0, s>>>(g, TTE, masks, seg_off, o, status, cnt);
+    emit2d<TYE, false><<<grid, 256, 0, s>>>(g, TTE, masks, seg_cnt, seg_off, o, status, cnt);
   return hipGetLastError();
 }
 

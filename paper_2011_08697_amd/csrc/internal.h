@@ -64,15 +64,17 @@ struct Out3 {
 
 hipError_t launch_detect2d(const Grid2& g, int ty, int tt, bool wide, uint16_t* masks, int* seg_cnt,
                            unsigned* status, hipStream_t s);
-hipError_t launch_emit2d(const Grid2& g, bool wide, const uint16_t* masks, const long long* seg_off, long long nseg,
-                         const Out2& o, unsigned* status, unsigned long long* cnt, hipStream_t s);
+hipError_t launch_emit2d(const Grid2& g, bool wide, const uint16_t* masks, const int* seg_cnt,
+                         const long long* seg_off, const Out2& o, unsigned* status, unsigned long long* cnt,
+                         hipStream_t s);
 
-hipError_t launch_emit2d_steps(const Grid2& g, bool wide, const uint16_t* masks, const long long* seg_off,
-                               const Out2& o, unsigned* status, unsigned long long* cnt, hipStream_t s);
+hipError_t launch_emit2d_steps(const Grid2& g, bool wide, const uint16_t* masks, const int* seg_cnt,
+                               const long long* seg_off, const Out2& o, unsigned* status, unsigned long long* cnt,
+                               hipStream_t s);
 hipError_t launch_detect2d_batched(const Series2* S, const int* prefix, int nser, int total_items, int tt, bool wide,
                                    int* counter, unsigned* status, hipStream_t s);
-hipError_t launch_emit2d_batched(const Series2* S, const int* prefix, int nser, int total_items, int* counter,
-                                 unsigned* status, unsigned long long* work_cnt, hipStream_t s);
+hipError_t launch_emit2d_batched(const Series2* S, const int* prefix, int nser, int total_items, bool wide,
+                                 int* counter, unsigned* status, unsigned long long* work_cnt, hipStream_t s);
 // Labels for concatenated series: hit i belongs to the series s with gbase[s] <= i < gbase[s+1].
 hipError_t launch_uf_label_batched(unsigned* parent, const Series2* S, const unsigned* gbase, int nser, long long n,
                                    hipStream_t s);
