@@ -31,20 +31,22 @@ constexpr int kWave = 64;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Inclusive prefix sum over the 64 lanes with DPP moves (all lanes active): shifts by 1, 2, 4, 8 inside each row
+// of 16 lanes (lanes without a source add 0), then lane 15 of each row added to the next row and lane 31 to
+// rows 2 and 3.
 __device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    unsigned o = __shfl_up(v, d, kWave);
-    if (lane >= d) v += o;
-  }
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
 }
 
+// Sum over the 64 lanes (all lanes active), returned on every lane.
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
+  return (unsigned)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {

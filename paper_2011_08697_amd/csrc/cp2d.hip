@@ -445,17 +445,23 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
                                             unsigned long long* __restrict__ work_cnt) {
   constexpr int GW = TX + 3, GH = TY + 3;  // vector field: x0-1 .. x0+TX+1, y0-1 .. y0+TY+1
   constexpr int FW = TX + 5, FH = TY + 5;  // scalar field: x0-2 .. x0+TX+2
-  constexpr int CAP = 1792;                // local union-find capacity (hits)
+  constexpr int RW = TX + 2, RH = TY + 2;  // mask slices: x0-1 .. x0+TX, y0-1 .. y0+TY
+  constexpr int CAP = 3584;                // local union-find capacity (hits)
   constexpr int MAXTT = kEmitTT;           // step tables (TT <= kEmitTT)
   __shared__ float fs[FH * FW];
   __shared__ float2 gs[2][GH * GW];
-  __shared__ unsigned short s_ex[TY][64];
-  __shared__ unsigned short s_m[TY][64];
-  __shared__ unsigned short nbm[4][7][64];
-  __shared__ unsigned nbo[4][7][64];
-  __shared__ unsigned char s_lane[4][12 * 64];  // hit j of the current row -> anchor lane
+  // Mask slices of steps t-1, t, t+1 (ring slot = step mod 3) over the tile's anchors with a one-anchor halo: hit
+  // masks, first hit of each anchor relative to its row segment's first hit (left halo column: minus its hit
+  // count, right halo column: the segment's total), and the segments' first hit indices.
+  __shared__ unsigned short rm[3][RH * RW];
+  __shared__ short rx[3][RH * RW];
+  __shared__ unsigned rb[3][RH];
+  __shared__ int s_slice[3];  // step held by each ring slot
+  __shared__ unsigned short s_lane[4][12 * 64];  // hit j of the wave's current row -> anchor lane | type << 6
   __shared__ unsigned lpar[CAP];
-  __shared__ unsigned lglob[CAP];
+  // row segments of the current chunk in local-id order: first local id and first global hit index
+  __shared__ unsigned s_segl[MAXTT * TY], s_segg[MAXTT * TY];
+  __shared__ int s_nseg;
   __shared__ unsigned lbase[MAXTT][TY];  // local id of the first hit of (step t - t0, row)
   __shared__ unsigned s_rc[MAXTT][TY], s_ro[MAXTT][TY];  // hits and first hit index of (step t - t0, row)
   __shared__ int s_chunk_t0, s_chunk_n, s_flush, s_global, s_plane_lbase, s_plane_total;
@@ -520,12 +526,52 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
     }
   };
 
-  // write the parent of every hit of the chunk: the hit index of its local root
+  // mask slice of step s (zero outside [0, nt)) into ring slot (s + 3) % 3
+  auto load_slice = [&](int s) {
+    const int slot = (s + 3) % 3;
+    const bool ok = s >= 0 && s < nt;
+    const long long mp = ok ? (long long)mpl(g, s) : 0;
+    for (int e = tid; e < RH * RW; e += 256) {
+      const int r = e / RW, c = e - r * RW;
+      const int y = y0 - 1 + r, x = x0 - 1 + c;
+      unsigned m = 0;
+      if (ok && y >= 0 && y < ny && x >= 0 && x < nx) m = masks[(mp * ny + y) * nx + x];
+      rm[slot][e] = (unsigned short)m;
+    }
+    if (tid < RH) {
+      const int y = y0 - 1 + tid;
+      rb[slot][tid] = (ok && y >= 0 && y < ny) ? (unsigned)seg_off[(mp * ny + y) * nxt + bx] : 0u;
+    }
+  };
+  // per-anchor offsets of a loaded slice: one wavefront per row
+  auto scan_slice = [&](int slot) {
+    for (int r = wave; r < RH; r += 4) {
+      const unsigned c = __popc((unsigned)rm[slot][r * RW + 1 + lane]);
+      const unsigned incl = wave_incl_scan(c);
+      rx[slot][r * RW + 1 + lane] = (short)(incl - c);
+      if (lane == 63) rx[slot][r * RW + RW - 1] = (short)incl;
+      if (lane == 0) rx[slot][r * RW] = (short)(-(int)__popc((unsigned)rm[slot][r * RW]));
+    }
+  };
+
+  // write the parent of every hit of the chunk: the hit index of its local root.  One wavefront per row segment;
+  // the root's hit index comes from a binary search of the segment table.
   auto flush = [&]() {
-    const int n = s_chunk_n;
-    for (int li = tid; li < n; li += 256) {
-      unsigned r = lfind(lpar, (unsigned)li);
-      o.parent[lglob[li]] = lglob[r];
+    const int n = s_chunk_n, nseg = s_nseg;
+    for (int k = wave; k < nseg; k += 4) {
+      const unsigned l0 = s_segl[k], l1 = k + 1 < nseg ? s_segl[k + 1] : (unsigned)n, g0 = s_segg[k];
+      for (unsigned li = l0 + lane; li < l1; li += 64) {
+        const unsigned r = lfind(lpar, li);
+        int lo = 0, hi = nseg;  // last segment with s_segl <= r
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_segl[mid] <= r)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        o.parent[g0 + (li - l0)] = s_segg[lo] + (r - s_segl[lo]);
+      }
     }
   };
   // move the staged edges to the global list
@@ -541,8 +587,10 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   if (tid == 0) {
     s_chunk_t0 = t0;
     s_chunk_n = 0;
+    s_nseg = 0;
     s_stage_n = 0;
     s_have[0] = s_have[1] = -1;
+    s_slice[0] = s_slice[1] = s_slice[2] = -2;
   }
   // hit counts and offsets of this tile's row segments for all its steps, read once: empty steps are skipped
   // without touching their masks
@@ -568,19 +616,11 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       if (tot == 0) continue;  // uniform
     }
     __syncthreads();
+    // ring slots still to be filled for steps t-1, t, t+1 (read before any slot is rewritten)
+    const bool need_prev = s_slice[(t + 2) % 3] != t - 1;
+    const bool need_cur = s_slice[t % 3] != t;
+    const bool need_next = s_slice[(t + 1) % 3] != t + 1;
     if (s_stage_n > kEdgeStage / 2) drain();
-
-    // row masks, prefixes and totals of this step
-    for (int ly = wave; ly < TY; ly += 4) {
-      const int y = y0 + ly, x = x0 + lane;
-      unsigned m = 0;
-      if (y < ny && x < nx) m = masks[(long long)mpl(g, t) * plane + (long long)y * nx + x];
-      const unsigned c = __popc(m);
-      const unsigned incl = wave_incl_scan(c);
-      s_m[ly][lane] = (unsigned short)m;
-      s_ex[ly][lane] = (unsigned short)(incl - c);
-    }
-    __syncthreads();
     if (tid == 0) {
       unsigned tot = 0;
       for (int r = 0; r < TY; ++r) tot += s_rc[t - t0][r];
@@ -593,6 +633,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       __syncthreads();
       if (tid == 0) {
         s_chunk_n = 0;
+        s_nseg = 0;
         s_chunk_t0 = t;
       }
       __syncthreads();
@@ -603,15 +644,21 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
         s_global = 1;
         s_chunk_t0 = t + 1;
         s_chunk_n = 0;
+        s_nseg = 0;
       } else {
         s_global = 0;
         if (s_chunk_n == 0) s_chunk_t0 = t;
         s_plane_lbase = s_chunk_n;
         unsigned run = (unsigned)s_chunk_n;
+        int ns = s_nseg;
         for (int r = 0; r < TY; ++r) {
           lbase[t - t0][r] = run;
+          s_segl[ns] = run;
+          s_segg[ns] = s_ro[t - t0][r];
+          ++ns;
           run += s_rc[t - t0][r];
         }
+        s_nseg = ns;
         s_chunk_n = (int)run;
       }
     }
@@ -621,7 +668,19 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
     if (s_plane_total == 0) continue;  // uniform: nothing anchored in this tile at this step
     if (!plane_global)
       for (int i = tid; i < s_plane_total; i += 256) lpar[s_plane_lbase + i] = (unsigned)(s_plane_lbase + i);
-    // the vector field of steps t and t+1, loaded only for steps that hold hits
+    // mask slices of steps t-1, t, t+1 (only those not held yet), then the vector field of steps t and t+1
+    if (need_prev) load_slice(t - 1);
+    if (need_cur) load_slice(t);
+    if (need_next) load_slice(t + 1);
+    __syncthreads();
+    if (need_prev) scan_slice((t + 2) % 3);
+    if (need_cur) scan_slice(t % 3);
+    if (need_next) scan_slice((t + 1) % 3);
+    if (tid == 0) {
+      s_slice[(t + 2) % 3] = t - 1;
+      s_slice[t % 3] = t;
+      s_slice[(t + 1) % 3] = t + 1;
+    }
     if (s_have[par] != t) {
       load_plane(t, par);
       __syncthreads();
@@ -639,62 +698,26 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       if (y >= ny) break;
       const unsigned total = s_rc[t - t0][ly];
       if (total == 0) continue;
-      const int x = x0 + lane;
-      const bool in = x < nx;
-      const long long gidx = (long long)mpl(g, t) * plane + (long long)y * nx + x;  // mask index
-      const unsigned m = s_m[ly][lane];
-      const unsigned ex = s_ex[ly][lane];
       const unsigned base = s_ro[t - t0][ly];
       const unsigned row_lbase = plane_global ? 0u : lbase[t - t0][ly];
+      const int cur = t % 3;
 
-      // neighbour masks and first-hit indices (wavefront-private LDS slots); hit -> lane map
+      // hit -> (anchor lane, type) map of this row segment (wavefront-private)
       {
-        unsigned mxm = 0, mxo = 0, pxm = 0, pxo = 0;
-        if (lane > 0) {
-          mxm = s_m[ly][lane - 1];
-          mxo = base + s_ex[ly][lane - 1];
-        } else if (x > 0) {
-          mxm = masks[gidx - 1];
-          mxo = base - __popc(mxm);
+        const int a = (ly + 1) * RW + 1 + lane;
+        unsigned m = rm[cur][a];
+        unsigned k = (unsigned)rx[cur][a];
+        while (m) {
+          const unsigned ty = (unsigned)__ffs((int)m) - 1u;
+          m &= m - 1u;
+          s_lane[wave][k++] = (unsigned short)((unsigned)lane | (ty << 6));
         }
-        if (x + 1 < nx) {
-          if (lane < 63) {
-            pxm = s_m[ly][lane + 1];
-            pxo = base + s_ex[ly][lane + 1];
-          } else {
-            pxm = masks[gidx + 1];
-            pxo = base + total;
-          }
-        }
-        nbm[wave][NB_SELF][lane] = (unsigned short)m;
-        nbo[wave][NB_SELF][lane] = base + ex;
-        nbm[wave][NB_MX][lane] = (unsigned short)mxm;
-        nbo[wave][NB_MX][lane] = mxo;
-        nbm[wave][NB_PX][lane] = (unsigned short)pxm;
-        nbo[wave][NB_PX][lane] = pxo;
-        // neighbour row segment (step tt, row yy) at the same lanes
-        auto seg_nb = [&](int slot, int tt, int yy, bool ok) {
-          const long long mp = ok ? (long long)mpl(g, tt) : 0;
-          unsigned mm = (ok && in) ? masks[(mp * ny + yy) * nx + x] : 0u;
-          unsigned inc = wave_incl_scan(__popc(mm));
-          unsigned b = ok ? (unsigned)seg_off[(mp * ny + yy) * nxt + bx] : 0u;
-          nbm[wave][slot][lane] = (unsigned short)mm;
-          nbo[wave][slot][lane] = b + inc - __popc(mm);
-        };
-        seg_nb(NB_MY, t, y - 1, y > 0);
-        seg_nb(NB_PY, t, y + 1, y + 1 < ny);
-        seg_nb(NB_MT, t - 1, y, t > 0);
-        seg_nb(NB_PT, t + 1, y, t + 1 < nt);
-        const unsigned c_self = __popc(m);
-        for (unsigned k = 0; k < c_self; ++k) s_lane[wave][ex + k] = (unsigned char)lane;
       }
       wave_lds_sync();
 
       for (unsigned j = lane; j < total; j += 64) {
-        const int L = s_lane[wave][j];
-        unsigned mm = s_m[ly][L];
-        for (unsigned k = j - s_ex[ly][L]; k > 0; --k) mm &= mm - 1;
-        const int ty = __ffs(mm) - 1;
+        const unsigned ent = s_lane[wave][j];
+        const int L = (int)(ent & 63u), ty = (int)(ent >> 6);
         const unsigned idx = base + j;
         const int ax = x0 + L;
         const unsigned pk = s_pack[ty];
@@ -858,10 +881,14 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           for (int sdx = 0; sdx < 3; ++sdx) {
             const unsigned f = (w >> (4 + 7 * sdx)) & 127u;
             const int slot = f & 7, tt = f >> 3;
-            const unsigned um = nbm[wave][slot][L];
+            // ring slot, slice row and column of the neighbour anchor
+            const int rs = slot == NB_MT ? (t + 2) % 3 : (slot == NB_PT ? (t + 1) % 3 : cur);
+            const int rr = ly + 1 + (slot == NB_MY ? -1 : (slot == NB_PY ? 1 : 0));
+            const int rc = L + 1 + (slot == NB_MX ? -1 : (slot == NB_PX ? 1 : 0));
+            const unsigned um = rm[rs][rr * RW + rc];
             if ((um >> tt) & 1u) {
               ++found;
-              other = nbo[wave][slot][L] + __popc(um & ((1u << tt) - 1u));
+              other = rb[rs][rr] + (unsigned)(int)rx[rs][rr * RW + rc] + __popc(um & ((1u << tt) - 1u));
               oslot = slot;
             }
           }
@@ -888,7 +915,6 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           g1 = ns > 1;
         } else {
           const unsigned li = row_lbase + j;
-          lglob[li] = idx;
           // smaller partners are anchored at p (same row), p - x, p - y or p - t; the link stays local when that
           // anchor lies in this tile and this chunk
           auto link = [&](unsigned other, int sl) -> bool {
