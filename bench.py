@@ -115,6 +115,11 @@ def bench_batched(args, F, synth, dev):
     tb, nhb = timed(batched)
     tp, nhp = timed(plain)
     assert nhb == nhp
+    # kernel phases of one batched call (HIP events on the stream)
+    st = F.track_cp2d_batched(ts, profile=1)[0]["stats"]
+    torch.cuda.synchronize()
+    phases = {"detect2d": round(st["t_detect_ms"], 3), "scan": round(st["t_scan_ms"], 3),
+              "emit2d": round(st["t_emit_ms"], 3), "uf_label": round(st["t_link_ms"], 3)}
     line = {
         "metric": "spacetime simplices tested/s + HBM roofline frac; batched vs plain steps/s",
         "value": round(tested / tb, 1), "unit": "simplices/s", "n_gpus": 1, "steps": args.steps,
@@ -122,7 +127,8 @@ def bench_batched(args, F, synth, dev):
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": WORKLOADS["c3"], "series": len(fields), "time_steps_total": steps_total,
                    "vertices_total": int(sum(f.size for f in fields)), "n_hits": nhb, "generation_s": round(gen_s, 1)},
-        "batched": {"steps_per_s": round(steps_total / tb, 1), "ms_per_batch": round(tb * 1e3, 3)},
+        "batched": {"steps_per_s": round(steps_total / tb, 1), "ms_per_batch": round(tb * 1e3, 3),
+                    "phase_ms": phases},
         "plain": {"steps_per_s": round(steps_total / tp, 1), "ms_per_batch": round(tp * 1e3, 3)},
         "batched_over_plain": round(tp / tb, 3),
         "roofline": None, "cpu_baseline": None,

@@ -385,12 +385,47 @@ __device__ __forceinline__ void lunite(unsigned* lp, unsigned a, unsigned b) {
   }
 }
 
+// Union-find on the global parent array restricted to the hits of one workgroup's tile and slab: during emission
+// nothing outside the workgroup reads or writes these parents, so workgroup-scope atomics (served by the CU's own
+// caches) are coherent for them.
+__device__ __forceinline__ unsigned wg_load(const unsigned* p, unsigned i) {
+  return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ unsigned wg_find(unsigned* parent, unsigned x) {
+  unsigned p = wg_load(parent, x);
+  while (p != x) {
+    const unsigned gp = wg_load(parent, p);
+    if (gp != p) __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+__device__ __forceinline__ void wg_unite(unsigned* parent, unsigned a, unsigned b) {
+  unsigned ra = wg_find(parent, a), rb = wg_find(parent, b);
+  while (ra != rb) {
+    if (ra < rb) {
+      const unsigned t = ra;
+      ra = rb;
+      rb = t;
+    }
+    unsigned expected = ra;
+    if (__hip_atomic_compare_exchange_strong(parent + ra, &expected, rb, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+      return;
+    ra = wg_find(parent, expected);
+    rb = wg_find(parent, rb);
+  }
+}
+
 // Edge list staging: links that leave the tile/chunk are collected in LDS and appended to the global list in
 // batches (one global atomic per batch; same-address atomics serialise at one L2 channel).
 constexpr int kEdgeStage = 512;
 
-// Wave-aggregated append of (idx, partner) for the active lanes with want == true: into the LDS stage if it has
-// room, otherwise straight to the global list.
+// Wave-aggregated append of (idx, partner) for the active lanes with want == true: one LDS add reserves the
+// wave's slots; slots past the stage capacity go straight to the global list (one global add for them).
 __device__ __forceinline__ void append_edge(bool want, unsigned idx, unsigned partner, uint2* stage, int* stage_n,
                                             uint2* work, unsigned long long* counter) {
   const unsigned long long bal = __ballot(want);
@@ -398,29 +433,25 @@ __device__ __forceinline__ void append_edge(bool want, unsigned idx, unsigned pa
   const int lane = lane_id();
   const int leader = __ffsll((long long)bal) - 1;
   const int k = __popcll(bal);
-  int pos = -1;
+  int pos = 0;
+  if (lane == leader) pos = atomicAdd(stage_n, k);
+  pos = __builtin_amdgcn_readlane(pos, leader);
+  const int first_over = pos > kEdgeStage ? pos : kEdgeStage;  // first slot number routed to the global list
+  const int n_over = pos + k - first_over;
   unsigned long long gpos = 0;
-  if (lane == leader) {
-    int old = *(volatile int*)stage_n;
-    while (old + k <= kEdgeStage) {
-      int prev = atomicCAS(stage_n, old, old + k);
-      if (prev == old) {
-        pos = old;
-        break;
-      }
-      old = prev;
-    }
-    if (pos < 0) gpos = atomicAdd(counter, (unsigned long long)k);
+  if (n_over > 0) {
+    if (lane == leader) gpos = atomicAdd(counter, (unsigned long long)n_over);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)gpos, leader);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(gpos >> 32), leader);
+    gpos = ((unsigned long long)hi << 32) | lo;
   }
-  pos = __shfl(pos, leader, 64);
-  gpos = __shfl(gpos, leader, 64);
   if (want) {
-    const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+    const int slot = pos + __popcll(bal & ((1ull << lane) - 1ull));
     const uint2 e = make_uint2(idx, partner);
-    if (pos >= 0)
-      stage[pos + rank] = e;
+    if (slot < kEdgeStage)
+      stage[slot] = e;
     else
-      work[gpos + rank] = e;
+      work[gpos + (unsigned long long)(slot - first_over)] = e;
   }
 }
 
@@ -554,31 +585,75 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
     }
   };
 
-  // write the parent of every hit of the chunk: the hit index of its local root.  One wavefront per row segment;
-  // the root's hit index comes from a binary search of the segment table.
+  // Local root of x in the flushing chunk: a local id, or CAP + i once the set has been attached to the set of an
+  // earlier chunk of this tile whose global root sits in stage slot i.
+  auto lroot = [&](unsigned x) -> unsigned {
+    for (;;) {
+      const unsigned p = lpar[x];
+      if (p == x || p >= (unsigned)CAP) return p;
+      x = p;
+    }
+  };
+  // local id of a hit of the current chunk from its global index (segments are in increasing global order)
+  auto seg_search = [&](const unsigned* key, unsigned v) -> int {
+    int lo = 0, hi = s_nseg;  // last segment with key <= v
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (key[mid] <= v)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    return lo;
+  };
+  // Write the parent of every hit of the chunk.  Links staged as (earlier partner, hit) go from the chunk's first
+  // step to an earlier chunk of this tile, whose parents are final: the hit's local set is attached to the
+  // partner's global root (two such roots met by one set are united in place), and each hit of the chunk gets its
+  // set's global root, or the hit index of its local root.  Attached links stay in the stage as no-op (R, R).
   auto flush = [&]() {
+    __syncthreads();  // parents written so far by this workgroup are visible to it
     const int n = s_chunk_n, nseg = s_nseg;
+    const int nst = s_stage_n < kEdgeStage ? s_stage_n : kEdgeStage;
+    for (int i = tid; i < nst; i += 256) {
+      const uint2 e = s_stage[i];
+      if (e.x >= e.y) continue;  // (hit, smaller partner): for the global list
+      const unsigned R = wg_find(o.parent, e.x);
+      s_stage[i] = make_uint2(R, R);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      const int k = seg_search(s_segg, e.y);
+      unsigned r = lroot(s_segl[k] + (e.y - s_segg[k]));
+      for (;;) {
+        if (r >= (unsigned)CAP) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          wg_unite(o.parent, R, s_stage[r - CAP].x);
+          break;
+        }
+        const unsigned old = atomicCAS(&lpar[r], r, (unsigned)(CAP + i));
+        if (old == r) break;
+        r = old >= (unsigned)CAP ? old : lroot(old);
+      }
+    }
+    __syncthreads();
     for (int k = wave; k < nseg; k += 4) {
       const unsigned l0 = s_segl[k], l1 = k + 1 < nseg ? s_segl[k + 1] : (unsigned)n, g0 = s_segg[k];
       for (unsigned li = l0 + lane; li < l1; li += 64) {
-        const unsigned r = lfind(lpar, li);
-        int lo = 0, hi = nseg;  // last segment with s_segl <= r
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_segl[mid] <= r)
-            lo = mid;
-          else
-            hi = mid;
+        const unsigned r = lroot(li);
+        unsigned target;
+        if (r >= (unsigned)CAP) {
+          target = s_stage[r - CAP].x;
+        } else {
+          const int kr = seg_search(s_segl, r);
+          target = s_segg[kr] + (r - s_segl[kr]);
         }
-        o.parent[g0 + (li - l0)] = s_segg[lo] + (r - s_segl[lo]);
+        o.parent[g0 + (li - l0)] = target;
       }
     }
   };
   // move the staged edges to the global list
   auto drain = [&]() {
-    if (tid == 0) s_stage_base = s_stage_n ? atomicAdd(work_cnt, (unsigned long long)s_stage_n) : 0ull;
+    const int n = s_stage_n < kEdgeStage ? s_stage_n : kEdgeStage;  // slots past the capacity went to the list
+    if (tid == 0) s_stage_base = n ? atomicAdd(work_cnt, (unsigned long long)n) : 0ull;
     __syncthreads();
-    const int n = s_stage_n;
     for (int i = tid; i < n; i += 256) o.work[s_stage_base + i] = s_stage[i];
     __syncthreads();
     if (tid == 0) s_stage_n = 0;
@@ -620,7 +695,6 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
     const bool need_prev = s_slice[(t + 2) % 3] != t - 1;
     const bool need_cur = s_slice[t % 3] != t;
     const bool need_next = s_slice[(t + 1) % 3] != t + 1;
-    if (s_stage_n > kEdgeStage / 2) drain();
     if (tid == 0) {
       unsigned tot = 0;
       for (int r = 0; r < TY; ++r) tot += s_rc[t - t0][r];
@@ -638,6 +712,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       }
       __syncthreads();
     }
+    if (s_stage_n > kEdgeStage / 2) drain();
     if (tid == 0) {
       const int tot = s_plane_total;
       if (tot > CAP) {  // too many hits for the local structure: this step links through the global list only
@@ -908,16 +983,18 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           }
         }
         n_linked += ns;
-        bool g0 = false, g1 = false;
+        int c0 = 0, c1 = 0;
         if (plane_global) {
           o.parent[idx] = idx;
-          g0 = ns > 0;
-          g1 = ns > 1;
+          c0 = ns > 0 ? 1 : 0;
+          c1 = ns > 1 ? 1 : 0;
         } else {
           const unsigned li = row_lbase + j;
           // smaller partners are anchored at p (same row), p - x, p - y or p - t; the link stays local when that
           // anchor lies in this tile and this chunk
-          auto link = [&](unsigned other, int sl) -> bool {
+          // 0: united here; 1: global list; 2: partner in an earlier chunk of this tile (staged as
+          // (partner, hit) and attached at this chunk's flush)
+          auto link = [&](unsigned other, int sl) -> int {
             int prow = ly, pstep = t - t0;
             bool local = true;
             if (sl == NB_MX) {
@@ -926,18 +1003,18 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
               local = ly > 0;
               prow = ly - 1;
             } else if (sl == NB_MT) {
-              local = t - 1 >= chunk_t0;
+              if (t - 1 < chunk_t0) return t - 1 >= t0 ? 2 : 1;
               pstep = t - 1 - t0;
             }
-            if (!local) return true;
+            if (!local) return 1;
             lunite(lpar, li, lbase[pstep][prow] + (other - s_ro[pstep][prow]));
-            return false;
+            return 0;
           };
-          if (ns > 0) g0 = link(sm0, sl0);
-          if (ns > 1) g1 = link(sm1, sl1);
+          if (ns > 0) c0 = link(sm0, sl0);
+          if (ns > 1) c1 = link(sm1, sl1);
         }
-        append_edge(g0, idx, sm0, s_stage, &s_stage_n, o.work, work_cnt);
-        append_edge(g1, idx, sm1, s_stage, &s_stage_n, o.work, work_cnt);
+        append_edge(c0 != 0, c0 == 2 ? sm0 : idx, c0 == 2 ? idx : sm0, s_stage, &s_stage_n, o.work, work_cnt);
+        append_edge(c1 != 0, c1 == 2 ? sm1 : idx, c1 == 2 ? idx : sm1, s_stage, &s_stage_n, o.work, work_cnt);
       }
       wave_lds_sync();
     }

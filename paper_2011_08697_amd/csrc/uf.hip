@@ -1,9 +1,9 @@
 // uf.hip -- GPU union-find for trajectory stitching (Alg. 1 pass 2: unite the punctured sides of every cell).
 //
-// The emission kernels initialise parent[i] to the smallest of i and its (at most two) partner hits, which already
-// encodes every link except, for hits whose two partners are both smaller, the link to the larger partner; those
-// links are queued and united here with compare-and-swap hooking (larger root under smaller root).  Labels are the
-// face id of each set's root, i.e. the smallest face id of the trajectory.
+// The emission kernels unite the links inside each tile (and, through the parents of earlier chunks, along time
+// within the tile's slab) and leave every hit's parent pointing at a smaller hit of its set; links that cross
+// tiles or slabs are queued, and are united here with compare-and-swap hooking (larger root under smaller root).
+// Labels are the face id of each set's root, i.e. the smallest face id of the trajectory.
 #include "common.h"
 #include "internal.h"
 
