@@ -182,22 +182,22 @@ __device__ __forceinline__ int classify2_fp32(const float mu[3], const float J[3
   }
   float smax = fmaxf(fmaxf(S[0], S[1]), fmaxf(S[2], S[3]));
   if (!(smax > 1e-15f) || !(smax < 1e15f)) return -1;  // keep the bounds away from under/overflow
-  float e32[4], e64[4], M32[4], M64[4];
+  // One bound covers both evaluations: with e >= e32 + e64, M = |Jc| + e (>= the magnitudes of the binary32,
+  // binary64 and exact entries) and u >= u32 + u64, bound_det2 dominates the sum of the two separate bounds term
+  // by term.  (u32 (1 + 1e-4) exceeds u32 + u64 = u32 (1 + 2^-29) with room for the rounding of the constants.)
+  constexpr float kU = kU32 * 1.0001f, kE = 10.0f * kU;
+  float e[4], M[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    e32[e] = 10.0f * kU32 * S[e];
-    e64[e] = 10.0f * kU64 * S[e];
-    M32[e] = fabsf(Jc[e]) + e32[e];
-    M64[e] = M32[e] + e64[e];
+  for (int q = 0; q < 4; ++q) {
+    e[q] = kE * S[q];
+    M[q] = fabsf(Jc[q]) + e[q];
   }
   float p1 = Jc[0] * Jc[3];
   float p2 = Jc[1] * Jc[2];
   float det = p1 - p2;
-  float Edet = bound_det2(M32[0], M32[1], M32[2], M32[3], e32[0], e32[1], e32[2], e32[3], kU32) +
-               bound_det2(M64[0], M64[1], M64[2], M64[3], e64[0], e64[1], e64[2], e64[3], kU64);
+  float Edet = bound_det2(M[0], M[1], M[2], M[3], e[0], e[1], e[2], e[3], kU);
   float tr = Jc[0] + Jc[3];
-  float Etr = (e32[0] + e32[3] + kU32 * (M32[0] + M32[3])) * 1.01f +
-              (e64[0] + e64[3] + kU64 * (M64[0] + M64[3])) * 1.01f;
+  float Etr = (e[0] + e[3] + kU * (M[0] + M[3])) * 1.01f;
   bool det_ok = fabsf(det) > Edet;
   bool tr_ok = fabsf(tr) > Etr;
   if (!det_ok) return -1;
@@ -208,9 +208,9 @@ __device__ __forceinline__ int classify2_fp32(const float mu[3], const float J[3
   float t2 = tr * tr;
   float d4 = 4.0f * det;
   float disc = t2 - d4;
-  float Edisc32 = (2.0f * T * Etr + 4.0f * Edet + kU32 * (2.02f * T * T + 4.02f * Dm)) * 1.01f;
-  float Edisc64 = (2.0f * T * Etr + 4.0f * Edet + kU64 * (2.02f * T * T + 4.02f * Dm)) * 1.01f;
-  if (!(fabsf(disc) > Edisc32 + Edisc64)) return -1;
+  // the discriminant's bound for the two evaluations, summed (Etr and Edet already cover both)
+  float Edisc = (2.0f * (2.0f * T * Etr + 4.0f * Edet) + kU * (2.02f * T * T + 4.02f * Dm)) * 1.01f;
+  if (!(fabsf(disc) > Edisc)) return -1;
   if (tr < 0) return disc >= 0 ? T_SINK : T_AFOCUS;
   return disc >= 0 ? T_SOURCE : T_RFOCUS;
 }

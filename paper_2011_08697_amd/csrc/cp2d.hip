@@ -422,7 +422,7 @@ __device__ __forceinline__ void wg_unite(unsigned* parent, unsigned a, unsigned 
 
 // Edge list staging: links that leave the tile/chunk are collected in LDS and appended to the global list in
 // batches (one global atomic per batch; same-address atomics serialise at one L2 channel).
-constexpr int kEdgeStage = 512;
+constexpr int kEdgeStage = 256;
 
 // Wave-aggregated append of (idx, partner) for the active lanes with want == true: one LDS add reserves the
 // wave's slots; slots past the stage capacity go straight to the global list (one global add for them).
@@ -477,9 +477,8 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   constexpr int GW = TX + 3, GH = TY + 3;  // vector field: x0-1 .. x0+TX+1, y0-1 .. y0+TY+1
   constexpr int FW = TX + 5, FH = TY + 5;  // scalar field: x0-2 .. x0+TX+2
   constexpr int RW = TX + 2, RH = TY + 2;  // mask slices: x0-1 .. x0+TX, y0-1 .. y0+TY
-  constexpr int CAP = 3584;                // local union-find capacity (hits)
+  constexpr int CAP = 2048;                // local union-find capacity (hits)
   constexpr int MAXTT = kEmitTT;           // step tables (TT <= kEmitTT)
-  __shared__ float fs[FH * FW];
   __shared__ float2 gs[2][GH * GW];
   // Mask slices of steps t-1, t, t+1 (ring slot = step mod 3) over the tile's anchors with a one-anchor halo: hit
   // masks, first hit of each anchor relative to its row segment's first hit (left halo column: minus its hit
@@ -488,9 +487,13 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   __shared__ short rx[3][RH * RW];
   __shared__ unsigned rb[3][RH];
   __shared__ int s_slice[3];  // step held by each ring slot
-  __shared__ unsigned short s_lane[4][12 * 64];  // hit j of the wave's current row -> anchor lane | type << 6
+  // hit j of the wave's current row -> anchor lane | type << 6; between hit phases the same LDS holds the scalar
+  // field of a plane being loaded
+  __shared__ __align__(16) unsigned short s_lane[4][12 * 64];
+  static_assert(FH * FW * sizeof(float) <= sizeof(s_lane), "scalar plane staging exceeds the hit map");
+  float* const fs = reinterpret_cast<float*>(&s_lane[0][0]);
   __shared__ unsigned lpar[CAP];
-  // row segments of the current chunk in local-id order: first local id and first global hit index
+  // non-empty row segments of the current chunk in local-id order: first local id and first global hit index
   __shared__ unsigned s_segl[MAXTT * TY], s_segg[MAXTT * TY];
   __shared__ int s_nseg;
   __shared__ unsigned lbase[MAXTT][TY];  // local id of the first hit of (step t - t0, row)
@@ -728,10 +731,13 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
         int ns = s_nseg;
         for (int r = 0; r < TY; ++r) {
           lbase[t - t0][r] = run;
-          s_segl[ns] = run;
-          s_segg[ns] = s_ro[t - t0][r];
-          ++ns;
-          run += s_rc[t - t0][r];
+          const unsigned c = s_rc[t - t0][r];
+          if (c) {  // non-empty segments only: both keys strictly increase (rows past the grid have no base)
+            s_segl[ns] = run;
+            s_segg[ns] = s_ro[t - t0][r];
+            ++ns;
+          }
+          run += c;
         }
         s_nseg = ns;
         s_chunk_n = (int)run;
@@ -938,19 +944,19 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
         // ---- pass 2 links: each of the (at most two) tetrahedra holding this triangle has exactly one other
         // punctured side.  Each link is recorded by its larger endpoint: inside this tile and chunk it goes to the
         // LDS union-find, otherwise to the global edge list.
+        // (branch-free: every neighbour lookup stays inside the ring slices)
         unsigned sm0 = 0, sm1 = 0;
-        int sl0 = -1, sl1 = -1;
+        int sl0 = 0, sl1 = 0;
         int ns = 0;
-        const int P3[3] = {ax, y, t};
-        const int N3[3] = {nx, ny, nt};
+        bool bad = false;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const unsigned w = s_cof[ty][k];
           const int rule = w & 3, axis = (w >> 2) & 3;
-          const int pa = axis == 0 ? P3[0] : (axis == 1 ? P3[1] : P3[2]);
-          const int Na = axis == 0 ? N3[0] : (axis == 1 ? N3[1] : N3[2]);
-          if ((rule == 2 && pa < 1) || (rule == 3 && pa + 1 > Na - 1)) continue;  // the cell leaves the grid
-          int found = 0, oslot = -1;
+          const int pa = axis == 0 ? ax : (axis == 1 ? y : t);
+          const int Na = axis == 0 ? nx : (axis == 1 ? ny : nt);
+          const bool exists = !((rule == 2 && pa < 1) || (rule == 3 && pa + 1 > Na - 1));  // the cell is in the grid
+          int found = 0, oslot = 0;
           unsigned other = 0;
 #pragma unroll
           for (int sdx = 0; sdx < 3; ++sdx) {
@@ -961,60 +967,48 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
             const int rr = ly + 1 + (slot == NB_MY ? -1 : (slot == NB_PY ? 1 : 0));
             const int rc = L + 1 + (slot == NB_MX ? -1 : (slot == NB_PX ? 1 : 0));
             const unsigned um = rm[rs][rr * RW + rc];
-            if ((um >> tt) & 1u) {
-              ++found;
-              other = rb[rs][rr] + (unsigned)(int)rx[rs][rr * RW + rc] + __popc(um & ((1u << tt) - 1u));
-              oslot = slot;
-            }
+            const unsigned hit = (um >> tt) & 1u;
+            const unsigned cand = rb[rs][rr] + (unsigned)(int)rx[rs][rr * RW + rc] + __popc(um & ((1u << tt) - 1u));
+            found += (int)hit;
+            other = hit ? cand : other;
+            oslot = hit ? slot : oslot;
           }
-          if (found != 1) {
-            st |= ST_INVARIANT;
-            continue;
-          }
-          if (other < idx) {
-            if (ns == 0) {
-              sm0 = other;
-              sl0 = oslot;
-            } else {
-              sm1 = other;
-              sl1 = oslot;
-            }
-            ++ns;
-          }
+          bad = bad || (exists && found != 1);
+          const bool take = exists && found == 1 && other < idx;
+          sm1 = (take && ns == 1) ? other : sm1;
+          sl1 = (take && ns == 1) ? oslot : sl1;
+          sm0 = (take && ns == 0) ? other : sm0;
+          sl0 = (take && ns == 0) ? oslot : sl0;
+          ns += take ? 1 : 0;
         }
+        if (bad) st |= ST_INVARIANT;
         n_linked += ns;
-        int c0 = 0, c1 = 0;
+        // link class of each smaller partner: 0 united here (anchor in this tile and chunk), 1 global list,
+        // 2 partner in an earlier chunk of this tile (staged as (partner, hit), attached at this chunk's flush);
+        // -1 none
+        int c0 = -1, c1 = -1;
         if (plane_global) {
           o.parent[idx] = idx;
-          c0 = ns > 0 ? 1 : 0;
-          c1 = ns > 1 ? 1 : 0;
+          c0 = ns > 0 ? 1 : -1;
+          c1 = ns > 1 ? 1 : -1;
         } else {
           const unsigned li = row_lbase + j;
-          // smaller partners are anchored at p (same row), p - x, p - y or p - t; the link stays local when that
-          // anchor lies in this tile and this chunk
-          // 0: united here; 1: global list; 2: partner in an earlier chunk of this tile (staged as
-          // (partner, hit) and attached at this chunk's flush)
-          auto link = [&](unsigned other, int sl) -> int {
-            int prow = ly, pstep = t - t0;
-            bool local = true;
-            if (sl == NB_MX) {
-              local = L > 0;
-            } else if (sl == NB_MY) {
-              local = ly > 0;
-              prow = ly - 1;
-            } else if (sl == NB_MT) {
-              if (t - 1 < chunk_t0) return t - 1 >= t0 ? 2 : 1;
-              pstep = t - 1 - t0;
-            }
-            if (!local) return 1;
-            lunite(lpar, li, lbase[pstep][prow] + (other - s_ro[pstep][prow]));
-            return 0;
+          auto link_class = [&](int sl) -> int {
+            if (sl == NB_MT && t - 1 < chunk_t0) return t - 1 >= t0 ? 2 : 1;
+            return ((sl == NB_MX && L == 0) || (sl == NB_MY && ly == 0)) ? 1 : 0;
           };
-          if (ns > 0) c0 = link(sm0, sl0);
-          if (ns > 1) c1 = link(sm1, sl1);
+          auto local_id = [&](unsigned other, int sl) -> unsigned {
+            const int prow = sl == NB_MY ? ly - 1 : ly;
+            const int pstep = (sl == NB_MT ? t - 1 : t) - t0;
+            return lbase[pstep][prow] + (other - s_ro[pstep][prow]);
+          };
+          c0 = ns > 0 ? link_class(sl0) : -1;
+          c1 = ns > 1 ? link_class(sl1) : -1;
+          if (c0 == 0) lunite(lpar, li, local_id(sm0, sl0));
+          if (c1 == 0) lunite(lpar, li, local_id(sm1, sl1));
         }
-        append_edge(c0 != 0, c0 == 2 ? sm0 : idx, c0 == 2 ? idx : sm0, s_stage, &s_stage_n, o.work, work_cnt);
-        append_edge(c1 != 0, c1 == 2 ? sm1 : idx, c1 == 2 ? idx : sm1, s_stage, &s_stage_n, o.work, work_cnt);
+        append_edge(c0 > 0, c0 == 2 ? sm0 : idx, c0 == 2 ? idx : sm0, s_stage, &s_stage_n, o.work, work_cnt);
+        append_edge(c1 > 0, c1 == 2 ? sm1 : idx, c1 == 2 ? idx : sm1, s_stage, &s_stage_n, o.work, work_cnt);
       }
       wave_lds_sync();
     }
@@ -1033,8 +1027,9 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   if (st) atomicOr(status, st);
 }
 
+// The narrow variant is held to 128 VGPRs so that four workgroups share a CU (its LDS allows four).
 template <int TY, bool WIDE>
-__global__ __launch_bounds__(256) void emit2d(Grid2 g, int TT, const uint16_t* __restrict__ masks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 4))) void emit2d(Grid2 g, int TT, const uint16_t* __restrict__ masks,
                                               const int* __restrict__ seg_cnt, const long long* __restrict__ seg_off,
                                               Out2 o, unsigned* __restrict__ status,
                                               unsigned long long* __restrict__ cnt) {
@@ -1084,7 +1079,7 @@ __global__ __launch_bounds__(256) void detect2d_batched(const Series2* __restric
 }
 
 template <int TY, bool WIDE>
-__global__ __launch_bounds__(256) void emit2d_batched(const Series2* __restrict__ S, const int* __restrict__ prefix,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 3))) void emit2d_batched(const Series2* __restrict__ S, const int* __restrict__ prefix,
                                                       int nser, int TT, int* counter, unsigned* status,
                                                       unsigned long long* work_cnt) {
   __shared__ int s_item;
