@@ -19,6 +19,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s
 
 WORKLOADS = {
     "c0": "2D scalar 64x64x10, 8 moving Gaussians, seed 0",
@@ -69,8 +70,9 @@ KERNEL_SOURCES = {
 }
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches the current source."""
+def measured_counters(kernel, workload):
+    """Counter summary of the kernel from the committed rocprofv3 runs (HBM bytes and VALU instructions per launch),
+    if it was taken on the current source; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -79,7 +81,7 @@ def measured_traffic(kernel, workload):
             d = json.load(fh)
         if d.get("source_hash") != source_hash(KERNEL_SOURCES[kernel]):
             return None
-        return float(d["bytes_per_launch"])
+        return d
     except Exception:
         return None
 
@@ -233,9 +235,15 @@ def main():
     k = int(np.argmax(phase))
     kernel = names[k]
     achieved = alg[k] / (phase[k] * 1e-3) / 1e9 if phase[k] > 0 else 0.0
-    traffic = measured_traffic(kernel, wl)
+    counters = measured_counters(kernel, wl)
+    traffic = float(counters["bytes_per_launch"]) if counters else None
+    # VALU busy: wave64 VALU instructions per launch over the issue capacity in the measured duration
+    # (256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction)
+    valu_busy = None
+    if counters and counters.get("valu_insts_per_launch") and phase[k] > 0:
+        valu_busy = round(counters["valu_insts_per_launch"] / (phase[k] * 1e-3 * VALU_ISSUE_PEAK), 3)
     roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "valu_busy": valu_busy,
                 "avg_ms": round(float(phase[k]), 4),
                 "phase_ms": {nm: round(float(p), 4) for nm, p in zip(names, phase)},
                 "path_frac": round((in_bytes + (rec + 8) * nh) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -244,7 +252,7 @@ def main():
     if not args.no_cpu_baseline and n == 2:
         from oracle import oracle as O
         cores = min(16, len(os.sched_getaffinity(0)))
-        steps = args.cpu_steps or (10 if wl in ("c1", "c1deg") else 3)
+        steps = args.cpu_steps or (20 if wl in ("c1", "c1deg") else 3)
         if wl == "c0":
             sample = field_np
         else:
