@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __res
 // ---------------------------------------------------------------------------------------------------------------
 namespace {
 
-// Side tables of the triangle types, built at compile time and copied to LDS at kernel start.
+// Side tables of the triangle types, built at compile time (read from constant memory).
 // kTri2Pack[ty] = M1 | M2 << 4.  kTri2Cof[ty][k] describes the k-th tetrahedron holding a triangle of type ty
 // (Alg. 1 pass 2, "tet.sides(2)" read backwards): bits 0-1 existence rule (1 always, 2 when p_a >= 1, 3 when
 // p_a + 1 <= N_a - 1), bits 2-3 the axis a, then its three other sides as (anchor slot, type) in 7-bit fields.
@@ -349,6 +349,7 @@ constexpr Tri2Tables build_tri2_tables() {
   return r;
 }
 constexpr Tri2Tables kTri2Tab = build_tri2_tables();
+__constant__ Tri2Tables kTri2Dev = kTri2Tab;  // read per hit with a lane-dependent type (cached, no LDS)
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -422,7 +423,7 @@ __device__ __forceinline__ void wg_unite(unsigned* parent, unsigned a, unsigned 
 
 // Edge list staging: links that leave the tile/chunk are collected in LDS and appended to the global list in
 // batches (one global atomic per batch; same-address atomics serialise at one L2 channel).
-constexpr int kEdgeStage = 256;
+constexpr int kEdgeStage = 512;
 
 // Wave-aggregated append of (idx, partner) for the active lanes with want == true: one LDS add reserves the
 // wave's slots; slots past the stage capacity go straight to the global list (one global add for them).
@@ -502,10 +503,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   __shared__ int s_have[2];  // step held by each field buffer (-1: none)
   __shared__ uint2 s_stage[kEdgeStage];
   __shared__ int s_stage_n;
-  __shared__ unsigned long long s_stage_base;
   __shared__ unsigned long long s_red[4];
-  __shared__ unsigned s_pack[12];
-  __shared__ unsigned s_cof[12][2];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int x0 = bx * TX, y0 = by * TY;
@@ -517,11 +515,6 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   unsigned st = 0;
   unsigned long long n_fp64 = 0, n_deg = 0, n_linked = 0;
 
-  if (tid < 12) {
-    s_pack[tid] = kTri2Tab.pack[tid];
-    s_cof[tid][0] = kTri2Tab.cof[tid][0];
-    s_cof[tid][1] = kTri2Tab.cof[tid][1];
-  }
 
   // vector field of plane t into gs[par]
   auto load_plane = [&](int t, int par) {
@@ -652,14 +645,44 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       }
     }
   };
-  // move the staged edges to the global list
+  // Move the staged links (hit, smaller partner) to the global list.  Links staged as (partner, hit) wait in the
+  // stage for their chunk's flush (compacted to the front); attached ones, (R, R), are dropped.  One wavefront.
   auto drain = [&]() {
+    __syncthreads();  // nobody reads the stage any more (a flush may just have)
     const int n = s_stage_n < kEdgeStage ? s_stage_n : kEdgeStage;  // slots past the capacity went to the list
-    if (tid == 0) s_stage_base = n ? atomicAdd(work_cnt, (unsigned long long)n) : 0ull;
+    if (wave == 0) {
+      unsigned n_out = 0;
+      for (int b = 0; b < n; b += 64) {
+        bool out = false;
+        if (b + lane < n) {
+          const uint2 e = s_stage[b + lane];
+          out = e.x > e.y;
+        }
+        n_out += (unsigned)__popcll(__ballot(out));
+      }
+      unsigned long long gb = 0;
+      if (lane == 0 && n_out) gb = atomicAdd(work_cnt, (unsigned long long)n_out);
+      gb = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(gb >> 32), 0) << 32) |
+           (unsigned)__builtin_amdgcn_readlane((int)(unsigned)gb, 0);
+      const unsigned long long below = (1ull << lane) - 1ull;
+      unsigned wo = 0, wk = 0;
+      for (int b = 0; b < n; b += 64) {
+        uint2 e = make_uint2(0u, 0u);
+        bool out = false, keep = false;
+        if (b + lane < n) {
+          e = s_stage[b + lane];
+          out = e.x > e.y;
+          keep = e.x < e.y;
+        }
+        const unsigned long long bo = __ballot(out), bk = __ballot(keep);
+        if (out) o.work[gb + wo + (unsigned)__popcll(bo & below)] = e;
+        if (keep) s_stage[wk + (unsigned)__popcll(bk & below)] = e;  // below b + 64: not read again
+        wo += (unsigned)__popcll(bo);
+        wk += (unsigned)__popcll(bk);
+      }
+      if (lane == 0) s_stage_n = (int)wk;
+    }
     __syncthreads();
-    for (int i = tid; i < n; i += 256) o.work[s_stage_base + i] = s_stage[i];
-    __syncthreads();
-    if (tid == 0) s_stage_n = 0;
   };
 
   if (tid == 0) {
@@ -801,7 +824,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
         const int L = (int)(ent & 63u), ty = (int)(ent >> 6);
         const unsigned idx = base + j;
         const int ax = x0 + L;
-        const unsigned pk = s_pack[ty];
+        const unsigned pk = kTri2Dev.pack[ty];
         const int m1 = pk & 15, m2 = pk >> 4;
         // vertex offsets along x, y, t of v1 and v2
         const int dx1 = m1 & 1, dy1 = (m1 >> 1) & 1, dt1 = (m1 >> 2) & 1;
@@ -951,7 +974,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-          const unsigned w = s_cof[ty][k];
+          const unsigned w = kTri2Dev.cof[ty][k];
           const int rule = w & 3, axis = (w >> 2) & 3;
           const int pa = axis == 0 ? ax : (axis == 1 ? y : t);
           const int Na = axis == 0 ? nx : (axis == 1 ? ny : nt);
