@@ -207,12 +207,23 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
       const double c0 = (double)qs[nxp][0][qa + 1], c1 = (double)qs[nxp][1][qa + 1];
       const double d0 = (double)qs[nxp][0][qa + QW], d1 = (double)qs[nxp][1][qa + QW];
       const double f0 = (double)qs[nxp][0][qa + QW + 1], f1 = (double)qs[nxp][1][qa + QW + 1];
-      const unsigned o = sos2_positive_d(b0, b1, c0, c1) | (sos2_positive_d(b0, b1, d0, d1) << 1) |
-                         (sos2_positive_d(b0, b1, f0, f1) << 2);
-      const unsigned w = (sos2_positive_d(a0, a1, b0, b1) << 3) | (sos2_positive_d(a0, a1, c0, c1) << 4) |
-                         (sos2_positive_d(a0, a1, d0, d1) << 5) | (sos2_positive_d(a0, a1, f0, f1) << 6);
-      ew[nxp][e] = (uint8_t)o;
-      ew[par][e] |= (uint8_t)w;
+      // edges (b c), (b d), (b f) -> ordinal bits 0-2 of step t+1; (a b), (a c), (a d), (a f) -> interval bits 3-6
+      const double P0[7] = {b0, b0, b0, a0, a0, a0, a0}, P1[7] = {b1, b1, b1, a1, a1, a1, a1};
+      const double Q0[7] = {c0, d0, f0, b0, c0, d0, f0}, Q1[7] = {c1, d1, f1, b1, c1, d1, f1};
+      unsigned bits = 0, zero = 0;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const double d = __builtin_fma(P0[k], Q1[k], -(P1[k] * Q0[k]));  // exact
+        bits |= (unsigned)(d > 0.0) << k;
+        zero |= (unsigned)(d == 0.0) << k;
+      }
+      if (zero) {  // the perturbation decides exact zeros only (rare on generic data)
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+          if ((zero >> k) & 1u) bits |= sos2_positive_d(P0[k], P1[k], Q0[k], Q1[k]) << k;
+      }
+      ew[nxp][e] = (uint8_t)(bits & 7u);
+      ew[par][e] |= (uint8_t)(bits & 0x78u);
     }
   };
 
