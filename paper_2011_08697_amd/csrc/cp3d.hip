@@ -169,6 +169,18 @@ __device__ __forceinline__ unsigned tri_sign(const Q* a, const Q* b, const Q* c)
 
 }  // namespace
 
+// compile-time triangle lists of the two passes (ordinal types of a plane; interval types towards the next one)
+struct OrdList {
+  static constexpr int n = 12;
+  static constexpr bool assign = true;
+  static constexpr int ti(int k) { return kTriSplit.ord[k]; }
+};
+struct ItvList {
+  static constexpr int n = 38;
+  static constexpr bool assign = false;
+  static constexpr int ti(int k) { return kTriSplit.itv[k]; }
+};
+
 // ---------------------------------------------------------------------------------------------------------------
 // Pass 1: detection.  grid = (ceil(nx/16), ceil(ny/8) * ceil(nz/4), ceil(nt/TT)), block = 256.
 // ---------------------------------------------------------------------------------------------------------------
@@ -185,6 +197,7 @@ __global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64
   __shared__ unsigned long long tw[2][WN];
   __shared__ unsigned s_tri[50];
   __shared__ int s_cdelta[16];
+  __shared__ unsigned char s_tcor[50];  // triangle type -> corner a | corner b << 4
 
   const int tid = threadIdx.x;
   if (tid < 50) {
@@ -194,6 +207,7 @@ __global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64
     s_tri[k] = (unsigned)ti | ((unsigned)ca << 8) | ((unsigned)cb << 12);
   }
   if (tid < 16) s_cdelta[tid] = (((tid >> 2) & 1) * QY + ((tid >> 1) & 1)) * QX + (tid & 1);
+  if (tid < 50) s_tcor[tid] = (unsigned char)(kTri3.m[tid][0] | ((kTri3.m[tid][0] | kTri3.m[tid][1]) << 4));
   __syncthreads();
   const int nx = g.nx, ny = g.ny, nz = g.nz, nt = g.nt;
   const int x0 = blockIdx.x * TX3;
@@ -263,8 +277,63 @@ __global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64
     }
     (void)q0p;
   };
-  auto ordinal_tris = [&](int par) { tris(par, 0, 12, true); };
-  auto interval_tris = [&](int par) { tris(par, 12, 50, false); };
+  // Narrow variant: det(c0, ca, cb) = (c0 x ca) . cb.  The cross product of two quantised vectors (below 2^20)
+  // is exact in binary64 (components below 2^41) and shared by every triangle with the same corner a; the dot
+  // product carries at most 3u sum |p_i| of rounding error, so |s| > 4e-16 sum |p_i| fixes the sign, as in
+  // sos3_positive_narrow.  Undecided triangles (every vanishing determinant among them) take the exact integer
+  // evaluation and SoS afterwards.
+  auto tris_narrow = [&](int ap, auto list) {
+    constexpr int N = decltype(list)::n;
+    const int op = ap ^ 1;
+    for (int e = tid; e < WN; e += 256) {
+      const int wx = e % WX, r = e / WX, wy = r % WY, wz = r / WY;
+      const int base = (wz * QY + wy) * QX + wx;
+      auto ld = [&](int cm, int comp) -> double {
+        return (double)qs[(cm >> 3) ? op : ap][comp][base + (((cm >> 2) & 1) * QY + ((cm >> 1) & 1)) * QX + (cm & 1)];
+      };
+      const double u0 = ld(0, 0), u1 = ld(0, 1), u2 = ld(0, 2);
+      unsigned long long w = 0, slow = 0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const int ti = decltype(list)::ti(k);
+        const int a = kTri3.m[ti][0], b = a | kTri3.m[ti][1];
+        const double a0 = ld(a, 0), a1 = ld(a, 1), a2 = ld(a, 2);
+        const double X0 = __builtin_fma(u1, a2, -(u2 * a1));
+        const double X1 = __builtin_fma(u2, a0, -(u0 * a2));
+        const double X2 = __builtin_fma(u0, a1, -(u1 * a0));
+        const double b0 = ld(b, 0), b1 = ld(b, 1), b2 = ld(b, 2);
+        const double p0 = X0 * b0, p1 = X1 * b1, p2 = X2 * b2;
+        const double sdet = (p0 + p1) + p2;
+        const double bound = ((fabs(p0) + fabs(p1)) + fabs(p2)) * 4e-16;
+        w |= (unsigned long long)(sdet > 0.0) << ti;
+        slow |= (unsigned long long)!(fabs(sdet) > bound) << ti;
+      }
+      while (slow) {
+        const int ti = __ffsll((long long)slow) - 1;
+        slow &= slow - 1;
+        const int cc = s_tcor[ti], a = cc & 15, b = cc >> 4;
+        const unsigned bit = sos3_exact_narrow((float)u0, (float)u1, (float)u2, (float)ld(a, 0), (float)ld(a, 1),
+                                               (float)ld(a, 2), (float)ld(b, 0), (float)ld(b, 1), (float)ld(b, 2));
+        w = (w & ~(1ull << ti)) | ((unsigned long long)bit << ti);
+      }
+      if (decltype(list)::assign)
+        tw[ap][e] = w;
+      else
+        tw[ap][e] |= w;
+    }
+  };
+  auto ordinal_tris = [&](int par) {
+    if constexpr (!WIDE)
+      tris_narrow(par, OrdList{});
+    else
+      tris(par, 0, 12, true);
+  };
+  auto interval_tris = [&](int par) {
+    if constexpr (!WIDE)
+      tris_narrow(par, ItvList{});
+    else
+      tris(par, 12, 50, false);
+  };
 
   load_plane(t0);
   __syncthreads();
