@@ -168,6 +168,49 @@ ftk_status ftk_track_cp2d_batched(int32_t n_series, const float* const* fields, 
                                   const int64_t* ny, const int64_t* nt, ftk_field_kind kind,
                                   const ftk_options* opt, ftk_stream_t stream, ftk_cp_result* outs);
 
+/*
+ * Trajectory post-processing (after a tracking call; n = 2 or 3, dims_with_t = (nx, ny, [nz,] nt) as tracked).
+ *
+ * Trajectory table (Sec. 4.4 "Filtering": per-trajectory attributes).  Device arrays of n entries, allocated through
+ * opt->alloc (or hipMallocAsync) in ascending label order; release with ftk_traj_table_free.  Needs the result's
+ * pos and label arrays (FTK_ERR_ARG otherwise).  Under the symbolic perturbation a punctured face lies in two cells
+ * with one more punctured side each, except on a boundary hyperplane of the grid (a coordinate equal to 0 along an
+ * axis the face does not use, or equal to N - 1), where only one cell holds it: every trajectory is a path with
+ * two such ends or a closed loop with none.
+ */
+typedef struct {
+  int64_t n;          /* trajectories (the result's n_trajectories) */
+  int64_t* label;     /* [n] smallest face id of the trajectory (its label), ascending */
+  uint64_t* n_points; /* [n] punctured faces in the trajectory */
+  float* t_min;       /* [n] smallest time coordinate of its points (pos[.][n]) */
+  float* t_max;       /* [n] largest time coordinate of its points */
+  int32_t* n_ends;    /* [n] points on a boundary hyperplane: 2 for a path, 0 for a closed loop */
+} ftk_traj_table;
+
+ftk_status ftk_traj_table_build(const ftk_cp_result* r, int32_t n, const int64_t* dims_with_t,
+                                const ftk_options* opt, ftk_stream_t stream, ftk_traj_table* out);
+void ftk_traj_table_free(ftk_traj_table* tt, const ftk_options* opt, ftk_stream_t stream);
+
+/*
+ * Critical points at time step t0 (Sec. 3.1, slicing through the ordinal faces): *idx receives a device array
+ * (allocated through opt->alloc; release with ftk_buffer_free) of the ascending indices, into the result's
+ * arrays, of the punctured faces anchored at step t0 that do not use the time axis; *count their number (host).
+ * 0 <= t0 < nt, else FTK_ERR_ARG.
+ */
+ftk_status ftk_cp_slice(const ftk_cp_result* r, int32_t n, const int64_t* dims_with_t, int64_t t0,
+                        const ftk_options* opt, ftk_stream_t stream, int64_t** idx, int64_t* count);
+
+/*
+ * Loop filter (Sec. 4.4 "Filtering"): keep[i] (device array of the result's n_hits bytes, owned by the caller)
+ * becomes 0 for the points of closed loops (n_ends == 0) whose time extent t_max - t_min is below min_duration,
+ * 1 for every other point.  tt must come from ftk_traj_table_build on the same result.
+ */
+ftk_status ftk_cp_filter_loops(const ftk_cp_result* r, const ftk_traj_table* tt, float min_duration,
+                               ftk_stream_t stream, uint8_t* keep);
+
+/* Release a device array returned by the library (with the allocator given in opt, which may be NULL). */
+void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream);
+
 /* Release the device arrays of a result (with the allocator given in opt, which may be NULL). */
 void ftk_result_free(ftk_cp_result* r, const ftk_options* opt, ftk_stream_t stream);
 

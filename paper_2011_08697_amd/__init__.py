@@ -20,7 +20,8 @@ SCALAR, VECTOR = 0, 1
 
 EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_create", "ftk_cp_push",
            "ftk_cp_finish", "ftk_cp_destroy", "ftk_track_cp2d_batched", "ftk_result_free", "ftk_simplex_count",
-           "ftk_last_error", "ftk_version"]
+           "ftk_last_error", "ftk_version", "ftk_traj_table_build", "ftk_traj_table_free", "ftk_cp_slice",
+           "ftk_cp_filter_loops", "ftk_buffer_free"]
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -53,6 +54,11 @@ class Result(ctypes.Structure):
                 ("n_trajectories", ctypes.c_int64), ("face_id", ctypes.c_void_p), ("pos", ctypes.c_void_p),
                 ("mu", ctypes.c_void_p), ("type", ctypes.c_void_p), ("flags", ctypes.c_void_p),
                 ("label", ctypes.c_void_p), ("stats", Stats)]
+
+
+class TrajTable(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("label", ctypes.c_void_p), ("n_points", ctypes.c_void_p),
+                ("t_min", ctypes.c_void_p), ("t_max", ctypes.c_void_p), ("n_ends", ctypes.c_void_p)]
 
 
 _lib = None
@@ -90,6 +96,18 @@ def lib():
         L.ftk_result_free.restype = None
         L.ftk_simplex_count.argtypes = [ctypes.c_int32, ctypes.POINTER(i64)]
         L.ftk_simplex_count.restype = i64
+        L.ftk_traj_table_build.argtypes = [ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(i64),
+                                           ctypes.POINTER(Options), vp, ctypes.POINTER(TrajTable)]
+        L.ftk_traj_table_build.restype = ctypes.c_int
+        L.ftk_traj_table_free.argtypes = [ctypes.POINTER(TrajTable), ctypes.POINTER(Options), vp]
+        L.ftk_traj_table_free.restype = None
+        L.ftk_cp_slice.argtypes = [ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(i64), i64,
+                                   ctypes.POINTER(Options), vp, ctypes.POINTER(vp), ctypes.POINTER(i64)]
+        L.ftk_cp_slice.restype = ctypes.c_int
+        L.ftk_cp_filter_loops.argtypes = [ctypes.POINTER(Result), ctypes.POINTER(TrajTable), ctypes.c_float, vp, vp]
+        L.ftk_cp_filter_loops.restype = ctypes.c_int
+        L.ftk_buffer_free.argtypes = [vp, ctypes.POINTER(Options), vp]
+        L.ftk_buffer_free.restype = None
         L.ftk_last_error.restype = ctypes.c_char_p
         L.ftk_version.restype = ctypes.c_char_p
         _lib = L
@@ -256,3 +274,84 @@ def track_cp2d_batched(fields, kind=SCALAR, **opts):
                                       res)
     _check(st)
     return [_wrap(pool, res[i]) for i in range(k)]
+
+
+# ---------------------------------------------------------------------------------------------------------------
+# Trajectory post-processing (slicing at a time step, per-trajectory table, loop filter)
+# ---------------------------------------------------------------------------------------------------------------
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
+
+
+def _device_of(res):
+    import torch
+    for k in ("face_id", "label", "pos", "type"):
+        if res.get(k) is not None:
+            return res[k].device
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def _dims_arg(res, dims_with_t):
+    if len(dims_with_t) != res["n"] + 1:
+        raise ValueError(f"dims_with_t must have {res['n'] + 1} entries for a {res['n']}D result")
+    return (ctypes.c_int64 * len(dims_with_t))(*dims_with_t)
+
+
+def _as_result(res):
+    """Result struct view of a result dict from the tracking calls (device pointers only)."""
+    r = Result()
+    r.n = res["n"]
+    r.n_hits = res["n_hits"]
+    r.n_trajectories = res["n_trajectories"]
+    for f in ("face_id", "pos", "mu", "type", "flags", "label"):
+        setattr(r, f, _ptr(res[f]).value)
+    return r
+
+
+def trajectory_table(res, dims_with_t):
+    """Per-trajectory attributes of a tracking result: label (ascending), n_points, t_min, t_max, n_ends."""
+    import torch
+    dev = _device_of(res)
+    pool = _TorchPool(dev)
+    o = _options(pool)
+    r = _as_result(res)
+    arr = _dims_arg(res, dims_with_t)
+    t = TrajTable()
+    _check(lib().ftk_traj_table_build(ctypes.byref(r), res["n"], arr, ctypes.byref(o), _stream_handle(dev),
+                                      ctypes.byref(t)))
+    n = int(t.n)
+    return dict(n=n, label=pool.take(t.label, torch.int64, (n,)), n_points=pool.take(t.n_points, torch.int64, (n,)),
+                t_min=pool.take(t.t_min, torch.float32, (n,)), t_max=pool.take(t.t_max, torch.float32, (n,)),
+                n_ends=pool.take(t.n_ends, torch.int32, (n,)))
+
+
+def slice_at(res, dims_with_t, t0):
+    """Indices (ascending) of the critical points at time step t0: punctured ordinal faces anchored at t0."""
+    import torch
+    dev = _device_of(res)
+    pool = _TorchPool(dev)
+    o = _options(pool)
+    r = _as_result(res)
+    arr = _dims_arg(res, dims_with_t)
+    p = ctypes.c_void_p()
+    cnt = ctypes.c_int64()
+    _check(lib().ftk_cp_slice(ctypes.byref(r), res["n"], arr, t0, ctypes.byref(o), _stream_handle(dev),
+                              ctypes.byref(p), ctypes.byref(cnt)))
+    k = int(cnt.value)
+    t = pool.take(p.value, torch.int64, (max(k, 1),))
+    return t[:k]
+
+
+def filter_loops(res, table, min_duration):
+    """uint8 keep mask: 0 for the points of closed loops shorter than min_duration (in step units)."""
+    import torch
+    dev = _device_of(res)
+    keep = torch.empty(res["n_hits"], dtype=torch.uint8, device=dev)
+    r = _as_result(res)
+    t = TrajTable()
+    t.n = table["n"]
+    for f in ("label", "n_points", "t_min", "t_max", "n_ends"):
+        setattr(t, f, _ptr(table[f]).value)
+    _check(lib().ftk_cp_filter_loops(ctypes.byref(r), ctypes.byref(t), float(min_duration), _stream_handle(dev),
+                                     _ptr(keep)))
+    return keep

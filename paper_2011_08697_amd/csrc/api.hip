@@ -1146,3 +1146,174 @@ extern "C" ftk_status ftk_track_cp2d(const float* field, ftk_field_kind kind, in
   if (st) return st;
   return ftk::track2d_impl(field, kind, nx, ny, nt, o, (hipStream_t)stream, out);
 }
+
+// ---------------------------------------------------------------------------------------------------------------
+// Trajectory post-processing (post.hip): trajectory table, slicing at a time step, loop filter.
+// ---------------------------------------------------------------------------------------------------------------
+namespace {
+
+ftk_status check_post_args(const ftk_cp_result* r, int32_t n, const int64_t* dims) {
+  if (!r || !dims) return fail(FTK_ERR_ARG, "result and dims must be given");
+  if (n != 2 && n != 3) return fail(FTK_ERR_ARG, "n must be 2 or 3");
+  if (r->n != n) return fail(FTK_ERR_ARG, "the result holds %dD faces, not %dD", (int)r->n, (int)n);
+  for (int a = 0; a <= n; ++a)
+    if (dims[a] < 2) return fail(FTK_ERR_ARG, "every dimension must be >= 2");
+  if (r->n_hits < 0 || r->n_trajectories < 0) return fail(FTK_ERR_ARG, "negative counts in the result");
+  if (r->n_hits > 0 && !r->face_id) return fail(FTK_ERR_ARG, "the result has no face_id array");
+  return FTK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ftk_status ftk_traj_table_build(const ftk_cp_result* r, int32_t n, const int64_t* dims_with_t,
+                                const ftk_options* opt, ftk_stream_t stream, ftk_traj_table* out) {
+  g_err.clear();
+  if (!out) return fail(FTK_ERR_ARG, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  ftk_status st = check_post_args(r, n, dims_with_t);
+  if (st) return st;
+  if (r->n_hits > 0 && (!r->pos || !r->label))
+    return fail(FTK_ERR_ARG, "the trajectory table needs the result's pos and label arrays");
+  ftk_options o;
+  resolve(opt, &o);
+  if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
+  hipStream_t s = (hipStream_t)stream;
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
+  const long long nh = r->n_hits, ntr = r->n_trajectories;
+  ftk_traj_table t;
+  std::memset(&t, 0, sizeof(t));
+  t.n = ntr;
+  t.label = (int64_t*)al.get(sizeof(int64_t) * ntr);
+  t.n_points = (uint64_t*)al.get(sizeof(uint64_t) * ntr);
+  t.t_min = (float*)al.get(sizeof(float) * ntr);
+  t.t_max = (float*)al.get(sizeof(float) * ntr);
+  t.n_ends = (int32_t*)al.get(sizeof(int32_t) * ntr);
+  int* flag = sc.get<int>((size_t)nh);
+  long long* off = sc.get<long long>((size_t)nh);
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(nh));
+  Ctl* dctl = sc.get<Ctl>(1);
+  if (!t.label || !t.n_points || !t.t_min || !t.t_max || !t.n_ends || !flag || !off || !tmp || !dctl) {
+    ftk_traj_table_free(&t, opt, stream);
+    return fail(FTK_ERR_OOM, "trajectory table allocation failed");
+  }
+  hipError_t he = hipMemsetAsync(dctl, 0, sizeof(Ctl), s);
+  if (he == hipSuccess)
+    he = ftk::launch_traj_table(n, dims_with_t, (const long long*)r->face_id, (const long long*)r->label, r->pos, nh,
+                                ntr, flag, off, &dctl->total, tmp, (long long*)t.label,
+                                (unsigned long long*)t.n_points, (int*)t.t_min, (int*)t.t_max, t.n_ends,
+                                &dctl->status, s);
+  Ctl h;
+  if (he == hipSuccess) {
+    st = read_ctl(&h, dctl, s);
+  } else {
+    st = fail(FTK_ERR_HIP, "kernel launch: %s", hipGetErrorString(he));
+  }
+  if (!st) st = decode_status(h.status);
+  if (!st && nh > 0 && h.total != ntr)
+    st = fail(FTK_ERR_INVARIANT, "%lld trajectory roots for %lld trajectories", h.total, ntr);
+  if (st) {
+    ftk_traj_table_free(&t, opt, stream);
+    return st;
+  }
+  *out = t;
+  return FTK_OK;
+}
+
+void ftk_traj_table_free(ftk_traj_table* tt, const ftk_options* opt, ftk_stream_t stream) {
+  if (!tt) return;
+  ftk_options o;
+  resolve(opt, &o);
+  Alloc al = make_alloc(o, (hipStream_t)stream);
+  al.put(tt->label);
+  al.put(tt->n_points);
+  al.put(tt->t_min);
+  al.put(tt->t_max);
+  al.put(tt->n_ends);
+  std::memset(tt, 0, sizeof(*tt));
+}
+
+ftk_status ftk_cp_slice(const ftk_cp_result* r, int32_t n, const int64_t* dims_with_t, int64_t t0,
+                        const ftk_options* opt, ftk_stream_t stream, int64_t** idx, int64_t* count) {
+  g_err.clear();
+  if (!idx || !count) return fail(FTK_ERR_ARG, "idx and count must be given");
+  *idx = nullptr;
+  *count = 0;
+  ftk_status st = check_post_args(r, n, dims_with_t);
+  if (st) return st;
+  if (t0 < 0 || t0 >= dims_with_t[n]) return fail(FTK_ERR_ARG, "t0 = %lld outside [0, nt)", (long long)t0);
+  ftk_options o;
+  resolve(opt, &o);
+  if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
+  hipStream_t s = (hipStream_t)stream;
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
+  const long long nh = r->n_hits;
+  long long* range = sc.get<long long>(2);
+  Ctl* dctl = sc.get<Ctl>(1);
+  if (!range || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  long long hr[2] = {0, 0};
+  if (nh > 0) {
+    HIP_TRY(ftk::launch_slice_range(n, dims_with_t, (const long long*)r->face_id, nh, t0, range, s));
+    HIP_TRY(hipMemcpyAsync(hr, range, sizeof(hr), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  const long long lo = hr[0], cnt = hr[1] - hr[0];
+  long long k = 0;
+  int* flag = nullptr;
+  long long* off = nullptr;
+  if (cnt > 0) {
+    flag = sc.get<int>((size_t)cnt);
+    off = sc.get<long long>((size_t)cnt);
+    long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(cnt));
+    if (!flag || !off || !tmp) return fail(FTK_ERR_OOM, "scratch allocation failed");
+    HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+    HIP_TRY(ftk::launch_slice_compact(n, dims_with_t, (const long long*)r->face_id, lo, cnt, flag, off, &dctl->total,
+                                      tmp, nullptr, false, s));
+    Ctl h;
+    st = read_ctl(&h, dctl, s);
+    if (st) return st;
+    k = h.total;
+  }
+  int64_t* out = (int64_t*)al.get(sizeof(int64_t) * (size_t)(k > 0 ? k : 1));
+  if (!out) return fail(FTK_ERR_OOM, "slice allocation failed");
+  if (k > 0) {
+    hipError_t he = ftk::launch_slice_compact(n, dims_with_t, (const long long*)r->face_id, lo, cnt, flag, off,
+                                              nullptr, nullptr, (long long*)out, true, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) {
+      al.put(out);
+      return fail(FTK_ERR_HIP, "slice: %s", hipGetErrorString(he));
+    }
+  }
+  *idx = out;
+  *count = k;
+  return FTK_OK;
+}
+
+ftk_status ftk_cp_filter_loops(const ftk_cp_result* r, const ftk_traj_table* tt, float min_duration,
+                               ftk_stream_t stream, uint8_t* keep) {
+  g_err.clear();
+  if (!r || !tt) return fail(FTK_ERR_ARG, "result and table must be given");
+  if (r->n_hits == 0) return FTK_OK;
+  if (!keep) return fail(FTK_ERR_ARG, "keep must be given");
+  if (!r->label) return fail(FTK_ERR_ARG, "the loop filter needs the result's label array");
+  if (tt->n != r->n_trajectories || !tt->label || !tt->t_min || !tt->t_max || !tt->n_ends)
+    return fail(FTK_ERR_ARG, "the trajectory table does not belong to this result");
+  if (!(min_duration == min_duration)) return fail(FTK_ERR_ARG, "min_duration is NaN");
+  HIP_TRY(ftk::launch_filter_loops((const long long*)r->label, r->n_hits, (const long long*)tt->label, tt->n,
+                                   (const int*)tt->t_min, (const int*)tt->t_max, tt->n_ends, min_duration, keep,
+                                   (hipStream_t)stream));
+  return FTK_OK;
+}
+
+void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream) {
+  if (!p) return;
+  ftk_options o;
+  resolve(opt, &o);
+  make_alloc(o, (hipStream_t)stream).put(p);
+}
+
+}  // extern "C"

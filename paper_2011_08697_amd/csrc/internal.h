@@ -89,6 +89,21 @@ hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const
 size_t scan_tmp_elems(long long n);
 hipError_t launch_scan(const int* in, long long* out, long long n, long long* total, long long* tmp, hipStream_t s);
 
+// Trajectory post-processing (post.hip).
+hipError_t launch_traj_table(int n, const int64_t* dims_with_t, const long long* face_id, const long long* label,
+                             const float* pos, long long n_hits, long long n_traj, int* flag, long long* off,
+                             long long* scan_total, long long* scan_tmp, long long* roots,
+                             unsigned long long* hits, int* t_min, int* t_max, int* n_ends, unsigned* status,
+                             hipStream_t s);
+hipError_t launch_slice_range(int n, const int64_t* dims_with_t, const long long* face_id, long long n_hits,
+                              long long t0, long long* range, hipStream_t s);
+hipError_t launch_slice_compact(int n, const int64_t* dims_with_t, const long long* face_id, long long lo,
+                                long long cnt, int* flag, long long* off, long long* total, long long* tmp,
+                                long long* idx_out, bool scatter, hipStream_t s);
+hipError_t launch_filter_loops(const long long* label, long long n_hits, const long long* roots, long long n_traj,
+                               const int* t_min, const int* t_max, const int* n_ends, float min_duration,
+                               uint8_t* keep, hipStream_t s);
+
 // Union-find passes over n hits: extra unions from the work list, then labels = face_id of the root.
 hipError_t launch_uf_hook(unsigned* parent, const uint2* work, const unsigned long long* work_count,
                           long long max_work, hipStream_t s);
