@@ -98,7 +98,7 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
   constexpr int FW = TX + 4, FH = TY + 4;  // field plane + 2-cell halo (x0-1 .. x0+TX+2)
   constexpr int QW = TX + 2, QH = TY + 2;  // quantised vectors (x0 .. x0+TX+1)
   constexpr int EW = TX + 1, EH = TY + 1;  // edge words (x0 .. x0+TX)
-  __shared__ float fs[2][FH * FW];
+  __shared__ float fs[FH * FW];     // scalar input: the field plane being loaded
   __shared__ Q qs[2][2][QH * QW];  // [plane parity][component]
   __shared__ uint8_t ew[2][EH * EW];
 
@@ -110,8 +110,8 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
   const long long plane = (long long)nx * ny;
   unsigned st = 0;
 
-  // Load plane t into fs (scalar: FH x FW with halo; vector: both components over the QH x QW region).
-  auto load_plane = [&](int t) {
+  // Load plane t: scalar input into fs (FH x FW with halo); vector input straight into qs[par] (quantised).
+  auto load_plane = [&](int t, int par) {
     if (g.kind == 0) {
       const float* src = g.f + (long long)fpl(g, t) * plane;
       for (int e = tid; e < FH * FW; e += 256) {
@@ -122,7 +122,7 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
           v = src[(long long)gy * nx + gx];
           if (!isfinite(v)) st |= ST_NONFINITE;
         }
-        fs[0][e] = v;
+        fs[e] = v;
       }
     } else {
       for (int c = 0; c < 2; ++c) {
@@ -130,33 +130,29 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
         for (int e = tid; e < QH * QW; e += 256) {
           int ly = e / QW, lx = e - ly * QW;
           int gx = x0 + lx, gy = y0 + ly;
-          float v = 0.0f;
+          Q q = 0;
           if (gx < nx && gy < ny) {
-            v = src[(long long)gy * nx + gx];
+            const float v = src[(long long)gy * nx + gx];
             if (!isfinite(v)) st |= ST_NONFINITE;
+            q = to_q<WIDE>(quant(v, g.qscale), st);
           }
-          fs[c][e] = v;
+          qs[par][c][e] = q;
         }
       }
     }
   };
 
-  // Quantised vectors of plane (parity par) from fs.
+  // Quantised gradient of plane (parity par) from fs (scalar input; vector input is quantised while loading).
   auto quantise_plane = [&](int par) {
+    if (g.kind != 0) return;
     for (int e = tid; e < QH * QW; e += 256) {
       int ly = e / QW, lx = e - ly * QW;
       int gx = x0 + lx, gy = y0 + ly;
       Q q0 = 0, q1 = 0;
       if (gx < nx && gy < ny) {
-        float v0, v1;
-        if (g.kind == 0) {
-          const float* r = &fs[0][(ly + 1) * FW + (lx + 1)];
-          v0 = diff3(r[-1], r[0], r[1], gx, nx);
-          v1 = diff3(r[-FW], r[0], r[FW], gy, ny);
-        } else {
-          v0 = fs[0][e];
-          v1 = fs[1][e];
-        }
+        const float* r = &fs[(ly + 1) * FW + (lx + 1)];
+        const float v0 = diff3(r[-1], r[0], r[1], gx, nx);
+        const float v1 = diff3(r[-FW], r[0], r[FW], gy, ny);
         q0 = to_q<WIDE>(quant(v0, g.qscale), st);
         q1 = to_q<WIDE>(quant(v1, g.qscale), st);
       }
@@ -232,7 +228,7 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
   for (int i = tid; i < 8 * 128; i += 256) s_lut[i >> 7][i & 127] = kTri2Lut.t[i >> 7][i & 127];
 
   // prologue: plane t0
-  load_plane(t0);
+  load_plane(t0, t0 & 1);
   __syncthreads();
   quantise_plane(t0 & 1);
   __syncthreads();
@@ -245,7 +241,7 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
     const bool has_next = (t + 1 < nt);
     __syncthreads();  // previous triangle pass done with ew / fs
     if (has_next) {
-      load_plane(t + 1);
+      load_plane(t + 1, nxp);
       __syncthreads();
       quantise_plane(nxp);
       __syncthreads();
