@@ -97,6 +97,11 @@ def bench_batched(args, F, synth, dev):
     steps_total = sum(f.shape[0] for f in fields)
     tested = sum(F.simplex_count(2, (f.shape[2], f.shape[1], f.shape[0])) for f in fields)
 
+    # tilings tuned per series shape first (untimed); plain calls use their own, the batched launch its largest's
+    for t in ts:
+        F.autotune_cp2d(t)
+    torch.cuda.synchronize()
+
     def batched():
         res = F.track_cp2d_batched(ts)
         return sum(r["n_hits"] for r in res)

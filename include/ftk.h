@@ -211,6 +211,16 @@ ftk_status ftk_cp_filter_loops(const ftk_cp_result* r, const ftk_traj_table* tt,
 /* Release a device array returned by the library (with the allocator given in opt, which may be NULL). */
 void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream);
 
+/*
+ * Autotuning of the 2D detection tiling (an implementation choice; the paper prescribes none): times the detection
+ * kernel on the caller's field (device pointer, layout as ftk_track_cp2d) for tile rows {8, 16, 32} x slab depths
+ * {8, 16, 32} and returns opt with the fastest tile_y / slab_depth in *tuned (host struct).  The choice is also
+ * remembered for (kind, nx, ny) in this process and used by later calls that leave tile_y / slab_depth at 0
+ * (the batched form takes the slab depth of its largest series).  Errors as ftk_track_cp2d.
+ */
+ftk_status ftk_autotune_cp2d(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,
+                             const ftk_options* opt, ftk_stream_t stream, ftk_options* tuned);
+
 /* Release the device arrays of a result (with the allocator given in opt, which may be NULL). */
 void ftk_result_free(ftk_cp_result* r, const ftk_options* opt, ftk_stream_t stream);
 

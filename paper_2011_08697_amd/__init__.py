@@ -21,7 +21,7 @@ SCALAR, VECTOR = 0, 1
 EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_create", "ftk_cp_push",
            "ftk_cp_finish", "ftk_cp_destroy", "ftk_track_cp2d_batched", "ftk_result_free", "ftk_simplex_count",
            "ftk_last_error", "ftk_version", "ftk_traj_table_build", "ftk_traj_table_free", "ftk_cp_slice",
-           "ftk_cp_filter_loops", "ftk_buffer_free"]
+           "ftk_cp_filter_loops", "ftk_buffer_free", "ftk_autotune_cp2d"]
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -108,6 +108,9 @@ def lib():
         L.ftk_cp_filter_loops.restype = ctypes.c_int
         L.ftk_buffer_free.argtypes = [vp, ctypes.POINTER(Options), vp]
         L.ftk_buffer_free.restype = None
+        L.ftk_autotune_cp2d.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.POINTER(Options), vp,
+                                        ctypes.POINTER(Options)]
+        L.ftk_autotune_cp2d.restype = ctypes.c_int
         L.ftk_last_error.restype = ctypes.c_char_p
         L.ftk_version.restype = ctypes.c_char_p
         _lib = L
@@ -355,3 +358,15 @@ def filter_loops(res, table, min_duration):
     _check(lib().ftk_cp_filter_loops(ctypes.byref(r), ctypes.byref(t), float(min_duration), _stream_handle(dev),
                                      _ptr(keep)))
     return keep
+
+
+def autotune_cp2d(field, kind=SCALAR):
+    """Time the detection tilings on this field; returns (tile_y, slab_depth), also remembered for the shape."""
+    if not field.is_contiguous() or field.dtype.itemsize != 4 or not field.is_cuda:
+        raise ValueError("field must be a contiguous float32 device tensor")
+    nt, ny, nx = (field.shape[0], field.shape[-2], field.shape[-1])
+    o = _options(None)
+    t = Options()
+    _check(lib().ftk_autotune_cp2d(ctypes.c_void_p(field.data_ptr()), kind, nx, ny, nt, ctypes.byref(o),
+                                   _stream_handle(field.device), ctypes.byref(t)))
+    return int(t.tile_y), int(t.slab_depth)

@@ -307,9 +307,42 @@ struct Detect2 {
   long long n_hits = 0;
 };
 
-static void tuned_tiles2(const ftk_options& o, int nt, int* ty, int* tt) {
-  *ty = o.tile_y ? o.tile_y : 16;
-  *tt = o.slab_depth ? o.slab_depth : 16;
+// Detection tile rows and slab depth picked by ftk_autotune_cp2d, per (kind, nx, ny): consulted when the options
+// leave them at 0.  Without an entry: 16 rows, 16 steps (within a few per cent of the best on the workloads here).
+struct TuneKey {
+  int kind;
+  long long nx, ny;
+  bool operator==(const TuneKey& k) const { return kind == k.kind && nx == k.nx && ny == k.ny; }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, std::pair<int, int>>> g_tune;
+
+static bool tune_lookup(int kind, long long nx, long long ny, int* ty, int* tt) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tune)
+    if (e.first == TuneKey{kind, nx, ny}) {
+      *ty = e.second.first;
+      *tt = e.second.second;
+      return true;
+    }
+  return false;
+}
+
+static void tune_store(int kind, long long nx, long long ny, int ty, int tt) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tune)
+    if (e.first == TuneKey{kind, nx, ny}) {
+      e.second = {ty, tt};
+      return;
+    }
+  g_tune.push_back({TuneKey{kind, nx, ny}, {ty, tt}});
+}
+
+static void tuned_tiles2(const ftk_options& o, int kind, long long nx, long long ny, int nt, int* ty, int* tt) {
+  int dty = 16, dtt = 16;
+  tune_lookup(kind, nx, ny, &dty, &dtt);
+  *ty = o.tile_y ? o.tile_y : dty;
+  *tt = o.slab_depth ? o.slab_depth : dtt;
   if (*tt > nt) *tt = nt;
 }
 
@@ -342,7 +375,7 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
 
   int ty, tt;
-  tuned_tiles2(o, g.nt, &ty, &tt);
+  tuned_tiles2(o, g.kind, nx, ny, g.nt, &ty, &tt);
   Ctl h;
   bool wide = false;
   Phases ph;
@@ -577,7 +610,16 @@ ftk_status track2d_batched_impl(int nser, const float* const* fields, const int6
   const Alloc al = make_alloc(o, s);
   Scratch sc(al);
   constexpr int TYD = 16, TYE = 8;
-  const int ttd = o.slab_depth ? o.slab_depth : 16;
+  // slab depth: the option, else the tuned one of the series with the most vertices, else 16 (rows fixed at 16)
+  int ttd = o.slab_depth;
+  if (!ttd) {
+    int big = 0;
+    for (int i = 1; i < nser; ++i)
+      if (nx[i] * ny[i] * nt[i] > nx[big] * ny[big] * nt[big]) big = i;
+    int tty = 16, ttt = 16;
+    tune_lookup((int)kind, nx[big], ny[big], &tty, &ttt);
+    ttd = ttt;
+  }
   std::vector<Series2> ser(nser);
   std::vector<long long> mask_off(nser), seg_start(nser);
   std::vector<int> pre_d(nser + 1), pre_e(nser + 1);
@@ -1317,3 +1359,72 @@ void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------------------------
+// Autotuning of the 2D detection tiling (tile rows x slab depth) on the caller's field.
+// ---------------------------------------------------------------------------------------------------------------
+extern "C" ftk_status ftk_autotune_cp2d(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,
+                                         const ftk_options* opt, ftk_stream_t stream, ftk_options* tuned) {
+  g_err.clear();
+  if (!field || !tuned) return fail(FTK_ERR_ARG, "field and tuned must be given");
+  if (kind != FTK_SCALAR && kind != FTK_VECTOR) return fail(FTK_ERR_ARG, "kind must be FTK_SCALAR or FTK_VECTOR");
+  if (nx < 2 || ny < 2 || nt < 2) return fail(FTK_ERR_ARG, "nx, ny, nt must be >= 2");
+  if (nx > (1 << 30) || ny > (1 << 30) || nt > (1 << 30)) return fail(FTK_ERR_ARG, "dimension too large");
+  ftk_options o;
+  resolve(opt, &o);
+  ftk_status st = ftk::validate_options(o);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
+  ftk::Grid2 g;
+  g.f = field;
+  g.kind = (int)kind;
+  g.nx = (int)nx;
+  g.ny = (int)ny;
+  g.nt = (int)nt;
+  g.nxt = (int)((nx + 63) / 64);
+  g.qscale = std::ldexp(1.0f, o.quant_log2);
+  g.precision = o.precision;
+  g.t_begin = 0;
+  g.t_end = (int)nt;
+  g.f_ring = 0;
+  g.m_ring = 0;
+  const long long V = (long long)nx * ny * nt, nseg = (long long)nt * ny * g.nxt;
+  uint16_t* masks = sc.get<uint16_t>((size_t)V);
+  int* seg_cnt = sc.get<int>((size_t)nseg);
+  Ctl* dctl = sc.get<Ctl>(1);
+  if (!masks || !seg_cnt || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+  Phases ph;
+  ph.init(true, s);
+  if (!ph.on) return fail(FTK_ERR_HIP, "event creation failed");
+  const int rows[3] = {8, 16, 32}, slabs[3] = {8, 16, 32};
+  int best_ty = 16, best_tt = 16;
+  float best = 1e30f;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const int ty = rows[a], tt = slabs[b] < nt ? slabs[b] : (int)nt;
+      if (b > 0 && slabs[b - 1] >= nt) continue;  // same clamped depth as the previous candidate
+      HIP_TRY(ftk::launch_detect2d(g, ty, tt, false, masks, seg_cnt, &dctl->status, s));  // warm-up
+      ph.mark(0);
+      for (int r = 0; r < 2; ++r) HIP_TRY(ftk::launch_detect2d(g, ty, tt, false, masks, seg_cnt, &dctl->status, s));
+      ph.mark(1);
+      HIP_TRY(hipStreamSynchronize(s));
+      const float ms = ph.ms(0, 1);
+      if (ms < best) {
+        best = ms;
+        best_ty = ty;
+        best_tt = tt;
+      }
+    }
+  Ctl h;
+  st = read_ctl(&h, dctl, s);
+  if (st) return st;
+  if (h.status & ftk::ST_NONFINITE) return decode_status(h.status);
+  ftk::tune_store((int)kind, nx, ny, best_ty, best_tt);
+  *tuned = o;
+  tuned->tile_y = best_ty;
+  tuned->slab_depth = best_tt;
+  return FTK_OK;
+}

@@ -151,3 +151,12 @@ def test_all_outputs_with_mu():
     g = run(f, outputs=F.OUT_ALL)
     assert g["mu"] is not None
     assert_full_parity(g, O.track(f))
+
+
+def test_autotune_picks_a_candidate_and_keeps_parity():
+    """The tuned tiling (remembered for the shape and used by the default call) changes no result."""
+    f = synth.moving_gaussians_2d(150, 90, 10, 10, seed=5, noise_std=1e-3)
+    t = torch.from_numpy(np.ascontiguousarray(f)).to(DEV)
+    ty, tt = F.autotune_cp2d(t)
+    assert ty in (8, 16, 32) and tt in (8, 10)  # slab depths clamp to nt = 10
+    assert_full_parity(run(f), O.track(f))
