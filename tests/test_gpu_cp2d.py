@@ -146,6 +146,34 @@ def test_full_size_c1_sampled():
         assert r["min_face"] == g["label"][i]
 
 
+def test_full_size_c4_sampled():
+    """4096 x 4096 x 50 vector field (the precision workload) in the benchmark's launch configuration: completeness
+    at sampled vertices, outputs of sampled hits and labels of sampled trajectories against the oracle."""
+    u = synth.make("c4", device=DEV)
+    g = to_np(run(u, kind=1))
+    fid = g["face_id"]
+    assert len(fid) > 0 and np.all(np.diff(fid) > 0)
+    rng = np.random.default_rng(4)
+    V = 4096 * 4096 * 50
+    verts = rng.integers(0, V, 400)
+    cand = (verts[:, None] * 12 + np.arange(12)[None, :]).ravel()
+    ev = O.eval_faces(u, cand, kind=1)
+    gpu_hit = np.isin(cand, fid)
+    valid = ev["punctured"] != 255
+    assert np.array_equal(gpu_hit[valid], ev["punctured"][valid].astype(bool))
+    assert not np.any(gpu_hit[~valid])
+    idx = rng.choice(len(fid), min(3000, len(fid)), replace=False)
+    ev = O.eval_faces(u, fid[idx], kind=1)
+    assert np.all(ev["punctured"] == 1)
+    assert np.array_equal(g["type"][idx], ev["type"])
+    assert np.array_equal(g["flags"][idx] & np.uint8(0xFD), ev["flags"])
+    assert_pos_close(g["pos"][idx], ev["pos"])
+    for i in rng.choice(len(fid), 20, replace=False):
+        r = O.trace(u, int(fid[i]), kind=1, max_steps=400000)
+        assert r["closed"] != -1
+        assert r["min_face"] == g["label"][i]
+
+
 def test_all_outputs_with_mu():
     f = synth.moving_gaussians_2d(150, 90, 7, 9, seed=12, noise_std=1e-3)
     g = run(f, outputs=F.OUT_ALL)
