@@ -131,16 +131,45 @@ __device__ __forceinline__ unsigned sos3_positive(const Q* a, const Q* b, const 
   return sos3_tail(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2]);
 }
 
+// The same sequence for narrow entries (below 2^20): every term is an entry or a 2x2 minor below 2^41, exact in
+// 64 bits.  Inlined (no call, so the kernel needs no stack).
+__device__ __forceinline__ unsigned sos3_tail64(long long m00, long long m10, long long m20, long long m01,
+                                                long long m11, long long m21, long long m02, long long m12,
+                                                long long m22) {
+  long long v;
+  v = m11 * m22 - m12 * m21;          // C00
+  if (v != 0) return v > 0;
+  v = -(m01 * m22 - m02 * m21);       // C10
+  if (v != 0) return v > 0;
+  v = m01 * m12 - m02 * m11;          // C20
+  if (v != 0) return v > 0;
+  v = -(m10 * m22 - m12 * m20);       // C01
+  if (v != 0) return v > 0;
+  if (m22 != 0) return m22 < 0;       // -m22
+  if (m12 != 0) return m12 > 0;       // m12
+  v = m00 * m22 - m02 * m20;          // C11
+  if (v != 0) return v > 0;
+  if (m02 != 0) return m02 < 0;       // -m02 (m22 == 0 here)
+  v = -(m00 * m12 - m02 * m10);       // C21
+  if (v != 0) return v > 0;
+  v = m10 * m21 - m11 * m20;          // C02 (m12 == m02 == 0 here)
+  if (v != 0) return v > 0;
+  if (m21 != 0) return m21 > 0;       // m21
+  if (m11 != 0) return m11 < 0;       // -m11
+  if (m20 != 0) return m20 < 0;       // -m20
+  return 0u;                          // -1
+}
+
 // Exact 64-bit evaluation (narrow entries below 2^20: minors below 2^41, terms below 2^61), then SoS.
-__device__ __noinline__ unsigned sos3_exact_narrow(float a0, float a1, float a2, float b0, float b1, float b2,
-                                                   float c0, float c1, float c2) {
+__device__ __forceinline__ unsigned sos3_exact_narrow(float a0, float a1, float a2, float b0, float b1, float b2,
+                                                      float c0, float c1, float c2) {
   const long long A0 = (long long)a0, A1 = (long long)a1, A2 = (long long)a2;
   const long long B0 = (long long)b0, B1 = (long long)b1, B2 = (long long)b2;
   const long long C0 = (long long)c0, C1 = (long long)c1, C2 = (long long)c2;
   const long long m0 = B1 * C2 - B2 * C1, m1 = B0 * C2 - B2 * C0, m2 = B0 * C1 - B1 * C0;
   const long long d = A0 * m0 - A1 * m1 + A2 * m2;
   if (d != 0) return d > 0;
-  return sos3_tail(A0, A1, A2, B0, B1, B2, C0, C1, C2);
+  return sos3_tail64(A0, A1, A2, B0, B1, B2, C0, C1, C2);
 }
 
 // Narrow sign of det(a, b, c): the 2x2 minors are exact in binary64 (integers below 2^41); the three products and
