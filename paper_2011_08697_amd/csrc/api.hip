@@ -543,7 +543,8 @@ ftk_status track3d_impl(const float* field, int64_t nx, int64_t ny, int64_t nz, 
   if (outs & FTK_OUT_LABEL) r.label = (int64_t*)al.get(sizeof(int64_t) * nh);
   unsigned* parent = sc.get<unsigned>((size_t)nh);
   uint2* work = sc.get<uint2>((size_t)nh);
-  bool oom = !r.face_id || !parent || !work || ((outs & FTK_OUT_POS) && !r.pos) || ((outs & FTK_OUT_MU) && !r.mu) ||
+  long long* list = sc.get<long long>((size_t)nh);  // row chunks with hits: at most one per hit
+  bool oom = !r.face_id || !parent || !work || !list || ((outs & FTK_OUT_POS) && !r.pos) || ((outs & FTK_OUT_MU) && !r.mu) ||
              ((outs & FTK_OUT_TYPE) && !r.type) || ((outs & FTK_OUT_FLAGS) && !r.flags) ||
              ((outs & FTK_OUT_LABEL) && !r.label);
   if (oom) {
@@ -561,7 +562,7 @@ ftk_status track3d_impl(const float* field, int64_t nx, int64_t ny, int64_t nz, 
   hipError_t he = hipSuccess;
   ph.mark(3);
   if (nh > 0) {
-    he = launch_emit3d(g, wide, masks, seg_off, nseg, od, &dctl->status, dctl->cnt, s);
+    he = launch_emit3d(g, wide, masks, seg_off, nh, od, &dctl->status, dctl->cnt, list, &dctl->cnt[CNT_LIST], s);
     ph.mark(4);
     if (he == hipSuccess) he = launch_uf_hook(parent, work, &dctl->cnt[CNT_WORK], nh, s);
     if (he == hipSuccess) he = launch_uf_label(parent, od.face_id, (long long*)r.label, nh, dctl->cnt, s);

@@ -18,7 +18,7 @@ enum : unsigned {
 };
 
 // Device counters (int64 each).
-enum { CNT_FP64 = 0, CNT_DEGEN = 1, CNT_LINKED = 2, CNT_WORK = 3, CNT_TRAJ = 4, CNT_N = 8 };
+enum { CNT_FP64 = 0, CNT_DEGEN = 1, CNT_LINKED = 2, CNT_WORK = 3, CNT_TRAJ = 4, CNT_LIST = 5, CNT_N = 8 };
 
 // Hit flags.
 enum : unsigned { FL_DEGENERATE = 1u, FL_FP64 = 2u, FL_WIDE = 4u };

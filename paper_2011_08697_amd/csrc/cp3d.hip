@@ -515,13 +515,35 @@ __device__ __noinline__ int classify3_fp64(double mu0, double mu1, double mu2, d
 
 }  // namespace
 
+// Wavefronts whose 64 vertices hold hits: a light pass over all masks that lists them (one append per such wave),
+// so the heavy emission kernel (large register footprint, low occupancy) runs only where there is work.
+__global__ __launch_bounds__(256) void emit3d_rows(Grid3 g, const uint64_t* __restrict__ masks, long long nvtx_rows,
+                                                   long long* __restrict__ list,
+                                                   unsigned long long* __restrict__ list_n) {
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int xblocks = (nx + 63) / 64;
+  if (row >= nvtx_rows * xblocks) return;
+  const long long r = row / xblocks;
+  const int x = (int)(row - r * xblocks) * 64 + lane;
+  const int y = (int)(r % ny), z = (int)((r / ny) % nz), t = (int)(r / ((long long)ny * nz));
+  const long long plane = (long long)nx * ny * nz;
+  const unsigned long long m = x < nx ? masks[(long long)t * plane + ((long long)z * ny + y) * nx + x] : 0ull;
+  if (__ballot(m != 0) != 0 && lane == 0) list[atomicAdd(list_n, 1ull)] = row;
+}
+
 template <bool WIDE>
 __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restrict__ masks,
                                               const long long* __restrict__ seg_off, long long nvtx_rows, Out3 o,
-                                              unsigned* __restrict__ status, unsigned long long* __restrict__ cnt) {
-  // thread -> vertex (x fastest, 16-wide segments)
+                                              unsigned* __restrict__ status, unsigned long long* __restrict__ cnt,
+                                              const long long* __restrict__ list,
+                                              const unsigned long long* __restrict__ list_n) {
+  // thread -> vertex (x fastest, 16-wide segments); wavefront -> one listed 64-vertex row chunk
   const int nx = g.nx, ny = g.ny, nz = g.nz, nt = g.nt, nxt = g.nxt;
-  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);  // wave -> 64 x-values of one row
+  const unsigned long long wi = (unsigned long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wi >= *list_n) return;
+  const long long row = list[wi];
   const int lane = threadIdx.x & 63;
   const int xblocks = (nx + 63) / 64;
   if (row >= nvtx_rows * xblocks) return;
@@ -750,16 +772,19 @@ hipError_t launch_detect3d(const Grid3& g, int tt, bool wide, uint64_t* masks, i
   return hipGetLastError();
 }
 
-hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const long long* seg_off, long long nseg,
-                         const Out3& o, unsigned* status, unsigned long long* cnt, hipStream_t s) {
-  (void)nseg;
+hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const long long* seg_off, long long n_hits,
+                         const Out3& o, unsigned* status, unsigned long long* cnt, long long* list,
+                         unsigned long long* list_n, hipStream_t s) {
   const long long rows = (long long)g.nt * g.nz * g.ny;
   const long long waves = rows * ((g.nx + 63) / 64);
-  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  emit3d_rows<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(g, masks, rows, list, list_n);
+  // at most one listed wavefront per hit
+  const long long lw = n_hits < waves ? n_hits : waves;
+  const unsigned blocks = (unsigned)((lw + 3) / 4 > 0 ? (lw + 3) / 4 : 1);
   if (wide)
-    emit3d<true><<<blocks, 256, 0, s>>>(g, masks, seg_off, rows, o, status, cnt);
+    emit3d<true><<<blocks, 256, 0, s>>>(g, masks, seg_off, rows, o, status, cnt, list, list_n);
   else
-    emit3d<false><<<blocks, 256, 0, s>>>(g, masks, seg_off, rows, o, status, cnt);
+    emit3d<false><<<blocks, 256, 0, s>>>(g, masks, seg_off, rows, o, status, cnt, list, list_n);
   return hipGetLastError();
 }
 
