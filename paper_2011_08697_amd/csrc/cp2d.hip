@@ -850,7 +850,8 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           const float2 v = G[c];
           qf[i][0] = quant(v.x, g.qscale);
           qf[i][1] = quant(v.y, g.qscale);
-          if (!(fabsf(qf[i][0]) < 2147483648.0f) || !(fabsf(qf[i][1]) < 2147483648.0f)) wide = true;
+          if constexpr (WIDE)  // the narrow variant only runs when every |q| < 2^24
+            if (!(fabsf(qf[i][0]) < 2147483648.0f) || !(fabsf(qf[i][1]) < 2147483648.0f)) wide = true;
           const int gxv = x0 + lxs[i], gyv = y0 + lys[i];
           const float2 xl = G[c - 1], xh = G[c + 1], yl = G[c - GW], yh = G[c + GW];
           J[i][0] = diff3(xl.x, v.x, xh.x, gxv, nx);
