@@ -1,6 +1,6 @@
 """Benchmark: spacetime simplices tested per second for critical-point tracking on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1] [--no-cpu-baseline]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload noise1024] [--no-cpu-baseline]
 
 One step = one ftk_track_cp2d/3d call over the whole series (detection of every n-simplex, compaction,
 sublocation, classification, union-find stitching, labels) with the input already resident in HBM.  Prints one
@@ -22,12 +22,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s
 
 WORKLOADS = {
-    "c0": "2D scalar 64x64x10, 8 moving Gaussians, seed 0",
-    "c1": "2D scalar 1024x1024x100, 256 moving Gaussians + N(0,1e-3) noise, seed 1",
-    "c1deg": "2D scalar 1024x1024x100, c1 field rounded to 16 levels",
-    "c2": "3D scalar 256x256x256x16, 512 moving Gaussians, seed 2",
-    "c4": "2D vector 4096x4096x50, 1024 moving sources/sinks/vortices, seed 4",
-    "c3": "96 uneven 2D scalar series (nx, ny log-uniform 128-2048, 8-64 steps), seeds 3+i; batched vs plain",
+    "blobs64": "2D scalar 64x64x10, 8 moving Gaussians, seed 0",
+    "noise1024": "2D scalar 1024x1024x100, 256 moving Gaussians + N(0,1e-3) noise, seed 1",
+    "levels1024": "2D scalar 1024x1024x100, the noisy blob field rounded to 16 levels",
+    "blobs3d256": "3D scalar 256x256x256x16, 512 moving Gaussians, seed 2",
+    "vortex4096": "2D vector 4096x4096x50, 1024 moving sources/sinks/vortices, seed 4",
+    "batch96": "96 uneven 2D scalar series (nx, ny log-uniform 128-2048, 8-64 steps), seeds 3+i; batched vs plain",
 }
 
 
@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="noise1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="time steps of the oracle sample (0: automatic)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -132,7 +132,7 @@ def bench_batched(args, F, synth, dev):
         "value": round(tested / tb, 1), "unit": "simplices/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": WORKLOADS["c3"], "series": len(fields), "time_steps_total": steps_total,
+        "config": {"workload": WORKLOADS["batch96"], "series": len(fields), "time_steps_total": steps_total,
                    "vertices_total": int(sum(f.size for f in fields)), "n_hits": nhb, "generation_s": round(gen_s, 1)},
         "batched": {"steps_per_s": round(steps_total / tb, 1), "ms_per_batch": round(tb * 1e3, 3),
                     "phase_ms": phases},
@@ -166,8 +166,8 @@ def precision_report(F, field_np, field, kind, n, sample=20000):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (time-slab sharding is described "
-              "in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (a series would shard by time "
+              "slabs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
@@ -182,12 +182,12 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     wl = args.workload
-    if wl == "c3":
+    if wl == "batch96":
         return bench_batched(args, F, synth, dev)
-    n = 3 if wl == "c2" else 2
-    kind = 1 if wl == "c4" else 0
+    n = 3 if wl == "blobs3d256" else 2
+    kind = 1 if wl == "vortex4096" else 0
     t0 = time.time()
-    field_np = synth.make(wl, device=dev if wl in ("c2", "c4") else None)
+    field_np = synth.make(wl, device=dev if wl in ("blobs3d256", "vortex4096") else None)
     gen_s = time.time() - t0
     field = torch.from_numpy(field_np).to(dev)
     if n == 2:
@@ -257,8 +257,8 @@ def main():
     if not args.no_cpu_baseline and n == 2:
         from oracle import oracle as O
         cores = min(16, len(os.sched_getaffinity(0)))
-        steps = args.cpu_steps or (20 if wl in ("c1", "c1deg") else 3)
-        if wl == "c0":
+        steps = args.cpu_steps or (20 if wl in ("noise1024", "levels1024") else 3)
+        if wl == "blobs64":
             sample = field_np
         else:
             sample = np.ascontiguousarray(field_np[:steps])
@@ -272,7 +272,7 @@ def main():
                          f"{cpu_s:.1f} s)"}
 
     precision = None
-    if wl == "c4":
+    if wl == "vortex4096":
         precision = precision_report(F, field_np, field, kind, n)
 
     line = {

@@ -20,7 +20,7 @@
  *     (n+1)-simplex with union-find.
  *   - Sec. 4.1: critical-point types from the spatial Jacobian.
  * Readings where the paper is silent (vertex order, SoS exponents, stencil at the boundary, quantisation,
- * type ties, trajectory identity) are listed in the design doc of this repository and restated at each function.
+ * type ties, trajectory identity) are stated at each function.
  *
  * Exactness: vectors are quantised to integers; every determinant is computed exactly in 128-bit integers
  * (the accepted value ranges keep all products in range).  Floating point appears only in the stencils

@@ -261,30 +261,30 @@ def spiral_woven(size, nt, extent, dt):
 
 
 # Named workloads (sizes of the paper-shaped synthetic configurations).
-CONFIGS = {
-    "c0": dict(n=2, kind=0, dims=(64, 64, 10), K=8, seed=0),
-    "c1": dict(n=2, kind=0, dims=(1024, 1024, 100), K=256, seed=1, noise_std=1e-3),
-    "c2": dict(n=3, kind=0, dims=(256, 256, 256, 16), K=512, seed=2),
-    "c4": dict(n=2, kind=1, dims=(4096, 4096, 50), K=1024, seed=4),
+WORKLOAD_PARAMS = {
+    "blobs64": dict(n=2, kind=0, dims=(64, 64, 10), K=8, seed=0),
+    "noise1024": dict(n=2, kind=0, dims=(1024, 1024, 100), K=256, seed=1, noise_std=1e-3),
+    "blobs3d256": dict(n=3, kind=0, dims=(256, 256, 256, 16), K=512, seed=2),
+    "vortex4096": dict(n=2, kind=1, dims=(4096, 4096, 50), K=1024, seed=4),
 }
 
 
 def make(name, nt=None, ny=None, device=None):
     """Generate a named workload (optionally only the first nt steps / ny rows; device: torch device for the 3D
     field's float64 evaluation)."""
-    c = CONFIGS[name]
-    if name == "c0":
+    c = WORKLOAD_PARAMS[name]
+    if name == "blobs64":
         nx, nyy, ntt = c["dims"]
         return moving_gaussians_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"])
-    if name in ("c1", "c1deg"):
-        c = CONFIGS["c1"]
+    if name in ("noise1024", "levels1024"):
+        c = WORKLOAD_PARAMS["noise1024"]
         nx, nyy, ntt = c["dims"]
         f = moving_gaussians_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"], noise_std=c["noise_std"])
-        return quantise_levels(f) if name == "c1deg" else f
-    if name == "c2":
+        return quantise_levels(f) if name == "levels1024" else f
+    if name == "blobs3d256":
         nx, nyy, nz, ntt = c["dims"]
         return moving_gaussians_3d(nx, ny or nyy, nz, nt or ntt, c["K"], seed=c["seed"], device=device)
-    if name == "c4":
+    if name == "vortex4096":
         nx, nyy, ntt = c["dims"]
         return vortex_sources_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"], device=device)
     raise KeyError(name)

@@ -24,8 +24,8 @@ def run(field, kind=0, **kw):
     return r
 
 
-def test_c0_full_parity():
-    f = synth.make("c0")
+def test_blobs64_full_parity():
+    f = synth.make("blobs64")
     assert_full_parity(run(f), O.track(f))
 
 
@@ -83,7 +83,7 @@ def test_wide_path_and_range_error():
 
 
 def test_errors():
-    f = synth.make("c0")
+    f = synth.make("blobs64")
     f[3, 10, 10] = np.nan
     with pytest.raises(F.FtkError) as e:
         run(f)
@@ -99,7 +99,7 @@ def test_all_zero_and_constant_fields():
 
 
 def test_outputs_subset():
-    f = synth.make("c0")
+    f = synth.make("blobs64")
     g = run(f, outputs=F.OUT_POS)
     assert g["type"] is None and g["label"] is None and g["pos"] is not None
     tr = O.track(f)
@@ -115,10 +115,10 @@ def test_determinism_repeated_runs():
             assert np.array_equal(a[k], b[k])
 
 
-def test_full_size_c1_sampled():
+def test_full_size_noise1024_sampled():
     """1024 x 1024 x 100 (the benchmark workload): every GPU output checked at sampled vertices and hits against
     point queries of the oracle, plus the trajectory of sampled hits traced through the cells."""
-    f = synth.make("c1")
+    f = synth.make("noise1024")
     g = to_np(run(f))
     fid = g["face_id"]
     assert np.all(np.diff(fid) > 0)
@@ -146,10 +146,10 @@ def test_full_size_c1_sampled():
         assert r["min_face"] == g["label"][i]
 
 
-def test_full_size_c4_sampled():
+def test_full_size_vortex4096_sampled():
     """4096 x 4096 x 50 vector field (the precision workload) in the benchmark's launch configuration: completeness
     at sampled vertices, outputs of sampled hits and labels of sampled trajectories against the oracle."""
-    u = synth.make("c4", device=DEV)
+    u = synth.make("vortex4096", device=DEV)
     g = to_np(run(u, kind=1))
     fid = g["face_id"]
     assert len(fid) > 0 and np.all(np.diff(fid) > 0)

@@ -67,10 +67,10 @@ def test_errors_3d():
     assert e.value.status == 2
 
 
-def test_full_size_c2_sampled():
+def test_full_size_blobs3d256_sampled():
     """256^3 x 16: sampled anchors (all 60 tetrahedra) and sampled hits against point queries of the oracle;
     labels of sampled hits by walking the trajectory through the pentachora."""
-    f = synth.make("c2", device=DEV)
+    f = synth.make("blobs3d256", device=DEV)
     g = to_np(run(f))
     fid = g["face_id"]
     assert g["n_hits"] > 0 and np.all(np.diff(fid) > 0)

@@ -42,7 +42,7 @@ def _check_table(g, o):
 
 
 CASES = {
-    "c0": lambda: (synth.make("c0"), 2, 0),
+    "blobs64": lambda: (synth.make("blobs64"), 2, 0),
     "noise_crop": lambda: (synth.moving_gaussians_2d(200, 150, 12, 12, seed=1, noise_std=1e-3), 2, 0),
     "vector": lambda: (synth.vortex_sources_2d(96, 80, 9, 12, seed=4), 2, 1),
     "3d": lambda: (synth.moving_gaussians_3d(24, 20, 18, 5, 6, seed=2), 3, 0),

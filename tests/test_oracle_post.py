@@ -61,7 +61,7 @@ def test_birth_death_pair_is_one_loop_with_its_time_extent():
 def test_every_trajectory_is_a_path_or_a_loop(case):
     """Under SoS the trajectories form a 1-manifold: a component has two ends on the grid boundary or none."""
     if case == "blob":
-        f, n = synth.make("c0"), 2
+        f, n = synth.make("blobs64"), 2
     elif case == "degenerate":
         f, n = synth.quantise_levels(synth.moving_gaussians_2d(48, 40, 6, 6, seed=11, noise_std=1e-3)), 2
     else:

@@ -111,7 +111,7 @@ def _degrees_equal_cofaces(tr, dims, n):
 
 
 def test_invariants_on_blob_field():
-    f = synth.make("c0")
+    f = synth.make("blobs64")
     tr = O.track(f)
     assert tr.status == 0 and tr.invariant_violations == 0
     assert tr.n_hits == 332 and int(np.isin(tr.face_id % 12, ORDINAL_2D).sum()) == 73
@@ -300,7 +300,7 @@ def test_stencil_on_linear_and_quadratic_fields():
 
 def test_sublocation_matches_exact_rationals():
     """mu from the oracle (binary64) against the exact rational solution of Eq. 2 on the quantised vectors."""
-    f = synth.make("c0")
+    f = synth.make("blobs64")
     tr = O.track(f)
     st, q = O.quantise_all(f)
     g = R.Grid((64, 64, 10))
@@ -328,7 +328,7 @@ def test_sublocation_matches_exact_rationals():
 
 
 def test_point_queries_agree_with_whole_field_run():
-    f = synth.make("c0")
+    f = synth.make("blobs64")
     tr = O.track(f)
     rng = np.random.default_rng(2)
     fids = np.concatenate([tr.face_id[rng.choice(tr.n_hits, 50, replace=False)],
