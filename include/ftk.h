@@ -144,7 +144,7 @@ ftk_status ftk_track_cp3d(const float* field, ftk_field_kind kind, int64_t nx, i
 
 /*
  * Streaming form, after the paper's push_field_data() and its two-step sliding window of ordinal and interval
- * elements (Sec. 3.1 "Ordinal and interval mesh elements", Sec. 8 "C++ programming interface").
+ * elements (Sec. 3.2 "Ordinal and interval mesh elements", Sec. 8 "C++ programming interface").
  *   ftk_cp_create: n = 2 or 3, dims = (nx, ny[, nz]); the tracker keeps the last pushed step on the device.
  *   ftk_cp_push:   step = device pointer to one time step in the layout above (for vector input [2][ny][nx]); the
  *                  caller may overwrite it once `stream` has passed the call.  Ordinal simplices of the step and
@@ -192,7 +192,7 @@ ftk_status ftk_traj_table_build(const ftk_cp_result* r, int32_t n, const int64_t
 void ftk_traj_table_free(ftk_traj_table* tt, const ftk_options* opt, ftk_stream_t stream);
 
 /*
- * Critical points at time step t0 (Sec. 3.1, slicing through the ordinal faces): *idx receives a device array
+ * Critical points at time step t0 (Sec. 3.2, slicing through the ordinal faces): *idx receives a device array
  * (allocated through opt->alloc; release with ftk_buffer_free) of the ascending indices, into the result's
  * arrays, of the punctured faces anchored at step t0 that do not use the time axis; *count their number (host).
  * 0 <= t0 < nt, else FTK_ERR_ARG.

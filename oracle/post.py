@@ -1,7 +1,7 @@
 """Trajectory post-processing on the oracle's results (test infrastructure only, like the rest of oracle/).
 
 Plain numpy over the host arrays of an oracle run, written from the definitions:
-  * slicing at a time step (Sec. 3.1, "Ordinal and interval mesh elements"): the critical points of step t0 are the
+  * slicing at a time step (Sec. 3.2, "Ordinal and interval mesh elements"): the critical points of step t0 are the
     punctured faces anchored at t0 whose vertices all lie in that step (no time axis in their type);
   * per-trajectory attributes for filtering (Sec. 4.4, "Filtering"): number of points, time extent of their
     positions, and the number of points that lie in only one cell of the grid (the trajectory's ends, counted

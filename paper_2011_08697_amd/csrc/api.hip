@@ -794,7 +794,7 @@ ftk_status track2d_batched_impl(int nser, const float* const* fields, const int6
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Streaming (Sec. 3.1 "Ordinal and interval mesh elements": every simplex is visited with a sliding window of two
+// Streaming (Sec. 3.2 "Ordinal and interval mesh elements": every simplex is visited with a sliding window of two
 // time steps).  2D: the tracker keeps the last three steps in a ring; pushing step s detects the anchors of step
 // s-1 (its ordinal simplices and the interval ones towards s) and emits step s-2, whose +t neighbour masks now
 // exist.  finish() closes the series and runs the global union-find passes.  3D: the steps are accumulated on the

@@ -1,6 +1,6 @@
 // post.hip -- trajectory post-processing on the device, after the tracking passes.
 //
-//   * Slicing at a time step (Sec. 3.1, "Ordinal and interval mesh elements"): the critical points of step t0 are
+//   * Slicing at a time step (Sec. 3.2, "Ordinal and interval mesh elements"): the critical points of step t0 are
 //     the punctured ordinal faces anchored at t0 (faces whose axis masks do not use the time axis).  Hits are
 //     sorted by face id and face ids are t-major, so they form one contiguous range of the hit arrays.
 //   * Per-trajectory attributes for filtering (Sec. 4.4, "Filtering"): number of points, time extent of their

@@ -96,7 +96,7 @@ def test_simplex_count_named_workloads():
 
 @pytest.mark.parametrize("dims", [(4, 3, 3), (3, 3, 2, 2)])
 def test_faces_in_one_or_two_cells(dims):
-    """Each n-face lies in exactly two (n+1)-simplices, one if it is on the domain boundary (Sec. 3.1)."""
+    """Each n-face lies in exactly two (n+1)-simplices, one if it is on the domain boundary (Sec. 3.2)."""
     n = len(dims) - 1
     g = R.Grid(dims)
     owners, verts = {}, {}
