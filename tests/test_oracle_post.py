@@ -94,3 +94,134 @@ def test_slice_equals_facewise_test_of_the_step():
         expect = np.sort(fids[ev["punctured"] == 1])
         got = tr.face_id[P.slice_at(tr, 2, dims, t0)]
         assert np.array_equal(got, expect)
+
+
+# ---------------------------------------------------------------------------------------------------------------
+# Order along the trajectories, type smoothing and simplification (Sec. 4.4).
+# ---------------------------------------------------------------------------------------------------------------
+
+def _face_vertices(fid, n, dims):
+    """Vertex coordinates (x, y, [z], t) of a face, decoded here from its id and the face's axis masks."""
+    T = 12 if n == 2 else 60
+    masks = O.kuhn_types(n + 1, n)[fid % T]
+    g = fid // T
+    c = []
+    for a in range(n + 1):
+        c.append(g % dims[a] if a < n else g)
+        g //= dims[a] if a < n else 1
+    vs = [tuple(c)]
+    for m in masks:
+        v = list(vs[-1])
+        for a in range(n + 1):
+            if (int(m) >> a) & 1:
+                v[a] += 1
+        vs.append(tuple(v))
+    return vs
+
+
+def _share_a_cell(f1, f2, n, dims):
+    """Two faces are sides of one cell: their vertices together form a unit-step chain across one unit cube."""
+    vs = sorted(set(_face_vertices(f1, n, dims)) | set(_face_vertices(f2, n, dims)), key=sum)
+    if len(vs) != n + 2:
+        return False
+    steps = [np.subtract(vs[k + 1], vs[k]) for k in range(n + 1)]
+    return all(s.min() == 0 and s.sum() == 1 for s in steps) and np.array_equal(np.subtract(vs[-1], vs[0]),
+                                                                                np.ones(n + 1))
+
+
+def _check_order(tr, n, dims, tab, order, offsets):
+    assert np.array_equal(np.sort(order), np.arange(tr.n_hits))
+    assert offsets[0] == 0 and offsets[-1] == tr.n_hits and len(offsets) == tab["n"] + 1
+    for j in range(tab["n"]):
+        seq = order[offsets[j]:offsets[j + 1]]
+        assert np.all(tr.label[seq] == tab["label"][j])
+        assert len(seq) == tab["n_points"][j]
+        links = list(zip(seq[:-1], seq[1:])) + ([(seq[-1], seq[0])] if tab["n_ends"][j] == 0 else [])
+        for a, b in links:
+            assert _share_a_cell(int(tr.face_id[a]), int(tr.face_id[b]), n, dims)
+            # the curve's piece in a cell is a segment inside that unit cube
+            assert np.all(np.abs(tr.pos[a] - tr.pos[b]) <= 1.0 + 1e-12)
+        if tab["n_ends"][j] == 0:
+            assert tr.face_id[seq[0]] == tab["label"][j]
+            assert tr.face_id[seq[1]] < tr.face_id[seq[-1]]
+        else:
+            assert tr.face_id[seq[0]] < tr.face_id[seq[-1]]
+
+
+@pytest.mark.parametrize("n,size,direction,nt", [(2, 21, (0.5, -0.25), 9), (3, 13, (0.25, 0.0, -0.5), 5)])
+def test_moving_minimum_is_ordered_forward_in_time(n, size, direction, nt):
+    """The single trajectory of a moving minimum starts on the t = 0 plane and its time coordinate never decreases
+    along the order; consecutive points are two sides of one cell."""
+    f = synth.moving_minimum(n, size, [size // 2] * n, list(direction), nt)
+    tr = O.track(f, n=n)
+    dims = tuple([size] * n + [nt])
+    tab = P.traj_table(tr, n, dims)
+    order, offsets = P.traj_order(tr, n, dims, tab)
+    _check_order(tr, n, dims, tab, order, offsets)
+    t = tr.pos[order, n]
+    assert t[0] == 0.0 and t[-1] == nt - 1 and np.all(np.diff(t) >= 0)
+
+
+def test_birth_death_loop_order_crosses_the_fold_twice():
+    """The birth-death loop is one cycle whose consecutive points share a cell; the minimum branch (x > 0 about the
+    centre) and the saddle branch (x < 0) meet at the two folds, so the sign of x changes exactly twice around it."""
+    f, dims = _birth_death_field()
+    tr = O.track(f)
+    tab = P.traj_table(tr, 2, dims)
+    order, offsets = P.traj_order(tr, 2, dims, tab)
+    _check_order(tr, 2, dims, tab, order, offsets)
+    side = np.sign(tr.pos[order, 0] - 16.0)
+    side = side[side != 0]
+    assert int(np.sum(side != np.roll(side, 1))) == 2
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_degenerate_grid_orders_are_curves(seed):
+    """On integer fields with many exact zeros every trajectory is walked as one curve: consecutive points share a
+    cell, a path runs between its two boundary ends, a loop closes."""
+    rng = np.random.default_rng(seed)
+    f = rng.integers(-1, 2, size=(5, 7, 6)).astype(np.float32)
+    tr = O.track(f)
+    dims = (6, 7, 5)
+    tab = P.traj_table(tr, 2, dims)
+    order, offsets = P.traj_order(tr, 2, dims, tab)
+    _check_order(tr, 2, dims, tab, order, offsets)
+
+
+def _one(types, loop=False):
+    m = len(types)
+    return np.arange(m, dtype=np.int64), np.array([0, m], np.int64), np.array([loop]), np.array(types, np.uint8)
+
+
+@pytest.mark.parametrize("types,loop,w,expect", [
+    ([1, 1, 3, 1, 1], False, 2, [1, 1, 1, 1, 1]),
+    ([1, 1, 3, 1, 1], False, 1, [1, 1, 1, 1, 1]),
+    ([1, 3, 1, 1, 1], False, 2, [1, 3, 1, 1, 1]),   # too close to the end for a half window of 2
+    ([1, 3, 1, 1, 1], False, 1, [1, 1, 1, 1, 1]),
+    ([1, 1, 3, 3, 1, 1], False, 1, [1, 1, 3, 3, 1, 1]),
+    ([1, 1, 3, 1, 3, 1, 1], False, 1, [1, 1, 1, 3, 1, 1, 1]),  # decisions read the input types only
+    ([2, 1, 1, 1, 1], True, 2, [1, 1, 1, 1, 1]),    # a loop wraps around
+    ([2, 1, 1, 1], True, 2, [2, 1, 1, 1]),          # loop shorter than the window
+    ([1, 2, 1, 2, 1, 2], True, 1, [2, 1, 2, 1, 2, 1]),
+])
+def test_smoothing_worked_examples(types, loop, w, expect):
+    order, offsets, is_loop, ty = _one(types, loop)
+    assert P.smooth_types(order, offsets, is_loop, ty, w).tolist() == expect
+
+
+A, B, C = 1, 3, 4
+
+
+@pytest.mark.parametrize("types,t,loop,theta,expect", [
+    # a short saddle run between two persistent runs of one type merges into them (Sec. 4.4 example)
+    ([A, A, A, B, B, A, A, A], [0, 1, 2, 2.2, 2.4, 2.6, 3.6, 4.6], False, 1.0, [A] * 8),
+    ([A, A, A, B, B, A, A, A], [0, 1, 2, 2.2, 2.4, 2.6, 3.6, 4.6], False, 0.1, [A, A, A, B, B, A, A, A]),
+    ([A, A, A, B, B, A, A, A], [0, 1, 2, 2.2, 2.4, 2.6, 3.6, 4.6], False, 2.5, [A, A, A, B, B, A, A, A]),
+    ([A, B, B, C, C], [0, 1, 1.1, 2, 3], False, 0.5, [A, B, B, C, C]),       # neighbours of different types
+    ([B, A, A, A], [0, 1, 2, 3], False, 0.5, [B, A, A, A]),                  # a run at a path end stays
+    ([A, A, B, A], [0, 1, 1.1, 0.5], True, 0.5, [A, A, A, A]),               # on a loop the run wraps around
+    ([A, A, B, B], [0, 0.1, 0.2, 0.3], True, 1.0, [A, A, B, B]),             # both runs short: neither changes
+])
+def test_simplification_worked_examples(types, t, loop, theta, expect):
+    order, offsets, is_loop, ty = _one(types, loop)
+    assert P.simplify_types(order, offsets, is_loop, ty, np.array(t, float), theta).tolist() == expect
