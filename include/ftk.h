@@ -208,6 +208,45 @@ ftk_status ftk_cp_slice(const ftk_cp_result* r, int32_t n, const int64_t* dims_w
 ftk_status ftk_cp_filter_loops(const ftk_cp_result* r, const ftk_traj_table* tt, float min_duration,
                                ftk_stream_t stream, uint8_t* keep);
 
+/*
+ * Order of the points along each trajectory (Sec. 3.1: a trajectory is a PL curve whose piece in each cell is the
+ * segment between the cell's two punctured sides; Alg. 1 pass 2).  tt must come from ftk_traj_table_build on the
+ * same result, which must carry its label array.
+ *   order   (device, caller-owned, n_hits entries): hit indices grouped by trajectory in the table's (ascending
+ *           label) order, each in curve order.  A path runs from its end with the smaller face id to the other
+ *           end; a closed loop starts at its label face and steps first to its neighbour with the smaller face id.
+ *   offsets (device, caller-owned, n_trajectories + 1 entries): start of each trajectory in order[], n_hits last.
+ * Synchronises the stream once per list-ranking round (about log2 of the longest trajectory).  FTK_ERR_CAPACITY
+ * beyond 2^31 - 1 points; FTK_ERR_INVARIANT if a cell holding a punctured face has no or several other punctured
+ * sides, or a trajectory is not one curve.
+ */
+ftk_status ftk_traj_order(const ftk_cp_result* r, int32_t n, const int64_t* dims_with_t, const ftk_traj_table* tt,
+                          const ftk_options* opt, ftk_stream_t stream, int64_t* order, int64_t* offsets);
+
+/*
+ * Type smoothing along the order (Sec. 4.4 "Smoothing", window shifting): type_out[i] becomes the type shared by
+ * the half_window points before and the half_window points after hit i on its trajectory when those points all
+ * have one type that differs from type_in[i]; otherwise type_in[i].  Every decision reads type_in (marks first,
+ * changes after the pass).  Loops wrap around; a loop of fewer than 2 * half_window + 1 points and the points of a
+ * path closer than half_window to an end keep their types.  order/offsets as from ftk_traj_order; type_in and
+ * type_out are device arrays of n_hits bytes (for instance the result's type array) that must not overlap.
+ */
+ftk_status ftk_traj_smooth_types(const ftk_cp_result* r, const ftk_traj_table* tt, const int64_t* order,
+                                 const int64_t* offsets, const uint8_t* type_in, int32_t half_window,
+                                 const ftk_options* opt, ftk_stream_t stream, uint8_t* type_out);
+
+/*
+ * Type simplification along the order (Sec. 4.4 "Simplification", persistence in time): a run is a maximal
+ * stretch of consecutive points of one type on a trajectory (on a loop, runs wrap around), its time extent the
+ * largest minus the smallest time coordinate (pos[.][n], FP32) of its points.  A run whose extent is below
+ * min_persistence, lying between two runs of one common type whose extents are both at least min_persistence,
+ * takes that type.  Runs at the ends of a path have one neighbour and keep their type; on a loop of two runs both
+ * neighbours are the other run.  Decisions read type_in only.  Arrays as ftk_traj_smooth_types; needs pos.
+ */
+ftk_status ftk_traj_simplify_types(const ftk_cp_result* r, const ftk_traj_table* tt, const int64_t* order,
+                                   const int64_t* offsets, const uint8_t* type_in, float min_persistence,
+                                   const ftk_options* opt, ftk_stream_t stream, uint8_t* type_out);
+
 /* Release a device array returned by the library (with the allocator given in opt, which may be NULL). */
 void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream);
 

@@ -21,7 +21,8 @@ SCALAR, VECTOR = 0, 1
 EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_create", "ftk_cp_push",
            "ftk_cp_finish", "ftk_cp_destroy", "ftk_track_cp2d_batched", "ftk_result_free", "ftk_simplex_count",
            "ftk_last_error", "ftk_version", "ftk_traj_table_build", "ftk_traj_table_free", "ftk_cp_slice",
-           "ftk_cp_filter_loops", "ftk_buffer_free", "ftk_autotune_cp2d"]
+           "ftk_cp_filter_loops", "ftk_buffer_free", "ftk_autotune_cp2d", "ftk_traj_order",
+           "ftk_traj_smooth_types", "ftk_traj_simplify_types"]
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -107,6 +108,15 @@ def lib():
         L.ftk_cp_filter_loops.argtypes = [ctypes.POINTER(Result), ctypes.POINTER(TrajTable), ctypes.c_float, vp, vp]
         L.ftk_cp_filter_loops.restype = ctypes.c_int
         L.ftk_buffer_free.argtypes = [vp, ctypes.POINTER(Options), vp]
+        L.ftk_traj_order.argtypes = [ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(i64),
+                                     ctypes.POINTER(TrajTable), ctypes.POINTER(Options), vp, vp, vp]
+        L.ftk_traj_order.restype = ctypes.c_int
+        L.ftk_traj_smooth_types.argtypes = [ctypes.POINTER(Result), ctypes.POINTER(TrajTable), vp, vp, vp,
+                                            ctypes.c_int32, ctypes.POINTER(Options), vp, vp]
+        L.ftk_traj_smooth_types.restype = ctypes.c_int
+        L.ftk_traj_simplify_types.argtypes = [ctypes.POINTER(Result), ctypes.POINTER(TrajTable), vp, vp, vp,
+                                              ctypes.c_float, ctypes.POINTER(Options), vp, vp]
+        L.ftk_traj_simplify_types.restype = ctypes.c_int
         L.ftk_buffer_free.restype = None
         L.ftk_autotune_cp2d.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.POINTER(Options), vp,
                                         ctypes.POINTER(Options)]
@@ -351,13 +361,63 @@ def filter_loops(res, table, min_duration):
     dev = _device_of(res)
     keep = torch.empty(res["n_hits"], dtype=torch.uint8, device=dev)
     r = _as_result(res)
+    t = _table_struct(table)
+    _check(lib().ftk_cp_filter_loops(ctypes.byref(r), ctypes.byref(t), float(min_duration), _stream_handle(dev),
+                                     _ptr(keep)))
+    return keep
+
+
+def _table_struct(table):
     t = TrajTable()
     t.n = table["n"]
     for f in ("label", "n_points", "t_min", "t_max", "n_ends"):
         setattr(t, f, _ptr(table[f]).value)
-    _check(lib().ftk_cp_filter_loops(ctypes.byref(r), ctypes.byref(t), float(min_duration), _stream_handle(dev),
-                                     _ptr(keep)))
-    return keep
+    return t
+
+
+def trajectory_order(res, dims_with_t, table):
+    """(order, offsets): hit indices grouped by trajectory (table order), each in curve order; offsets[j] is the
+    start of trajectory j in order, offsets[-1] = n_hits."""
+    import torch
+    dev = _device_of(res)
+    pool = _TorchPool(dev)
+    o = _options(pool)
+    r = _as_result(res)
+    arr = _dims_arg(res, dims_with_t)
+    t = _table_struct(table)
+    order = torch.empty(max(res["n_hits"], 1), dtype=torch.int64, device=dev)
+    offsets = torch.empty(table["n"] + 1, dtype=torch.int64, device=dev)
+    _check(lib().ftk_traj_order(ctypes.byref(r), res["n"], arr, ctypes.byref(t), ctypes.byref(o),
+                                _stream_handle(dev), _ptr(order), _ptr(offsets)))
+    return order[:res["n_hits"]], offsets
+
+
+def _walk_types(fn, res, table, order, offsets, arg, types):
+    import torch
+    dev = _device_of(res)
+    pool = _TorchPool(dev)
+    o = _options(pool)
+    r = _as_result(res)
+    t = _table_struct(table)
+    tin = res["type"] if types is None else types
+    if tin is None:
+        raise ValueError("the result carries no types; pass types")
+    if tin.dtype != torch.uint8 or tin.numel() != res["n_hits"] or not tin.is_contiguous():
+        raise ValueError("types must be a contiguous uint8 tensor of n_hits entries")
+    tout = torch.empty(max(res["n_hits"], 1), dtype=torch.uint8, device=dev)
+    _check(fn(ctypes.byref(r), ctypes.byref(t), _ptr(order), _ptr(offsets), _ptr(tin), arg, ctypes.byref(o),
+              _stream_handle(dev), _ptr(tout)))
+    return tout[:res["n_hits"]]
+
+
+def smooth_types(res, table, order, offsets, half_window=2, types=None):
+    """Window-shifting type smoothing along the trajectories (types default to the result's)."""
+    return _walk_types(lib().ftk_traj_smooth_types, res, table, order, offsets, int(half_window), types)
+
+
+def simplify_types(res, table, order, offsets, min_persistence, types=None):
+    """Run simplification: short runs of one type between two persistent runs of another take their type."""
+    return _walk_types(lib().ftk_traj_simplify_types, res, table, order, offsets, float(min_persistence), types)
 
 
 def autotune_cp2d(field, kind=SCALAR):

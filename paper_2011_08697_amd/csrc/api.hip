@@ -1,6 +1,7 @@
 // api.hip -- the C ABI (include/ftk.h): argument checks, device memory, launch sequence, status decoding.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1350,6 +1351,137 @@ ftk_status ftk_cp_filter_loops(const ftk_cp_result* r, const ftk_traj_table* tt,
                                    (const int*)tt->t_min, (const int*)tt->t_max, tt->n_ends, min_duration, keep,
                                    (hipStream_t)stream));
   return FTK_OK;
+}
+
+ftk_status ftk_traj_order(const ftk_cp_result* r, int32_t n, const int64_t* dims_with_t, const ftk_traj_table* tt,
+                          const ftk_options* opt, ftk_stream_t stream, int64_t* order, int64_t* offsets) {
+  g_err.clear();
+  ftk_status st = check_post_args(r, n, dims_with_t);
+  if (st) return st;
+  if (!tt || !offsets) return fail(FTK_ERR_ARG, "table and offsets must be given");
+  if (tt->n != r->n_trajectories || (tt->n > 0 && (!tt->label || !tt->n_points || !tt->n_ends)))
+    return fail(FTK_ERR_ARG, "the trajectory table does not belong to this result");
+  const long long nh = r->n_hits, ntr = r->n_trajectories;
+  if (nh > 0 && (!order || !r->label)) return fail(FTK_ERR_ARG, "order and the result's label array must be given");
+  if (nh > INT_MAX) return fail(FTK_ERR_CAPACITY, "ordering supports up to 2^31 - 1 points");
+  ftk_options o;
+  resolve(opt, &o);
+  if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
+  hipStream_t s = (hipStream_t)stream;
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
+  const size_t nz = (size_t)(nh > 0 ? nh : 1);
+  long long* nb0 = sc.get<long long>(nz);
+  long long* nb1 = sc.get<long long>(nz);
+  long long* ws = sc.get<long long>(12 * nz);
+  unsigned char* dws = sc.get<unsigned char>(4 * nz);
+  int* cnt = sc.get<int>((size_t)(ntr > 0 ? ntr : 1));
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(ntr));
+  Ctl* dctl = sc.get<Ctl>(1);
+  if (!nb0 || !nb1 || !ws || !dws || !cnt || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+  HIP_TRY(ftk::launch_order_setup(n, dims_with_t, (const long long*)r->face_id, (const long long*)r->label, nh,
+                                  (const long long*)tt->label, (const unsigned long long*)tt->n_points, tt->n_ends,
+                                  ntr, nb0, nb1, ws, dws, cnt, (long long*)offsets, tmp, &dctl->status, s));
+  Ctl h;
+  int buf = 0;
+  if (nh > 0) {
+    // every round doubles the reach of each open arm; a path of at most n_hits points closes within
+    // ceil(log2(n_hits)) + 1 rounds, and an arm that walks past n_hits steps is closed as an invariant error
+    bool closed = false;
+    for (int round = 0; round < 64 && !closed; ++round) {
+      HIP_TRY(hipMemsetAsync(&dctl->cnt[0], 0, sizeof(unsigned long long), s));
+      HIP_TRY(ftk::launch_order_jump(nb0, nb1, nh, ws, dws, buf, (unsigned long long*)&dctl->cnt[0],
+                                     &dctl->status, s));
+      buf = 1 - buf;
+      st = read_ctl(&h, dctl, s);
+      if (st) return st;
+      if (h.status) return decode_status(h.status);
+      closed = h.cnt[0] == 0;
+    }
+    if (!closed) return fail(FTK_ERR_INVARIANT, "trajectory walk did not close (internal error)");
+    HIP_TRY(ftk::launch_order_place((const long long*)r->label, nh, (const long long*)tt->label, ntr,
+                                    (const long long*)offsets, ws, dws, buf, (long long*)order, &dctl->status, s));
+  }
+  st = read_ctl(&h, dctl, s);
+  if (st) return st;
+  return decode_status(h.status);
+}
+
+namespace {
+
+ftk_status check_walk_args(const ftk_cp_result* r, const ftk_traj_table* tt, const int64_t* order,
+                           const int64_t* offsets, const uint8_t* type_in, const uint8_t* type_out) {
+  if (!r || !tt) return fail(FTK_ERR_ARG, "result and table must be given");
+  if (r->n != 2 && r->n != 3) return fail(FTK_ERR_ARG, "the result holds no 2D or 3D faces");
+  if (tt->n != r->n_trajectories || (tt->n > 0 && !tt->n_ends))
+    return fail(FTK_ERR_ARG, "the trajectory table does not belong to this result");
+  if (r->n_hits == 0) return FTK_OK;
+  if (!order || !offsets || !type_in || !type_out) return fail(FTK_ERR_ARG, "order, offsets and types must be given");
+  const uint8_t* a = type_in;
+  const uint8_t* b = type_out;
+  if (a < b + r->n_hits && b < a + r->n_hits) return fail(FTK_ERR_ARG, "type_out must not overlap type_in");
+  return FTK_OK;
+}
+
+}  // namespace
+
+ftk_status ftk_traj_smooth_types(const ftk_cp_result* r, const ftk_traj_table* tt, const int64_t* order,
+                                 const int64_t* offsets, const uint8_t* type_in, int32_t half_window,
+                                 const ftk_options* opt, ftk_stream_t stream, uint8_t* type_out) {
+  g_err.clear();
+  ftk_status st = check_walk_args(r, tt, order, offsets, type_in, type_out);
+  if (st || r->n_hits == 0) return st;
+  if (half_window < 0) return fail(FTK_ERR_ARG, "half_window must be >= 0");
+  ftk_options o;
+  resolve(opt, &o);
+  if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
+  hipStream_t s = (hipStream_t)stream;
+  Scratch sc(make_alloc(o, s));
+  Ctl* dctl = sc.get<Ctl>(1);
+  if (!dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+  HIP_TRY(ftk::launch_smooth((const long long*)order, (const long long*)offsets, tt->n_ends, tt->n, r->n_hits, type_in,
+                             half_window, type_out, &dctl->status, s));
+  Ctl h;
+  st = read_ctl(&h, dctl, s);
+  if (st) return st;
+  return decode_status(h.status);
+}
+
+ftk_status ftk_traj_simplify_types(const ftk_cp_result* r, const ftk_traj_table* tt, const int64_t* order,
+                                   const int64_t* offsets, const uint8_t* type_in, float min_persistence,
+                                   const ftk_options* opt, ftk_stream_t stream, uint8_t* type_out) {
+  g_err.clear();
+  ftk_status st = check_walk_args(r, tt, order, offsets, type_in, type_out);
+  if (st || r->n_hits == 0) return st;
+  if (!r->pos) return fail(FTK_ERR_ARG, "simplification needs the result's pos array");
+  if (!(min_persistence == min_persistence)) return fail(FTK_ERR_ARG, "min_persistence is NaN");
+  ftk_options o;
+  resolve(opt, &o);
+  if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
+  hipStream_t s = (hipStream_t)stream;
+  Scratch sc(make_alloc(o, s));
+  const long long nh = r->n_hits;
+  long long* rot = sc.get<long long>((size_t)(tt->n > 0 ? tt->n : 1));
+  int* flag = sc.get<int>((size_t)nh);
+  long long* run_off = sc.get<long long>((size_t)nh);
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(nh));
+  int* tmin = sc.get<int>((size_t)nh);
+  int* tmax = sc.get<int>((size_t)nh);
+  uint8_t* run_type = sc.get<uint8_t>((size_t)nh);
+  uint8_t* new_type = sc.get<uint8_t>((size_t)nh);
+  Ctl* dctl = sc.get<Ctl>(1);
+  if (!rot || !flag || !run_off || !tmp || !tmin || !tmax || !run_type || !new_type || !dctl)
+    return fail(FTK_ERR_OOM, "scratch allocation failed");
+  HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+  HIP_TRY(ftk::launch_simplify(r->n, r->pos, (const long long*)order, (const long long*)offsets, tt->n_ends, tt->n, nh,
+                               type_in, min_persistence, rot, flag, run_off, &dctl->total, tmp, tmin, tmax, run_type,
+                               new_type, type_out, &dctl->status, s));
+  Ctl h;
+  st = read_ctl(&h, dctl, s);
+  if (st) return st;
+  return decode_status(h.status);
 }
 
 void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream) {

@@ -105,6 +105,30 @@ hipError_t launch_filter_loops(const long long* label, long long n_hits, const l
                                const int* t_min, const int* t_max, const int* n_ends, float min_duration,
                                uint8_t* keep, hipStream_t s);
 
+// Order of the points along each trajectory: neighbours, loop cuts and arm init (buffer 0), per-trajectory offsets
+// (offsets[n_traj] = n_hits); one pointer-jumping round from buffer `from` into 1 - from (active counts the arms
+// still open); placement from buffer `buf`.  ws holds 12 * n_hits int64 values, dws 4 * n_hits bytes.
+hipError_t launch_order_setup(int n, const int64_t* dims_with_t, const long long* face_id, const long long* label,
+                              long long n_hits, const long long* roots, const unsigned long long* n_points,
+                              const int* n_ends, long long n_traj, long long* nb0, long long* nb1, long long* ws,
+                              unsigned char* dws, int* cnt, long long* offsets, long long* scan_tmp,
+                              unsigned* status, hipStream_t s);
+hipError_t launch_order_jump(const long long* nb0, const long long* nb1, long long n_hits, long long* ws,
+                             unsigned char* dws, int from, unsigned long long* active, unsigned* status,
+                             hipStream_t s);
+hipError_t launch_order_place(const long long* label, long long n_hits, const long long* roots, long long n_traj,
+                              const long long* offsets, long long* ws, unsigned char* dws, int buf,
+                              long long* order, unsigned* status, hipStream_t s);
+// Type smoothing and run simplification along an order.
+hipError_t launch_smooth(const long long* order, const long long* offsets, const int* n_ends, long long n_traj,
+                         long long n_hits, const uint8_t* type_in, int half, uint8_t* type_out, unsigned* status,
+                         hipStream_t s);
+hipError_t launch_simplify(int n, const float* pos, const long long* order, const long long* offsets,
+                           const int* n_ends, long long n_traj, long long n_hits, const uint8_t* type_in, float theta,
+                           long long* rot, int* flag, long long* run_off, long long* total, long long* scan_tmp,
+                           int* t_min, int* t_max, uint8_t* run_type, uint8_t* new_type, uint8_t* type_out,
+                           unsigned* status, hipStream_t s);
+
 // Union-find passes over n hits: extra unions from the work list, then labels = face_id of the root.
 hipError_t launch_uf_hook(unsigned* parent, const uint2* work, const unsigned long long* work_count,
                           long long max_work, hipStream_t s);

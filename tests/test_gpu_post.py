@@ -98,3 +98,80 @@ def test_empty_result_and_argument_errors():
         F.slice_at(g, (10, 9, 4), 4)  # t0 outside [0, nt)
     with pytest.raises(ValueError):
         F.trajectory_table(g, (10, 9))  # wrong dimension count
+
+
+def _stable_theta(order, offsets, is_loop, types, t, base):
+    """A persistence threshold near base whose oracle decisions do not change within +-1e-4 (so FP32 run extents
+    on the device cannot fall on the other side of it)."""
+    for k in range(50):
+        th = base * (1.0 + 0.0137 * k)
+        outs = [P.simplify_types(order, offsets, is_loop, types, t, x) for x in (th - 1e-4, th, th + 1e-4)]
+        if np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2]):
+            return th, outs[1]
+    raise AssertionError("no stable threshold near %g" % base)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_order_smoothing_and_simplification_match_oracle(case):
+    f, n, kind = CASES[case]()
+    dims = _dims(f, n, kind)
+    g = _track(f, n, kind)
+    tr = O.track(f, n=n, kind=kind)
+    tab_o = P.traj_table(tr, n, dims)
+    tab_g = F.trajectory_table(g, dims)
+    order_o, off_o = P.traj_order(tr, n, dims, tab_o)
+    order_g, off_g = F.trajectory_order(g, dims, tab_g)
+    assert np.array_equal(off_g.cpu().numpy(), off_o)
+    assert np.array_equal(order_g.cpu().numpy(), order_o)
+    loop = tab_o["n_ends"] == 0
+    t = tr.pos[:, n]
+    rng = np.random.default_rng(17)
+    planted = rng.integers(1, 3, size=tr.n_hits).astype(np.uint8)  # two types at random: many runs and changes
+    for types in (tr.type, planted):
+        tg = torch.from_numpy(types).to(DEV)
+        for w in (1, 2, 3):
+            want = P.smooth_types(order_o, off_o, loop, types, w)
+            got = F.smooth_types(g, tab_g, order_g, off_g, w, types=tg).cpu().numpy()
+            assert np.array_equal(got, want), w
+        for base in (0.3, 1.0, 2.5):
+            th, want = _stable_theta(order_o, off_o, loop, types, t, base)
+            got = F.simplify_types(g, tab_g, order_g, off_g, th, types=tg).cpu().numpy()
+            assert np.array_equal(got, want), th
+
+
+def test_birth_death_loop_order_and_simplification():
+    """The loop is walked from its label face; a persistence threshold above the whole loop's extent leaves both
+    branches (neither run has a persistent neighbour), one below the shorter branch changes nothing either."""
+    nx, ny, nt = 33, 17, 21
+    X = np.arange(nx, dtype=np.float64) - 16.0
+    Y = np.arange(ny, dtype=np.float64) - 8.0
+    f = np.zeros((nt, ny, nx))
+    for t in range(nt):
+        f[t] = (X[None, :] ** 3) / 3.0 - (30.0 - 0.5 * (t - 10.0) ** 2) * X[None, :] + (Y[:, None] ** 2)
+    f = f.astype(np.float32)
+    dims = (nx, ny, nt)
+    g = _track(f, 2)
+    tab = F.trajectory_table(g, dims)
+    order, off = F.trajectory_order(g, dims, tab)
+    o = order.cpu().numpy()
+    assert off.cpu().numpy().tolist() == [0, g["n_hits"]]
+    assert int(g["face_id"][o[0]]) == int(tab["label"][0])
+    assert int(g["face_id"][o[1]]) < int(g["face_id"][o[-1]])
+    assert np.array_equal(F.simplify_types(g, tab, order, off, 100.0).cpu().numpy(), g["type"].cpu().numpy())
+
+
+def test_order_and_walk_errors():
+    f = np.zeros((4, 9, 10), np.float32)
+    g = _track(f, 2)
+    tab = F.trajectory_table(g, (10, 9, 4))
+    order, off = F.trajectory_order(g, (10, 9, 4), tab)
+    assert order.numel() == 0 and off.cpu().numpy().tolist() == [0]
+    f = synth.make("blobs64")
+    g = _track(f, 2)
+    dims = (f.shape[-1], f.shape[-2], f.shape[0])
+    tab = F.trajectory_table(g, dims)
+    order, off = F.trajectory_order(g, dims, tab)
+    with pytest.raises(F.FtkError):
+        F.smooth_types(g, tab, order, off, -1)
+    with pytest.raises(ValueError):
+        F.smooth_types(g, tab, order, off, 2, types=g["type"][:-1].contiguous())
