@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="noise1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-post", action="store_true", help="skip the trajectory post-processing timings")
     ap.add_argument("--cpu-steps", type=int, default=0, help="time steps of the oracle sample (0: automatic)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration) and exit")
@@ -163,6 +164,35 @@ def precision_report(F, field_np, field, kind, n, sample=20000):
             "degenerate_frac": float(np.mean((flg & 1) != 0))}
 
 
+def post_report(F, field, n, kind, dims, reps=2):
+    """Wall time of each trajectory post-processing call on this workload's result (after the timed region; not part
+    of value): table, slice at the middle step, loop filter, order, smoothing (half window 2), simplification."""
+    import torch
+    res = F.track_cp2d(field, kind=kind) if n == 2 else F.track_cp3d(field)
+    torch.cuda.synchronize()
+    ms = {}
+    for _ in range(reps):  # the first pass also grows torch's cache; keep the last
+        def timed(name, fn):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ms[name] = round((time.perf_counter() - t0) * 1e3, 3)
+            return out
+        tab = timed("table", lambda: F.trajectory_table(res, dims))
+        timed("slice", lambda: F.slice_at(res, dims, dims[-1] // 2))
+        timed("filter_loops", lambda: F.filter_loops(res, tab, 1.0))
+        order, off = timed("order", lambda: F.trajectory_order(res, dims, tab))
+        sm = timed("smooth", lambda: F.smooth_types(res, tab, order, off, 2))
+        si = timed("simplify", lambda: F.simplify_types(res, tab, order, off, 1.0))
+    nh = res["n_hits"]
+    lengths = (off[1:] - off[:-1]) if tab["n"] else off[:0]
+    return {"ms": ms, "n_hits": nh, "n_trajectories": tab["n"],
+            "longest": int(lengths.max()) if tab["n"] else 0,
+            "order_hits_per_s": round(nh / (ms["order"] * 1e-3), 1) if ms["order"] > 0 else None,
+            "smoothed": int((sm != res["type"]).sum()), "simplified": int((si != res["type"]).sum())}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -271,6 +301,8 @@ def main():
                          f"({tr.simplices_tested} simplices, {tr.n_hits} hits, full detect + sublocate + stitch, "
                          f"{cpu_s:.1f} s)"}
 
+    post = None if args.no_post else post_report(F, field, n, kind, dims)
+
     precision = None
     if wl == "vortex4096":
         precision = precision_report(F, field_np, field, kind, n)
@@ -287,6 +319,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if post is not None:
+        line["post"] = post
     if precision is not None:
         line["precision"] = precision
     print(json.dumps(line), flush=True)
