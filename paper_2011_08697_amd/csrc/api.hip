@@ -1238,15 +1238,16 @@ ftk_status ftk_traj_table_build(const ftk_cp_result* r, int32_t n, const int64_t
   int* flag = sc.get<int>((size_t)nh);
   long long* off = sc.get<long long>((size_t)nh);
   long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(nh));
+  long long* rb = sc.get<long long>((size_t)ftk::row_buckets(n, dims_with_t) + 1);
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!t.label || !t.n_points || !t.t_min || !t.t_max || !t.n_ends || !flag || !off || !tmp || !dctl) {
+  if (!t.label || !t.n_points || !t.t_min || !t.t_max || !t.n_ends || !flag || !off || !tmp || !rb || !dctl) {
     ftk_traj_table_free(&t, opt, stream);
     return fail(FTK_ERR_OOM, "trajectory table allocation failed");
   }
   hipError_t he = hipMemsetAsync(dctl, 0, sizeof(Ctl), s);
   if (he == hipSuccess)
     he = ftk::launch_traj_table(n, dims_with_t, (const long long*)r->face_id, (const long long*)r->label, r->pos, nh,
-                                ntr, flag, off, &dctl->total, tmp, (long long*)t.label,
+                                ntr, flag, off, &dctl->total, tmp, (long long*)t.label, rb,
                                 (unsigned long long*)t.n_points, (int*)t.t_min, (int*)t.t_max, t.n_ends,
                                 &dctl->status, s);
   Ctl h;
@@ -1368,40 +1369,67 @@ ftk_status ftk_traj_order(const ftk_cp_result* r, int32_t n, const int64_t* dims
   resolve(opt, &o);
   if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
   hipStream_t s = (hipStream_t)stream;
-  const Alloc al = make_alloc(o, s);
-  Scratch sc(al);
+  Scratch sc(make_alloc(o, s));
   const size_t nz = (size_t)(nh > 0 ? nh : 1);
-  long long* nb0 = sc.get<long long>(nz);
-  long long* nb1 = sc.get<long long>(nz);
-  long long* ws = sc.get<long long>(12 * nz);
-  unsigned char* dws = sc.get<unsigned char>(4 * nz);
+  int* nb = sc.get<int>(2 * nz);
+  unsigned* seg = sc.get<unsigned>(4 * nz);
+  unsigned char* is_ruler = sc.get<unsigned char>(nz);
+  int* rid = sc.get<int>(nz);
+  int* list = sc.get<int>(nz);
+  int* flag = sc.get<int>(nz);
+  long long* off = sc.get<long long>(nz);
+  long long hB;
+  long long* bstart = sc.get<long long>((size_t)ftk::hit_buckets(n, dims_with_t, nh, &hB) + 1);
+  long long* rb = sc.get<long long>((size_t)ftk::row_buckets(n, dims_with_t) + 1);
   int* cnt = sc.get<int>((size_t)(ntr > 0 ? ntr : 1));
-  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(ntr));
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(nh > ntr ? nh : ntr));
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!nb0 || !nb1 || !ws || !dws || !cnt || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  if (!nb || !seg || !is_ruler || !rid || !list || !flag || !off || !bstart || !rb || !cnt || !tmp || !dctl)
+    return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   HIP_TRY(ftk::launch_order_setup(n, dims_with_t, (const long long*)r->face_id, (const long long*)r->label, nh,
                                   (const long long*)tt->label, (const unsigned long long*)tt->n_points, tt->n_ends,
-                                  ntr, nb0, nb1, ws, dws, cnt, (long long*)offsets, tmp, &dctl->status, s));
+                                  ntr, nb, seg, is_ruler, rid, list, bstart, rb, flag, off, &dctl->total, cnt,
+                                  (long long*)offsets, tmp, &dctl->status, s));
   Ctl h;
-  int buf = 0;
+  st = read_ctl(&h, dctl, s);
+  if (st) return st;
+  if (h.status) return decode_status(h.status);
   if (nh > 0) {
-    // every round doubles the reach of each open arm; a path of at most n_hits points closes within
-    // ceil(log2(n_hits)) + 1 rounds, and an arm that walks past n_hits steps is closed as an invariant error
-    bool closed = false;
-    for (int round = 0; round < 64 && !closed; ++round) {
+    const long long nr = h.total;
+    const size_t nrz = (size_t)(nr > 0 ? nr : 1);
+    int* st0 = sc.get<int>(8 * nrz);
+    int* st1 = sc.get<int>(8 * nrz);
+    int* act0 = sc.get<int>(nrz);
+    int* act1 = sc.get<int>(nrz);
+    if (!st0 || !st1 || !act0 || !act1) return fail(FTK_ERR_OOM, "scratch allocation failed");
+    HIP_TRY(ftk::launch_order_walk(nb, is_ruler, list, nr, nh, seg, st0, &dctl->status, s));
+    // pointer jumping over the rulers: the reach of every open arm doubles per round, so a path of L rulers closes
+    // within ceil(log2 L) + 2 rounds (one more to copy the final states); an arm that walks past n_hits steps is
+    // closed as an invariant error
+    int* in = st0;
+    int* out = st1;
+    const int* act = nullptr;
+    long long n_act = nr;
+    int* lists[2] = {act0, act1};
+    for (int round = 0; n_act > 0; ++round) {
+      if (round >= 64) return fail(FTK_ERR_INVARIANT, "trajectory walk did not close (internal error)");
       HIP_TRY(hipMemsetAsync(&dctl->cnt[0], 0, sizeof(unsigned long long), s));
-      HIP_TRY(ftk::launch_order_jump(nb0, nb1, nh, ws, dws, buf, (unsigned long long*)&dctl->cnt[0],
+      int* next = lists[round & 1];
+      HIP_TRY(ftk::launch_order_jump(nb, rid, act, n_act, nh, in, out, next, (unsigned long long*)&dctl->cnt[0],
                                      &dctl->status, s));
-      buf = 1 - buf;
       st = read_ctl(&h, dctl, s);
       if (st) return st;
       if (h.status) return decode_status(h.status);
-      closed = h.cnt[0] == 0;
+      n_act = (long long)h.cnt[0];
+      act = next;
+      int* x = in;
+      in = out;
+      out = x;
     }
-    if (!closed) return fail(FTK_ERR_INVARIANT, "trajectory walk did not close (internal error)");
-    HIP_TRY(ftk::launch_order_place((const long long*)r->label, nh, (const long long*)tt->label, ntr,
-                                    (const long long*)offsets, ws, dws, buf, (long long*)order, &dctl->status, s));
+    HIP_TRY(ftk::launch_order_place(n, dims_with_t, (const long long*)r->label, nh, (const long long*)tt->label, rb,
+                                    (const long long*)offsets, is_ruler, rid, seg, in, (long long*)order,
+                                    &dctl->status, s));
   }
   st = read_ctl(&h, dctl, s);
   if (st) return st;
@@ -1438,11 +1466,15 @@ ftk_status ftk_traj_smooth_types(const ftk_cp_result* r, const ftk_traj_table* t
   if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
   hipStream_t s = (hipStream_t)stream;
   Scratch sc(make_alloc(o, s));
+  const long long nh = r->n_hits;
+  int* head = sc.get<int>((size_t)nh);
+  long long* heads = sc.get<long long>((size_t)nh);
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(nh));
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  if (!head || !heads || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
-  HIP_TRY(ftk::launch_smooth((const long long*)order, (const long long*)offsets, tt->n_ends, tt->n, r->n_hits, type_in,
-                             half_window, type_out, &dctl->status, s));
+  HIP_TRY(ftk::launch_smooth((const long long*)order, (const long long*)offsets, tt->n_ends, tt->n, nh, type_in,
+                             half_window, head, heads, &dctl->total, tmp, type_out, &dctl->status, s));
   Ctl h;
   st = read_ctl(&h, dctl, s);
   if (st) return st;
@@ -1471,13 +1503,15 @@ ftk_status ftk_traj_simplify_types(const ftk_cp_result* r, const ftk_traj_table*
   int* tmax = sc.get<int>((size_t)nh);
   uint8_t* run_type = sc.get<uint8_t>((size_t)nh);
   uint8_t* new_type = sc.get<uint8_t>((size_t)nh);
+  int* head = sc.get<int>((size_t)nh);
+  long long* heads = sc.get<long long>((size_t)nh);
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!rot || !flag || !run_off || !tmp || !tmin || !tmax || !run_type || !new_type || !dctl)
+  if (!rot || !flag || !run_off || !tmp || !tmin || !tmax || !run_type || !new_type || !head || !heads || !dctl)
     return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   HIP_TRY(ftk::launch_simplify(r->n, r->pos, (const long long*)order, (const long long*)offsets, tt->n_ends, tt->n, nh,
-                               type_in, min_persistence, rot, flag, run_off, &dctl->total, tmp, tmin, tmax, run_type,
-                               new_type, type_out, &dctl->status, s));
+                               type_in, min_persistence, rot, flag, run_off, head, heads, &dctl->total, tmp, tmin,
+                               tmax, run_type, new_type, type_out, &dctl->status, s));
   Ctl h;
   st = read_ctl(&h, dctl, s);
   if (st) return st;

@@ -93,7 +93,7 @@ hipError_t launch_scan(const int* in, long long* out, long long n, long long* to
 // Trajectory post-processing (post.hip).
 hipError_t launch_traj_table(int n, const int64_t* dims_with_t, const long long* face_id, const long long* label,
                              const float* pos, long long n_hits, long long n_traj, int* flag, long long* off,
-                             long long* scan_total, long long* scan_tmp, long long* roots,
+                             long long* scan_total, long long* scan_tmp, long long* roots, long long* rb,
                              unsigned long long* hits, int* t_min, int* t_max, int* n_ends, unsigned* status,
                              hipStream_t s);
 hipError_t launch_slice_range(int n, const int64_t* dims_with_t, const long long* face_id, long long n_hits,
@@ -105,29 +105,41 @@ hipError_t launch_filter_loops(const long long* label, long long n_hits, const l
                                const int* t_min, const int* t_max, const int* n_ends, float min_duration,
                                uint8_t* keep, hipStream_t s);
 
-// Order of the points along each trajectory: neighbours, loop cuts and arm init (buffer 0), per-trajectory offsets
-// (offsets[n_traj] = n_hits); one pointer-jumping round from buffer `from` into 1 - from (active counts the arms
-// still open); placement from buffer `buf`.  ws holds 12 * n_hits int64 values, dws 4 * n_hits bytes.
+// Order of the points along each trajectory.  setup: per-trajectory offsets (offsets[n_traj] = n_hits), cell
+// neighbours nb ([n_hits][2] int32), loop cuts, rulers (is_ruler, rid = slot in list, *n_rulers = count); seg
+// ([n_hits][2] x 2 uint32) is cleared.  walk: ruler-to-ruler walks filling seg, ruler states st ([n_rulers][2] x 4
+// int32).  jump: one pointer-jumping round over the listed rulers (act = null: all), still-open ones appended to
+// next.  place: order[] from the rulers' final states.
 hipError_t launch_order_setup(int n, const int64_t* dims_with_t, const long long* face_id, const long long* label,
                               long long n_hits, const long long* roots, const unsigned long long* n_points,
-                              const int* n_ends, long long n_traj, long long* nb0, long long* nb1, long long* ws,
-                              unsigned char* dws, int* cnt, long long* offsets, long long* scan_tmp,
-                              unsigned* status, hipStream_t s);
-hipError_t launch_order_jump(const long long* nb0, const long long* nb1, long long n_hits, long long* ws,
-                             unsigned char* dws, int from, unsigned long long* active, unsigned* status,
+                              const int* n_ends, long long n_traj, int* nb, unsigned* seg, unsigned char* is_ruler,
+                              int* rid, int* list, long long* bstart, long long* rb, int* flag, long long* off,
+                              long long* n_rulers, int* cnt, long long* offsets, long long* scan_tmp, unsigned* status,
+                              hipStream_t s);
+// Number of vertex rows of the grid: the sorted hit and label lookups of the post-processing bucket their face ids
+// by row, so their bucket tables (bstart, rb) need row_buckets() + 1 entries.
+long long row_buckets(int n, const int64_t* dims_with_t);
+// Buckets of the hit lookup of the ordering: one per vertex when the hits are dense (at least one per 16 vertices),
+// else one per row; *B = face ids per bucket.  bstart needs the returned count + 1 entries.
+long long hit_buckets(int n, const int64_t* dims_with_t, long long n_hits, long long* B);
+hipError_t launch_order_walk(const int* nb, const unsigned char* is_ruler, const int* list, long long n_rulers,
+                             long long n_hits, unsigned* seg, int* st, unsigned* status, hipStream_t s);
+hipError_t launch_order_jump(const int* nb, const int* rid, const int* act, long long n_act, long long n_hits,
+                             const int* in, int* out, int* next, unsigned long long* next_n, unsigned* status,
                              hipStream_t s);
-hipError_t launch_order_place(const long long* label, long long n_hits, const long long* roots, long long n_traj,
-                              const long long* offsets, long long* ws, unsigned char* dws, int buf,
+hipError_t launch_order_place(int n, const int64_t* dims_with_t, const long long* label, long long n_hits,
+                              const long long* roots, const long long* rb, const long long* offsets,
+                              const unsigned char* is_ruler, const int* rid, const unsigned* seg, const int* st,
                               long long* order, unsigned* status, hipStream_t s);
-// Type smoothing and run simplification along an order.
+// Type smoothing and run simplification along an order (head/heads: [n_hits] int / int64 scratch).
 hipError_t launch_smooth(const long long* order, const long long* offsets, const int* n_ends, long long n_traj,
-                         long long n_hits, const uint8_t* type_in, int half, uint8_t* type_out, unsigned* status,
-                         hipStream_t s);
+                         long long n_hits, const uint8_t* type_in, int half, int* head, long long* heads,
+                         long long* total, long long* scan_tmp, uint8_t* type_out, unsigned* status, hipStream_t s);
 hipError_t launch_simplify(int n, const float* pos, const long long* order, const long long* offsets,
                            const int* n_ends, long long n_traj, long long n_hits, const uint8_t* type_in, float theta,
-                           long long* rot, int* flag, long long* run_off, long long* total, long long* scan_tmp,
-                           int* t_min, int* t_max, uint8_t* run_type, uint8_t* new_type, uint8_t* type_out,
-                           unsigned* status, hipStream_t s);
+                           long long* rot, int* flag, long long* run_off, int* head, long long* heads,
+                           long long* total, long long* scan_tmp, int* t_min, int* t_max, uint8_t* run_type,
+                           uint8_t* new_type, uint8_t* type_out, unsigned* status, hipStream_t s);
 
 // Union-find passes over n hits: extra unions from the work list, then labels = face_id of the root.
 hipError_t launch_uf_hook(unsigned* parent, const uint2* work, const unsigned long long* work_count,

@@ -100,15 +100,16 @@ def test_empty_result_and_argument_errors():
         F.trajectory_table(g, (10, 9))  # wrong dimension count
 
 
-def _stable_theta(order, offsets, is_loop, types, t, base):
-    """A persistence threshold near base whose oracle decisions do not change within +-1e-4 (so FP32 run extents
-    on the device cannot fall on the other side of it)."""
-    for k in range(50):
-        th = base * (1.0 + 0.0137 * k)
-        outs = [P.simplify_types(order, offsets, is_loop, types, t, x) for x in (th - 1e-4, th, th + 1e-4)]
-        if np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2]):
-            return th, outs[1]
-    raise AssertionError("no stable threshold near %g" % base)
+def _check_simplified(got, order, offsets, is_loop, types, t, theta, delta=1e-3):
+    """Device runs have FP32 time extents, the oracle's binary64 ones (positions agree to 1e-5 relative, so extents
+    to about 2.4e-4 at t <= 12).  Where the oracle's decision is the same at theta - delta, theta and theta + delta
+    the device must agree with it; where a run extent lies within delta of the threshold either side is accepted."""
+    outs = [P.simplify_types(order, offsets, is_loop, types, t, x) for x in (theta - delta, theta, theta + delta)]
+    ok = (got == outs[0]) | (got == outs[1]) | (got == outs[2])
+    assert np.all(ok), int((~ok).sum())
+    firm = (outs[0] == outs[1]) & (outs[1] == outs[2])
+    assert np.array_equal(got[firm], outs[1][firm])
+    assert firm.mean() > 0.95  # the comparison still covers nearly every point
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -133,10 +134,9 @@ def test_order_smoothing_and_simplification_match_oracle(case):
             want = P.smooth_types(order_o, off_o, loop, types, w)
             got = F.smooth_types(g, tab_g, order_g, off_g, w, types=tg).cpu().numpy()
             assert np.array_equal(got, want), w
-        for base in (0.3, 1.0, 2.5):
-            th, want = _stable_theta(order_o, off_o, loop, types, t, base)
+        for th in (0.3, 1.0, 2.5):
             got = F.simplify_types(g, tab_g, order_g, off_g, th, types=tg).cpu().numpy()
-            assert np.array_equal(got, want), th
+            _check_simplified(got, order_o, off_o, loop, types, t, th)
 
 
 def test_birth_death_loop_order_and_simplification():
