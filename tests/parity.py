@@ -35,3 +35,35 @@ def assert_full_parity(gpu, orc):
     assert_pos_close(g["pos"], orc.pos)
     if g.get("mu") is not None:
         assert np.all(np.abs(g["mu"] - orc.mu) <= 1e-5)
+
+
+def face_vertices(fid, n, dims):
+    """Vertex coordinates (x, y, [z], t) of a face, decoded from its id (t-major anchor index times the type count
+    plus the type) and the type's axis masks."""
+    from oracle import oracle as O
+    T = 12 if n == 2 else 60
+    masks = O.kuhn_types(n + 1, n)[fid % T]
+    g = fid // T
+    c = []
+    for a in range(n):
+        c.append(g % dims[a])
+        g //= dims[a]
+    c.append(g)
+    vs = [tuple(c)]
+    for m in masks:
+        v = list(vs[-1])
+        for a in range(n + 1):
+            if (int(m) >> a) & 1:
+                v[a] += 1
+        vs.append(tuple(v))
+    return vs
+
+
+def share_a_cell(f1, f2, n, dims):
+    """Two faces are sides of one cell: their vertices together form a unit-step chain across one unit cube."""
+    vs = sorted(set(face_vertices(f1, n, dims)) | set(face_vertices(f2, n, dims)), key=sum)
+    if len(vs) != n + 2:
+        return False
+    steps = [np.subtract(vs[k + 1], vs[k]) for k in range(n + 1)]
+    return all(s.min() == 0 and s.sum() == 1 for s in steps) and np.array_equal(np.subtract(vs[-1], vs[0]),
+                                                                                np.ones(n + 1))

@@ -6,6 +6,7 @@ import pytest
 from oracle import oracle as O
 from oracle import post as P
 from paper_2011_08697_amd import synth
+from parity import share_a_cell
 
 pytestmark = pytest.mark.gpu
 
@@ -175,3 +176,37 @@ def test_order_and_walk_errors():
         F.smooth_types(g, tab, order, off, -1)
     with pytest.raises(ValueError):
         F.smooth_types(g, tab, order, off, 2, types=g["type"][:-1].contiguous())
+
+
+def test_full_size_noise1024_order_properties():
+    """The order on the full 1024^2 x 100 noise result (1.8e8 points): a permutation grouped by trajectory in label
+    order with the table's offsets, one label per group, paths from their smaller-id end and loops from their
+    label face, and consecutive points that are two sides of one cell (sampled, decoded on the host)."""
+    f = synth.make("noise1024")
+    dims = (f.shape[-1], f.shape[-2], f.shape[0])
+    g = _track(f, 2)
+    del f
+    tab = F.trajectory_table(g, dims)
+    order, off = F.trajectory_order(g, dims, tab)
+    nh = g["n_hits"]
+    assert torch.equal(torch.sort(order).values, torch.arange(nh, device=DEV))
+    cnt = tab["n_points"]
+    assert torch.equal(off[1:] - off[:-1], cnt) and int(off[0]) == 0 and int(off[-1]) == nh
+    traj = torch.repeat_interleave(torch.arange(tab["n"], device=DEV), cnt)
+    assert torch.equal(g["label"][order], tab["label"][traj])
+    fid = g["face_id"]
+    first, last = fid[order[off[:-1]]], fid[order[off[1:] - 1]]
+    loop = tab["n_ends"] == 0
+    assert torch.equal(first[loop], tab["label"][loop])
+    assert bool((first[~loop] < last[~loop]).all())
+    rng = np.random.default_rng(5)
+    ks = rng.integers(0, nh - 1, size=3000)
+    same = (traj[ks] == traj[ks + 1]).cpu().numpy()
+    a = fid[order[ks]].cpu().numpy()
+    b = fid[order[ks + 1]].cpu().numpy()
+    checked = 0
+    for x, y, s in zip(a, b, same):
+        if s:
+            assert share_a_cell(int(x), int(y), 2, dims)
+            checked += 1
+    assert checked > 2000

@@ -8,6 +8,7 @@ import pytest
 from oracle import oracle as O
 from oracle import post as P
 from paper_2011_08697_amd import synth
+from parity import share_a_cell
 
 
 def _birth_death_field():
@@ -100,35 +101,6 @@ def test_slice_equals_facewise_test_of_the_step():
 # Order along the trajectories, type smoothing and simplification (Sec. 4.4).
 # ---------------------------------------------------------------------------------------------------------------
 
-def _face_vertices(fid, n, dims):
-    """Vertex coordinates (x, y, [z], t) of a face, decoded here from its id and the face's axis masks."""
-    T = 12 if n == 2 else 60
-    masks = O.kuhn_types(n + 1, n)[fid % T]
-    g = fid // T
-    c = []
-    for a in range(n + 1):
-        c.append(g % dims[a] if a < n else g)
-        g //= dims[a] if a < n else 1
-    vs = [tuple(c)]
-    for m in masks:
-        v = list(vs[-1])
-        for a in range(n + 1):
-            if (int(m) >> a) & 1:
-                v[a] += 1
-        vs.append(tuple(v))
-    return vs
-
-
-def _share_a_cell(f1, f2, n, dims):
-    """Two faces are sides of one cell: their vertices together form a unit-step chain across one unit cube."""
-    vs = sorted(set(_face_vertices(f1, n, dims)) | set(_face_vertices(f2, n, dims)), key=sum)
-    if len(vs) != n + 2:
-        return False
-    steps = [np.subtract(vs[k + 1], vs[k]) for k in range(n + 1)]
-    return all(s.min() == 0 and s.sum() == 1 for s in steps) and np.array_equal(np.subtract(vs[-1], vs[0]),
-                                                                                np.ones(n + 1))
-
-
 def _check_order(tr, n, dims, tab, order, offsets):
     assert np.array_equal(np.sort(order), np.arange(tr.n_hits))
     assert offsets[0] == 0 and offsets[-1] == tr.n_hits and len(offsets) == tab["n"] + 1
@@ -138,7 +110,7 @@ def _check_order(tr, n, dims, tab, order, offsets):
         assert len(seq) == tab["n_points"][j]
         links = list(zip(seq[:-1], seq[1:])) + ([(seq[-1], seq[0])] if tab["n_ends"][j] == 0 else [])
         for a, b in links:
-            assert _share_a_cell(int(tr.face_id[a]), int(tr.face_id[b]), n, dims)
+            assert share_a_cell(int(tr.face_id[a]), int(tr.face_id[b]), n, dims)
             # the curve's piece in a cell is a segment inside that unit cube
             assert np.all(np.abs(tr.pos[a] - tr.pos[b]) <= 1.0 + 1e-12)
         if tab["n_ends"][j] == 0:
