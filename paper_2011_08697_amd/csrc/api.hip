@@ -115,13 +115,15 @@ void cache_put(void* p, size_t size) {
 
 // Scratch list released (to the cache) on scope exit.  Callers synchronise their stream before returning.
 struct Scratch {
-  const Alloc& al;
-  void* p[16];
-  size_t sz[16];
+  static constexpr int kMax = 32;
+  const Alloc& al;  // must outlive the Scratch (declare the Alloc as a named local first)
+  void* p[kMax];
+  size_t sz[kMax];
   int n = 0;
   explicit Scratch(const Alloc& a) : al(a) {}
   template <typename T>
   T* get(size_t count) {
+    if (n >= kMax) return nullptr;  // callers report a failed scratch allocation
     size_t got = 0;
     void* q = cache_get(count * sizeof(T) + 16, &got);
     if (q) {
@@ -1369,7 +1371,8 @@ ftk_status ftk_traj_order(const ftk_cp_result* r, int32_t n, const int64_t* dims
   resolve(opt, &o);
   if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
   hipStream_t s = (hipStream_t)stream;
-  Scratch sc(make_alloc(o, s));
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
   const size_t nz = (size_t)(nh > 0 ? nh : 1);
   int* nb = sc.get<int>(2 * nz);
   unsigned* seg = sc.get<unsigned>(4 * nz);
@@ -1465,7 +1468,8 @@ ftk_status ftk_traj_smooth_types(const ftk_cp_result* r, const ftk_traj_table* t
   resolve(opt, &o);
   if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
   hipStream_t s = (hipStream_t)stream;
-  Scratch sc(make_alloc(o, s));
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
   const long long nh = r->n_hits;
   int* head = sc.get<int>((size_t)nh);
   long long* heads = sc.get<long long>((size_t)nh);
@@ -1493,7 +1497,8 @@ ftk_status ftk_traj_simplify_types(const ftk_cp_result* r, const ftk_traj_table*
   resolve(opt, &o);
   if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
   hipStream_t s = (hipStream_t)stream;
-  Scratch sc(make_alloc(o, s));
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
   const long long nh = r->n_hits;
   long long* rot = sc.get<long long>((size_t)(tt->n > 0 ? tt->n : 1));
   int* flag = sc.get<int>((size_t)nh);
