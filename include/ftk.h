@@ -260,6 +260,36 @@ void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream);
 ftk_status ftk_autotune_cp2d(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,
                              const ftk_options* opt, ftk_stream_t stream, ftk_options* tuned);
 
+/*
+ * Isovolume tracking in a 3D scalar series (Sec. 5.1, two passes on the spacetime mesh; Sec. 5.2 robustness).
+ * field: device pointer, contiguous binary32 [nt][nz][ny][nx]; isovalue c (finite).  An edge anchored at vertex p
+ * (t-major index g) with axis mask M (1..15; x = 1, y = 2, z = 4, t = 8) joins p and p + e(M) and has the id
+ * g * 15 + (M - 1).  It crosses the level set when its two vertices lie on different sides, a value equal to c
+ * counting as above (the symbolic perturbation of a single value is positive).  The crossed edges of every
+ * pentachoron are united into isovolumes; every pentachoron with crossings contributes one tetrahedron (one vertex
+ * on its side) or three (two vertices: the prism of crossed edges split along monotone paths in vertex order).
+ * Outputs are allocated through opt->alloc (or hipMallocAsync on stream); release with ftk_iso_result_free.
+ * Synchronises the stream twice (hit and tetrahedron counts, component count).  Every dimension >= 2; ny and
+ * nz * nt at most 65535.  FTK_ERR_NONFINITE for NaN/Inf in the field; FTK_ERR_CAPACITY beyond 2^32 - 2 crossings.
+ */
+typedef struct {
+  int64_t n_hits;       /* crossed edges */
+  int64_t n_components; /* isovolumes (connected components) */
+  int64_t n_tets;       /* tetrahedra of the tessellation */
+  int64_t* edge_id;     /* [n_hits] ascending */
+  float* pos;           /* [n_hits][4] intersection point (x, y, z, t): p + mu e(M), mu = (c - f(p)) / (f(q) - f(p)) */
+  int64_t* label;       /* [n_hits] smallest edge id of the isovolume */
+  int64_t* tets;        /* [n_tets][4] indices into the hit arrays, by pentachoron (g * 24 + type) */
+} ftk_iso_result;
+
+ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t nz, int64_t nt, float isovalue,
+                           const ftk_options* opt, ftk_stream_t stream, ftk_iso_result* out);
+void ftk_iso_result_free(ftk_iso_result* r, const ftk_options* opt, ftk_stream_t stream);
+
+/* Number of spacetime edges tested for a 3D grid: sum over the 15 axis masks M of prod_a (N_a - [a in M]),
+ * dims_with_t = (nx, ny, nz, nt).  Returns -1 for bad arguments. */
+int64_t ftk_edge_count(const int64_t* dims_with_t);
+
 /* Release the device arrays of a result (with the allocator given in opt, which may be NULL). */
 void ftk_result_free(ftk_cp_result* r, const ftk_options* opt, ftk_stream_t stream);
 

@@ -22,7 +22,8 @@ EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_cr
            "ftk_cp_finish", "ftk_cp_destroy", "ftk_track_cp2d_batched", "ftk_result_free", "ftk_simplex_count",
            "ftk_last_error", "ftk_version", "ftk_traj_table_build", "ftk_traj_table_free", "ftk_cp_slice",
            "ftk_cp_filter_loops", "ftk_buffer_free", "ftk_autotune_cp2d", "ftk_traj_order",
-           "ftk_traj_smooth_types", "ftk_traj_simplify_types"]
+           "ftk_traj_smooth_types", "ftk_traj_simplify_types", "ftk_track_iso3d", "ftk_iso_result_free",
+           "ftk_edge_count"]
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -55,6 +56,12 @@ class Result(ctypes.Structure):
                 ("n_trajectories", ctypes.c_int64), ("face_id", ctypes.c_void_p), ("pos", ctypes.c_void_p),
                 ("mu", ctypes.c_void_p), ("type", ctypes.c_void_p), ("flags", ctypes.c_void_p),
                 ("label", ctypes.c_void_p), ("stats", Stats)]
+
+
+class IsoResult(ctypes.Structure):
+    _fields_ = [("n_hits", ctypes.c_int64), ("n_components", ctypes.c_int64), ("n_tets", ctypes.c_int64),
+                ("edge_id", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("label", ctypes.c_void_p),
+                ("tets", ctypes.c_void_p)]
 
 
 class TrajTable(ctypes.Structure):
@@ -108,6 +115,13 @@ def lib():
         L.ftk_cp_filter_loops.argtypes = [ctypes.POINTER(Result), ctypes.POINTER(TrajTable), ctypes.c_float, vp, vp]
         L.ftk_cp_filter_loops.restype = ctypes.c_int
         L.ftk_buffer_free.argtypes = [vp, ctypes.POINTER(Options), vp]
+        L.ftk_track_iso3d.argtypes = [vp, i64, i64, i64, i64, ctypes.c_float, ctypes.POINTER(Options), vp,
+                                      ctypes.POINTER(IsoResult)]
+        L.ftk_track_iso3d.restype = ctypes.c_int
+        L.ftk_iso_result_free.argtypes = [ctypes.POINTER(IsoResult), ctypes.POINTER(Options), vp]
+        L.ftk_iso_result_free.restype = None
+        L.ftk_edge_count.argtypes = [ctypes.POINTER(i64)]
+        L.ftk_edge_count.restype = i64
         L.ftk_traj_order.argtypes = [ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(i64),
                                      ctypes.POINTER(TrajTable), ctypes.POINTER(Options), vp, vp, vp]
         L.ftk_traj_order.restype = ctypes.c_int
@@ -365,6 +379,33 @@ def filter_loops(res, table, min_duration):
     _check(lib().ftk_cp_filter_loops(ctypes.byref(r), ctypes.byref(t), float(min_duration), _stream_handle(dev),
                                      _ptr(keep)))
     return keep
+
+
+def track_iso3d(field, isovalue):
+    """Isovolume of f = isovalue in a 3D series: field is a contiguous float32 CUDA tensor [nt][nz][ny][nx].
+    Returns crossed edges (edge_id ascending, pos [n][4] as x, y, z, t), labels (smallest edge id of each
+    isovolume), n_components and the tessellation tets [m][4] (indices into the hits)."""
+    import torch
+    if not field.is_contiguous() or field.dtype != torch.float32 or not field.is_cuda or field.dim() != 4:
+        raise ValueError("field must be a contiguous 4D float32 device tensor")
+    nt, nz, ny, nx = field.shape
+    pool = _TorchPool(field.device)
+    o = _options(pool)
+    r = IsoResult()
+    _check(lib().ftk_track_iso3d(ctypes.c_void_p(field.data_ptr()), nx, ny, nz, nt, float(isovalue), ctypes.byref(o),
+                                 _stream_handle(field.device), ctypes.byref(r)))
+    nh, nt4 = int(r.n_hits), int(r.n_tets)
+    return dict(n_hits=nh, n_components=int(r.n_components), n_tets=nt4,
+                edge_id=pool.take(r.edge_id, torch.int64, (max(nh, 1),))[:nh],
+                pos=pool.take(r.pos, torch.float32, (max(nh, 1), 4))[:nh],
+                label=pool.take(r.label, torch.int64, (max(nh, 1),))[:nh],
+                tets=pool.take(r.tets, torch.int64, (max(nt4, 1), 4))[:nt4])
+
+
+def edge_count(dims_with_t):
+    """Spacetime edges tested for a 3D grid (nx, ny, nz, nt)."""
+    arr = (ctypes.c_int64 * 4)(*dims_with_t)
+    return int(lib().ftk_edge_count(arr))
 
 
 def _table_struct(table):

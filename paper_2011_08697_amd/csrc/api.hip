@@ -1523,6 +1523,105 @@ ftk_status ftk_traj_simplify_types(const ftk_cp_result* r, const ftk_traj_table*
   return decode_status(h.status);
 }
 
+int64_t ftk_edge_count(const int64_t* d) {
+  if (!d) return -1;
+  for (int a = 0; a < 4; ++a)
+    if (d[a] < 2) return -1;
+  int64_t tot = 0;
+  for (int M = 1; M < 16; ++M) {
+    int64_t p = 1;
+    for (int a = 0; a < 4; ++a) p *= d[a] - ((M >> a) & 1);
+    tot += p;
+  }
+  return tot;
+}
+
+void ftk_iso_result_free(ftk_iso_result* r, const ftk_options* opt, ftk_stream_t stream) {
+  if (!r) return;
+  ftk_options o;
+  resolve(opt, &o);
+  const Alloc al = make_alloc(o, (hipStream_t)stream);
+  al.put(r->edge_id);
+  al.put(r->pos);
+  al.put(r->label);
+  al.put(r->tets);
+  std::memset(r, 0, sizeof(*r));
+}
+
+ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t nz, int64_t nt, float isovalue,
+                           const ftk_options* opt, ftk_stream_t stream, ftk_iso_result* out) {
+  g_err.clear();
+  if (!out) return fail(FTK_ERR_ARG, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (!field) return fail(FTK_ERR_ARG, "field is NULL");
+  if (nx < 2 || ny < 2 || nz < 2 || nt < 2) return fail(FTK_ERR_ARG, "every dimension must be >= 2");
+  if (nx > (1 << 30) || ny > 65535 || nz * nt > 65535) return fail(FTK_ERR_ARG, "grid too large (ny and nz * nt <= 65535)");
+  if (!std::isfinite(isovalue)) return fail(FTK_ERR_ARG, "isovalue must be finite");
+  ftk_options o;
+  resolve(opt, &o);
+  if ((o.alloc == nullptr) != (o.free == nullptr)) return fail(FTK_ERR_ARG, "alloc and free must be given together");
+  hipStream_t s = (hipStream_t)stream;
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
+  const long long V = nx * ny * nz * nt;
+  unsigned short* emask = sc.get<unsigned short>((size_t)V);
+  int* hcnt = sc.get<int>((size_t)V);
+  int* tcnt = sc.get<int>((size_t)V);
+  long long* hoff = sc.get<long long>((size_t)V);
+  long long* toff = sc.get<long long>((size_t)V);
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(V));
+  Ctl* dctl = sc.get<Ctl>(1);
+  if (!emask || !hcnt || !tcnt || !hoff || !toff || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+  HIP_TRY(ftk::launch_iso_count(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, emask, hcnt, tcnt,
+                                &dctl->status, s));
+  HIP_TRY(ftk::launch_scan(hcnt, hoff, V, &dctl->total, tmp, s));
+  HIP_TRY(ftk::launch_scan(tcnt, toff, V, (long long*)&dctl->cnt[ftk::CNT_LIST], tmp, s));
+  Ctl h;
+  ftk_status st = read_ctl(&h, dctl, s);
+  if (st) return st;
+  st = decode_status(h.status);
+  if (st) return st;
+  const long long nh = h.total, ntets = (long long)h.cnt[ftk::CNT_LIST];
+  if (nh >= 0xffffffffll) return fail(FTK_ERR_CAPACITY, "%lld crossed edges exceed the 32-bit union-find", nh);
+  ftk_iso_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.n_hits = nh;
+  r.n_tets = ntets;
+  r.edge_id = (int64_t*)al.get(sizeof(int64_t) * (size_t)(nh > 0 ? nh : 1));
+  r.pos = (float*)al.get(sizeof(float) * 4 * (size_t)(nh > 0 ? nh : 1));
+  r.label = (int64_t*)al.get(sizeof(int64_t) * (size_t)(nh > 0 ? nh : 1));
+  r.tets = (int64_t*)al.get(sizeof(int64_t) * 4 * (size_t)(ntets > 0 ? ntets : 1));
+  unsigned* parent = sc.get<unsigned>((size_t)(nh > 0 ? nh : 1));
+  if (!r.edge_id || !r.pos || !r.label || !r.tets || !parent) {
+    ftk_iso_result_free(&r, opt, stream);
+    return fail(FTK_ERR_OOM, "output allocation failed");
+  }
+  hipError_t he = hipSuccess;
+  if (nh > 0) {
+    he = ftk::launch_iso_emit(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, emask, hoff, (long long*)r.edge_id,
+                              r.pos, parent, s);
+    if (he == hipSuccess)
+      he = ftk::launch_iso_unite(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, emask, hoff, tcnt, toff, parent,
+                                 (long long*)r.tets, &dctl->status, s);
+    if (he == hipSuccess)
+      he = ftk::launch_uf_label(parent, (const long long*)r.edge_id, (long long*)r.label, nh, dctl->cnt, s);
+  }
+  if (he != hipSuccess) {
+    ftk_iso_result_free(&r, opt, stream);
+    return fail(FTK_ERR_HIP, "kernel launch: %s", hipGetErrorString(he));
+  }
+  st = read_ctl(&h, dctl, s);
+  if (!st) st = decode_status(h.status);
+  if (st) {
+    ftk_iso_result_free(&r, opt, stream);
+    return st;
+  }
+  r.n_components = (long long)h.cnt[ftk::CNT_TRAJ];
+  *out = r;
+  return FTK_OK;
+}
+
 void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream) {
   if (!p) return;
   ftk_options o;

@@ -1,0 +1,255 @@
+// iso.hip -- isovolume tracking in 3D space + time (Sec. 5.1, two passes on the regular simplicial spacetime mesh;
+// Alg. 1 right column).
+//
+// Mesh (Sec. 3.3): an edge anchored at vertex p with axis mask M (1..15; x = 1, y = 2, z = 4, t = 8) joins p and
+// p + e(M); its id is g(p) * 15 + (M - 1) with the t-major vertex index g.  A pentachoron anchored at p with axis
+// order (s1, s2, s3, s4) has the chain vertices p, p + e(s1), p + e(s1|s2), p + e(s1|s2|s3), p + e(1111).
+//
+//   iso_count -- one lane per vertex: the side of the level set at the 16 corners of its unit 4-cube (a value equal
+//                to the isovalue lies above it: the symbolic perturbation of a single entry is positive, Sec. 5.2),
+//                the crossing mask of its 15 edges, and the tetrahedra of its 24 pentachora (case I: one vertex on
+//                its side, 1 tetrahedron; case II: two, 3 tetrahedra).
+//   iso_emit  -- edge ids and intersection points p + mu e(M), mu = (c - f(p)) / (f(q) - f(p)), from the scanned
+//                counts; union-find parents start as the identity.
+//   iso_unite -- per pentachoron with crossings: unite its crossed edges (CAS hooking, larger root under the
+//                smaller), and write its tetrahedra (indices of crossed edges): case I the four edges of the lone
+//                vertex in chain order; case II the prism pair x triple split along the three monotone paths
+//                (staircase), which matches on the quadrilateral shared with the neighbouring pentachoron.
+// Labels (smallest edge id of each isovolume) come from the shared union-find label kernel.
+#include "common.h"
+#include "internal.h"
+#include "kuhn.h"
+
+namespace ftk {
+
+namespace {
+
+constexpr int kIsoBX = 128;  // lanes per block along x
+
+// chain corners of the 24 pentachoron types: corner k = s1 | ... | sk
+struct PenCorners {
+  unsigned char c[24][5];
+};
+constexpr PenCorners build_pen_corners() {
+  PenCorners r{};
+  for (int ty = 0; ty < 24; ++ty) {
+    int acc = 0;
+    r.c[ty][0] = 0;
+    for (int k = 0; k < 4; ++k) {
+      acc |= kPen3.m[ty][k];
+      r.c[ty][k + 1] = (unsigned char)acc;
+    }
+  }
+  return r;
+}
+__constant__ PenCorners kPenDev = build_pen_corners();
+
+struct IsoGrid {
+  const float* f;
+  int nx, ny, nz, nt;
+  float c;
+};
+
+__device__ __forceinline__ long long vidx(const IsoGrid& g, int x, int y, int z, int t) {
+  return (((long long)t * g.nz + z) * g.ny + y) * g.nx + x;
+}
+
+// above bits of the 16 cube corners (bit cm) and their validity (bit cm: corner in the grid)
+__device__ __forceinline__ void corner_bits(const IsoGrid& g, int x, int y, int z, int t, unsigned& above,
+                                            unsigned& valid, float* fv) {
+  above = 0;
+  valid = 0;
+#pragma unroll
+  for (int cm = 0; cm < 16; ++cm) {
+    const int cx = x + (cm & 1), cy = y + ((cm >> 1) & 1), cz = z + ((cm >> 2) & 1), ct = t + ((cm >> 3) & 1);
+    float v = 0.0f;
+    if (cx < g.nx && cy < g.ny && cz < g.nz && ct < g.nt) {
+      v = g.f[vidx(g, cx, cy, cz, ct)];
+      valid |= 1u << cm;
+      above |= (v >= g.c ? 1u : 0u) << cm;
+    }
+    if (fv) fv[cm] = v;
+  }
+}
+
+__device__ __forceinline__ int pen_above(unsigned above, int ty) {
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) k += (above >> kPenDev.c[ty][i]) & 1u;
+  return k;
+}
+
+__global__ __launch_bounds__(kIsoBX) void iso_count(IsoGrid g, unsigned short* __restrict__ emask,
+                                                     int* __restrict__ hcnt, int* __restrict__ tcnt,
+                                                     unsigned* __restrict__ status) {
+  const int x = blockIdx.x * kIsoBX + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
+  if (x >= g.nx) return;
+  const long long v = vidx(g, x, y, z, t);
+  unsigned above, valid;
+  corner_bits(g, x, y, z, t, above, valid, nullptr);
+  if (!isfinite(g.f[v])) atomicOr(status, ST_NONFINITE);
+  unsigned m = 0;
+#pragma unroll
+  for (int M = 1; M < 16; ++M)
+    if (((valid >> M) & 1u) && (((above >> M) ^ above) & 1u)) m |= 1u << (M - 1);
+  int tets = 0;
+  if (valid == 0xffffu && above != 0u && above != 0xffffu) {
+#pragma unroll 4
+    for (int ty = 0; ty < 24; ++ty) {
+      const int k = pen_above(above, ty);
+      tets += (k == 1 || k == 4) ? 1 : ((k == 2 || k == 3) ? 3 : 0);
+    }
+  }
+  emask[v] = (unsigned short)m;
+  hcnt[v] = __popc(m);
+  tcnt[v] = tets;
+}
+
+__global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned short* __restrict__ emask,
+                                                    const long long* __restrict__ hoff, long long* __restrict__ edge_id,
+                                                    float* __restrict__ pos, unsigned* __restrict__ parent) {
+  const int x = blockIdx.x * kIsoBX + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
+  if (x >= g.nx) return;
+  const long long v = vidx(g, x, y, z, t);
+  unsigned m = emask[v];
+  if (!m) return;
+  const float f0 = g.f[v];
+  long long o = hoff[v];
+  while (m) {
+    const int b = __ffs(m) - 1;
+    m &= m - 1;
+    const int M = b + 1;
+    const int dx = M & 1, dy = (M >> 1) & 1, dz = (M >> 2) & 1, dt = (M >> 3) & 1;
+    const float f1 = g.f[vidx(g, x + dx, y + dy, z + dz, t + dt)];
+    const float mu = (g.c - f0) / (f1 - f0);
+    edge_id[o] = v * 15 + b;
+    if (pos) {
+      pos[o * 4 + 0] = (float)x + mu * (float)dx;
+      pos[o * 4 + 1] = (float)y + mu * (float)dy;
+      pos[o * 4 + 2] = (float)z + mu * (float)dz;
+      pos[o * 4 + 3] = (float)t + mu * (float)dt;
+    }
+    parent[o] = (unsigned)o;
+    ++o;
+  }
+}
+
+__global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const unsigned short* __restrict__ emask,
+                                                     const long long* __restrict__ hoff,
+                                                     const int* __restrict__ tcnt, const long long* __restrict__ toff,
+                                                     unsigned* __restrict__ parent, long long* __restrict__ tets,
+                                                     unsigned* __restrict__ status) {
+  const int x = blockIdx.x * kIsoBX + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
+  if (x >= g.nx) return;
+  const long long v = vidx(g, x, y, z, t);
+  if (tcnt[v] == 0) return;
+  unsigned above, valid;
+  corner_bits(g, x, y, z, t, above, valid, nullptr);
+  // first hit index and crossing mask of every corner that anchors an edge of a pentachoron (all but 1111)
+  long long cb[15];
+  unsigned cm_mask[15];
+#pragma unroll
+  for (int cm = 0; cm < 15; ++cm) {
+    const long long w = vidx(g, x + (cm & 1), y + ((cm >> 1) & 1), z + ((cm >> 2) & 1), t + ((cm >> 3) & 1));
+    cb[cm] = hoff[w];
+    cm_mask[cm] = emask[w];
+  }
+  long long o = toff[v];
+  const long long o_end = o + tcnt[v];
+  for (int ty = 0; ty < 24; ++ty) {
+    unsigned ch[5];
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      ch[i] = kPenDev.c[ty][i];
+      k += (above >> ch[i]) & 1u;
+    }
+    if (k == 0 || k == 5) continue;
+    // hit index of the edge between chain vertices i < j (crossed, so its bit is set; the count pass took the same
+    // decisions, so a clear bit is an internal error and the pentachoron is skipped)
+    bool bad = false;
+    auto edge = [&](int i, int j) -> long long {
+      const unsigned a = ch[i], M = ch[j] ^ ch[i];
+      const unsigned mk = cm_mask[a];
+      if (!((mk >> (M - 1)) & 1u)) bad = true;
+      return cb[a] + __popc(mk & ((1u << (M - 1)) - 1u));
+    };
+    // minority side: the one (case I) or two (case II) chain vertices on the less populated side
+    const unsigned lone_side = k <= 2 ? 1u : 0u;
+    int mi[2] = {0, 0}, ma[4] = {0, 0, 0, 0}, nm = 0, na = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      if (((above >> ch[i]) & 1u) == lone_side) {
+        if (nm < 2) mi[nm++] = i;
+      } else {
+        if (na < 4) ma[na++] = i;
+      }
+    }
+    if (nm + na != 5) {
+      atomicOr(status, ST_INVARIANT);
+      return;
+    }
+    auto pe = [&](int p, int q) { return edge(min(mi[p], ma[q]), max(mi[p], ma[q])); };
+    for (int p = 0; p < nm; ++p)
+      for (int q = 0; q < na; ++q) (void)pe(p, q);
+    if (bad) {
+      atomicOr(status, ST_INVARIANT);
+      return;
+    }
+    // the crossed edges are exactly the (minority, majority) pairs: unite each with the first
+    const long long e0 = pe(0, 0);
+    for (int p = 0; p < nm; ++p)
+      for (int q = 0; q < na; ++q)
+        if (p | q) uf_unite(parent, (unsigned)e0, (unsigned)pe(p, q));
+    const int nt_here = nm == 1 ? 1 : 3;
+    if (o + nt_here > o_end) {
+      atomicOr(status, ST_INVARIANT);
+      return;
+    }
+    long long* T = tets + o * 4;
+    if (nm == 1) {
+      for (int q = 0; q < 4; ++q) T[q] = pe(0, q);
+    } else {
+      const long long p1m1 = pe(0, 0), p1m2 = pe(0, 1), p1m3 = pe(0, 2);
+      const long long p2m1 = pe(1, 0), p2m2 = pe(1, 1), p2m3 = pe(1, 2);
+      T[0] = p1m1; T[1] = p1m2; T[2] = p1m3; T[3] = p2m3;
+      T[4] = p1m1; T[5] = p1m2; T[6] = p2m2; T[7] = p2m3;
+      T[8] = p1m1; T[9] = p2m1; T[10] = p2m2; T[11] = p2m3;
+    }
+    o += nt_here;
+  }
+}
+
+dim3 iso_grid(const IsoGrid& g) { return dim3((unsigned)((g.nx + kIsoBX - 1) / kIsoBX), (unsigned)g.ny, (unsigned)(g.nz * g.nt)); }
+
+}  // namespace
+
+hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, float c, unsigned short* emask, int* hcnt,
+                            int* tcnt, unsigned* status, hipStream_t s) {
+  const IsoGrid g{f, nx, ny, nz, nt, c};
+  iso_count<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hcnt, tcnt, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float c, const unsigned short* emask,
+                           const long long* hoff, long long* edge_id, float* pos, unsigned* parent, hipStream_t s) {
+  const IsoGrid g{f, nx, ny, nz, nt, c};
+  iso_emit<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hoff, edge_id, pos, parent);
+  return hipGetLastError();
+}
+
+hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c, const unsigned short* emask,
+                            const long long* hoff, const int* tcnt, const long long* toff, unsigned* parent,
+                            long long* tets, unsigned* status, hipStream_t s) {
+  const IsoGrid g{f, nx, ny, nz, nt, c};
+  iso_unite<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hoff, tcnt, toff, parent, tets, status);
+  return hipGetLastError();
+}
+
+}  // namespace ftk
