@@ -28,6 +28,7 @@ WORKLOADS = {
     "blobs3d256": "3D scalar 256x256x256x16, 512 moving Gaussians, seed 2",
     "vortex4096": "2D vector 4096x4096x50, 1024 moving sources/sinks/vortices, seed 4",
     "batch96": "96 uneven 2D scalar series (nx, ny log-uniform 128-2048, 8-64 steps), seeds 3+i; batched vs plain",
+    "iso_blobs3d256": "isovolume f = 0.5 of the 3D scalar 256x256x256x16 blob series (512 moving Gaussians, seed 2)",
 }
 
 
@@ -164,6 +165,66 @@ def precision_report(F, field_np, field, kind, n, sample=20000):
             "degenerate_frac": float(np.mean((flg & 1) != 0))}
 
 
+def bench_iso(args, F, synth, dev):
+    """Isovolume tracking (edge pass, pentachoron unions, tessellation, labels) of the 3D blob series: K calls of
+    ftk_track_iso3d on the resident field; value = spacetime edges tested per second."""
+    import numpy as np
+    import torch
+    field = torch.from_numpy(synth.make("blobs3d256", device=dev)).to(dev)
+    nt, nz, ny, nx = field.shape
+    dims = (nx, ny, nz, nt)
+    c = 0.5
+    L = F.lib()
+    stream = torch.cuda.current_stream(dev)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    pool = F._TorchPool(dev)
+    opt = F._options(pool)
+
+    def one():
+        r = F.IsoResult()
+        st = L.ftk_track_iso3d(ctypes.c_void_p(field.data_ptr()), nx, ny, nz, nt, c, ctypes.byref(opt), sh,
+                               ctypes.byref(r))
+        if st != 0:
+            raise F.FtkError(st, F.last_error())
+        out = (int(r.n_hits), int(r.n_components), int(r.n_tets))
+        L.ftk_iso_result_free(ctypes.byref(r), ctypes.byref(opt), sh)
+        return out
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nh, ncomp, ntets = one()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el * 1e3 / args.steps
+    edges = F.edge_count(dims)
+    V = int(np.prod(dims))
+    alg = 4 * V + 32 * nh + 32 * ntets  # field in; edge id, position and label per crossing; 4 indices per tet
+    line = {
+        "metric": "spacetime edges tested/s (isovolume tracking)", "value": round(edges / (ms * 1e-3), 1),
+        "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["iso_blobs3d256"], "dims": list(dims), "isovalue": c, "n_hits": nh,
+                   "n_components": ncomp, "n_tets": ntets, "edges_per_step": edges},
+        "roofline": {"bound": "hbm", "kernel": "whole call", "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import iso as OI
+        sample = np.ascontiguousarray(field[:2, :24, :24, :24].cpu().numpy())
+        t0 = time.perf_counter()
+        OI.track_iso(sample, c)
+        cpu_s = time.perf_counter() - t0
+        se = F.edge_count((24, 24, 24, 2))
+        line["cpu_baseline"] = {"value": round(se / cpu_s, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+                                "sample": f"24x24x24x2 corner of the same series ({se} edges, numpy, {cpu_s:.1f} s)"}
+    print(json.dumps(line), flush=True)
+
+
 def post_report(F, field, n, kind, dims, reps=2):
     """Wall time of each trajectory post-processing call on this workload's result (after the timed region; not part
     of value): table, slice at the middle step, loop filter, order, smoothing (half window 2), simplification."""
@@ -214,6 +275,8 @@ def main():
     wl = args.workload
     if wl == "batch96":
         return bench_batched(args, F, synth, dev)
+    if wl == "iso_blobs3d256":
+        return bench_iso(args, F, synth, dev)
     n = 3 if wl == "blobs3d256" else 2
     kind = 1 if wl == "vortex4096" else 0
     t0 = time.time()

@@ -138,6 +138,23 @@ __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned sho
   }
 }
 
+// Unite for this pass, where most pairs are already connected: first a find through plain (cached, possibly stale)
+// loads.  A stale parent is still an ancestor and sets only merge, so equal roots mean the pair is connected now;
+// otherwise the coherent path (uf_unite) decides.
+__device__ __forceinline__ unsigned uf_find_cached(const unsigned* parent, unsigned x) {
+  unsigned p = parent[x];
+  while (p != x) {
+    x = p;
+    p = parent[x];
+  }
+  return x;
+}
+
+__device__ __forceinline__ void uf_unite_cached(unsigned* parent, unsigned a, unsigned b) {
+  if (uf_find_cached(parent, a) == uf_find_cached(parent, b)) return;
+  uf_unite(parent, a, b);
+}
+
 __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const unsigned short* __restrict__ emask,
                                                      const long long* __restrict__ hoff,
                                                      const int* __restrict__ tcnt, const long long* __restrict__ toff,
@@ -206,7 +223,7 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const unsigned sh
     const long long e0 = pe(0, 0);
     for (int p = 0; p < nm; ++p)
       for (int q = 0; q < na; ++q)
-        if (p | q) uf_unite(parent, (unsigned)e0, (unsigned)pe(p, q));
+        if (p | q) uf_unite_cached(parent, (unsigned)e0, (unsigned)pe(p, q));
     const int nt_here = nm == 1 ? 1 : 3;
     if (o + nt_here > o_end) {
       atomicOr(status, ST_INVARIANT);
