@@ -1569,20 +1569,23 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   int* tcnt = sc.get<int>((size_t)V);
   long long* hoff = sc.get<long long>((size_t)V);
   long long* toff = sc.get<long long>((size_t)V);
+  long long* aoff = sc.get<long long>((size_t)V);
   long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(V));
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!emask || !hcnt || !tcnt || !hoff || !toff || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  if (!emask || !hcnt || !tcnt || !hoff || !toff || !aoff || !tmp || !dctl)
+    return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   HIP_TRY(ftk::launch_iso_count(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, emask, hcnt, tcnt,
                                 &dctl->status, s));
   HIP_TRY(ftk::launch_scan(hcnt, hoff, V, &dctl->total, tmp, s));
   HIP_TRY(ftk::launch_scan(tcnt, toff, V, (long long*)&dctl->cnt[ftk::CNT_LIST], tmp, s));
+  HIP_TRY(ftk::launch_iso_active(tcnt, V, hcnt, aoff, (long long*)&dctl->cnt[ftk::CNT_WORK], tmp, nullptr, false, s));
   Ctl h;
   ftk_status st = read_ctl(&h, dctl, s);
   if (st) return st;
   st = decode_status(h.status);
   if (st) return st;
-  const long long nh = h.total, ntets = (long long)h.cnt[ftk::CNT_LIST];
+  const long long nh = h.total, ntets = (long long)h.cnt[ftk::CNT_LIST], nact = (long long)h.cnt[ftk::CNT_WORK];
   if (nh >= 0xffffffffll) return fail(FTK_ERR_CAPACITY, "%lld crossed edges exceed the 32-bit union-find", nh);
   ftk_iso_result r;
   std::memset(&r, 0, sizeof(r));
@@ -1593,7 +1596,8 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   r.label = (int64_t*)al.get(sizeof(int64_t) * (size_t)(nh > 0 ? nh : 1));
   r.tets = (int64_t*)al.get(sizeof(int64_t) * 4 * (size_t)(ntets > 0 ? ntets : 1));
   unsigned* parent = sc.get<unsigned>((size_t)(nh > 0 ? nh : 1));
-  if (!r.edge_id || !r.pos || !r.label || !r.tets || !parent) {
+  long long* active = sc.get<long long>((size_t)(nact > 0 ? nact : 1));
+  if (!r.edge_id || !r.pos || !r.label || !r.tets || !parent || !active) {
     ftk_iso_result_free(&r, opt, stream);
     return fail(FTK_ERR_OOM, "output allocation failed");
   }
@@ -1602,8 +1606,10 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
     he = ftk::launch_iso_emit(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, emask, hoff, (long long*)r.edge_id,
                               r.pos, parent, s);
     if (he == hipSuccess)
-      he = ftk::launch_iso_unite(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, emask, hoff, tcnt, toff, parent,
-                                 (long long*)r.tets, &dctl->status, s);
+      he = ftk::launch_iso_active(tcnt, V, hcnt, aoff, nullptr, nullptr, active, true, s);
+    if (he == hipSuccess)
+      he = ftk::launch_iso_unite(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, active, nact, emask, hoff, tcnt,
+                                 toff, parent, (long long*)r.tets, &dctl->status, s);
     if (he == hipSuccess)
       he = ftk::launch_uf_label(parent, (const long long*)r.edge_id, (long long*)r.label, nh, dctl->cnt, s);
   }

@@ -44,6 +44,22 @@ constexpr PenCorners build_pen_corners() {
 }
 __constant__ PenCorners kPenDev = build_pen_corners();
 
+// Local index (0..64) of the edge between cube corners a and a | M (a & M == 0, M != 0), 255 otherwise.
+struct CubeEdges {
+  unsigned char idx[16][16];
+};
+constexpr CubeEdges build_cube_edges() {
+  CubeEdges r{};
+  int k = 0;
+  for (int a = 0; a < 16; ++a)
+    for (int M = 0; M < 16; ++M) r.idx[a][M] = 255;
+  for (int a = 0; a < 16; ++a)
+    for (int M = 1; M < 16; ++M)
+      if (!(a & M)) r.idx[a][M] = (unsigned char)k++;
+  return r;
+}
+__constant__ CubeEdges kCubeEdges = build_cube_edges();
+
 struct IsoGrid {
   const float* f;
   int nx, ny, nz, nt;
@@ -107,6 +123,19 @@ __global__ __launch_bounds__(kIsoBX) void iso_count(IsoGrid g, unsigned short* _
   tcnt[v] = tets;
 }
 
+// list of the vertices whose cube has crossed pentachora (about one in sixteen on smooth fields), so that the
+// pentachoron pass runs on busy lanes only
+__global__ void iso_active_flags(const int* __restrict__ tcnt, long long V, int* __restrict__ flag) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < V) flag[v] = tcnt[v] > 0 ? 1 : 0;
+}
+
+__global__ void iso_active_list(const int* __restrict__ flag, const long long* __restrict__ off, long long V,
+                                long long* __restrict__ list) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < V && flag[v]) list[off[v]] = v;
+}
+
 __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned short* __restrict__ emask,
                                                     const long long* __restrict__ hoff, long long* __restrict__ edge_id,
                                                     float* __restrict__ pos, unsigned* __restrict__ parent) {
@@ -155,16 +184,19 @@ __device__ __forceinline__ void uf_unite_cached(unsigned* parent, unsigned a, un
   uf_unite(parent, a, b);
 }
 
-__global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const unsigned short* __restrict__ emask,
+__global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* __restrict__ active,
+                                                     long long n_active, const unsigned short* __restrict__ emask,
                                                      const long long* __restrict__ hoff,
                                                      const int* __restrict__ tcnt, const long long* __restrict__ toff,
                                                      unsigned* __restrict__ parent, long long* __restrict__ tets,
                                                      unsigned* __restrict__ status) {
-  const int x = blockIdx.x * kIsoBX + threadIdx.x;
-  const int y = blockIdx.y;
-  const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
-  if (x >= g.nx) return;
-  const long long v = vidx(g, x, y, z, t);
+  const long long a_i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a_i >= n_active) return;
+  const long long v = active[a_i];
+  const int x = (int)(v % g.nx);
+  const int y = (int)((v / g.nx) % g.ny);
+  const int z = (int)((v / ((long long)g.nx * g.ny)) % g.nz);
+  const int t = (int)(v / ((long long)g.nx * g.ny * g.nz));
   if (tcnt[v] == 0) return;
   unsigned above, valid;
   corner_bits(g, x, y, z, t, above, valid, nullptr);
@@ -179,6 +211,12 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const unsigned sh
   }
   long long o = toff[v];
   const long long o_end = o + tcnt[v];
+  // When the cube's diagonal (corner 0 to corner 1111) crosses, it is a crossed edge of all 24 pentachora, so the
+  // cube's crossed edges form one set: each is united once with the diagonal.  Otherwise each pentachoron unites
+  // its own crossed edges.
+  const bool diag = ((above ^ (above >> 15)) & 1u) != 0u;
+  const long long dhit = cb[0] + __popc(cm_mask[0] & ((1u << 14) - 1u));
+  unsigned long long seen0 = 0, seen1 = 0;
   for (int ty = 0; ty < 24; ++ty) {
     unsigned ch[5];
     int k = 0;
@@ -219,11 +257,28 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const unsigned sh
       atomicOr(status, ST_INVARIANT);
       return;
     }
-    // the crossed edges are exactly the (minority, majority) pairs: unite each with the first
-    const long long e0 = pe(0, 0);
-    for (int p = 0; p < nm; ++p)
-      for (int q = 0; q < na; ++q)
-        if (p | q) uf_unite_cached(parent, (unsigned)e0, (unsigned)pe(p, q));
+    // the crossed edges are exactly the (minority, majority) pairs
+    if (diag) {
+      for (int p = 0; p < nm; ++p)
+        for (int q = 0; q < na; ++q) {
+          const int i = min(mi[p], ma[q]), j = max(mi[p], ma[q]);
+          const unsigned li = kCubeEdges.idx[ch[i]][ch[j] ^ ch[i]];
+          const unsigned long long bit = 1ull << (li & 63u);
+          const bool seen = li < 64u ? (seen0 & bit) != 0 : (seen1 & bit) != 0;
+          if (seen) continue;
+          if (li < 64u)
+            seen0 |= bit;
+          else
+            seen1 |= bit;
+          const long long e = pe(p, q);
+          if (e != dhit) uf_unite_cached(parent, (unsigned)dhit, (unsigned)e);
+        }
+    } else {
+      const long long e0 = pe(0, 0);
+      for (int p = 0; p < nm; ++p)
+        for (int q = 0; q < na; ++q)
+          if (p | q) uf_unite_cached(parent, (unsigned)e0, (unsigned)pe(p, q));
+    }
     const int nt_here = nm == 1 ? 1 : 3;
     if (o + nt_here > o_end) {
       atomicOr(status, ST_INVARIANT);
@@ -261,11 +316,25 @@ hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float
   return hipGetLastError();
 }
 
-hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c, const unsigned short* emask,
-                            const long long* hoff, const int* tcnt, const long long* toff, unsigned* parent,
-                            long long* tets, unsigned* status, hipStream_t s) {
+hipError_t launch_iso_active(const int* tcnt, long long V, int* flag, long long* off, long long* total,
+                             long long* scan_tmp, long long* list, bool scatter, hipStream_t s) {
+  const unsigned b = (unsigned)((V + 255) / 256);
+  if (!scatter) {
+    iso_active_flags<<<b, 256, 0, s>>>(tcnt, V, flag);
+    return launch_scan(flag, off, V, total, scan_tmp, s);
+  }
+  iso_active_list<<<b, 256, 0, s>>>(flag, off, V, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c, const long long* active,
+                            long long n_active, const unsigned short* emask, const long long* hoff, const int* tcnt,
+                            const long long* toff, unsigned* parent, long long* tets, unsigned* status,
+                            hipStream_t s) {
+  if (n_active == 0) return hipSuccess;
   const IsoGrid g{f, nx, ny, nz, nt, c};
-  iso_unite<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hoff, tcnt, toff, parent, tets, status);
+  iso_unite<<<(unsigned)((n_active + kIsoBX - 1) / kIsoBX), kIsoBX, 0, s>>>(g, active, n_active, emask, hoff, tcnt,
+                                                                            toff, parent, tets, status);
   return hipGetLastError();
 }
 
