@@ -6,9 +6,11 @@
 // vectors of one of its triangles, so one SoS sign bit per triangle (50 per vertex, a 64-bit word) is computed and
 // shared through LDS.
 //
-//   detect3d -- time-marching slab kernel over a 16 x 8 x 4 anchor tile: field plane with a 2-cell halo, gradient,
-//               quantisation, triangle sign words of the tile (+1 halo), 60 tetrahedron tests per anchor; writes a
-//               60-bit puncture mask per vertex and the hit count of every 16-vertex row segment.
+//   detect3d -- time-marching slab kernel over a 16 x 8 x 4 anchor tile: gradient stencils read from global memory
+//               (L2-cached neighbours) and quantised into LDS, triangle sign words of the tile (+1 halo), 60
+//               tetrahedron tests per anchor; writes a 60-bit puncture mask per vertex and the hit count of every
+//               16-vertex row segment.  Without a staged field plane the block's LDS (38.5 KB) admits four blocks
+//               per CU, and the register target of four waves per SIMD matches it.
 //   emit3d   -- one lane per vertex (hits are sparse in 3D): output index from the segment prefix, exact cofactors,
 //               sublocation, Hessian type, and the union-find links of the hit's two pentachora (Alg. 1 pass 2).
 #include "common.h"
@@ -214,14 +216,12 @@ struct ItvList {
 // Pass 1: detection.  grid = (ceil(nx/16), ceil(ny/8) * ceil(nz/4), ceil(nt/TT)), block = 256.
 // ---------------------------------------------------------------------------------------------------------------
 template <bool WIDE>
-__global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64_t* __restrict__ masks,
-                                                int* __restrict__ seg_cnt, unsigned* __restrict__ status) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void detect3d(
+    Grid3 g, int TT, int nyt, uint64_t* __restrict__ masks, int* __restrict__ seg_cnt, unsigned* __restrict__ status) {
   typedef typename Q3<WIDE>::T Q;
-  constexpr int FX = TX3 + 4, FY = TY3 + 4, FZ = TZ3 + 4;  // field: x0-1 .. x0+TX+2
   constexpr int QX = TX3 + 2, QY = TY3 + 2, QZ = TZ3 + 2;  // quantised vectors: x0 .. x0+TX+1
   constexpr int WX = TX3 + 1, WY = TY3 + 1, WZ = TZ3 + 1;  // triangle words: x0 .. x0+TX
-  constexpr int FN = FX * FY * FZ, QN = QX * QY * QZ, WN = WX * WY * WZ;
-  __shared__ float fs[FN];
+  constexpr int QN = QX * QY * QZ, WN = WX * WY * WZ;
   __shared__ Q qs[2][3][QN];
   __shared__ unsigned long long tw[2][WN];
   __shared__ unsigned s_tri[50];
@@ -246,29 +246,23 @@ __global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64
   const long long plane = (long long)nx * ny * nz;
   unsigned st = 0;
 
-  auto load_plane = [&](int t) {
-    const float* src = g.f + (long long)t * plane;
-    for (int e = tid; e < FN; e += 256) {
-      int lx = e % FX, r = e / FX, ly = r % FY, lz = r / FY;
-      int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-      float v = 0.0f;
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
-        v = src[((long long)gz * ny + gy) * nx + gx];
-        if (!isfinite(v)) st |= ST_NONFINITE;
-      }
-      fs[e] = v;
-    }
-  };
-  auto quantise_plane = [&](int par) {
+  auto quantise_plane = [&](int tq, int par) {
+    const float* src = g.f + (long long)tq * plane;
+    const long long sxy = (long long)nx * ny;
     for (int e = tid; e < QN; e += 256) {
       int lx = e % QX, r = e / QX, ly = r % QY, lz = r / QY;
       int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
       Q q0 = 0, q1 = 0, q2 = 0;
       if (gx < nx && gy < ny && gz < nz) {
-        const float* c = &fs[((lz + 1) * FY + (ly + 1)) * FX + (lx + 1)];
-        float v0 = diff3(c[-1], c[0], c[1], gx, nx);
-        float v1 = diff3(c[-FX], c[0], c[FX], gy, ny);
-        float v2 = diff3(c[-FX * FY], c[0], c[FX * FY], gz, nz);
+        const float* c = src + ((long long)gz * ny + gy) * nx + gx;
+        const float c0 = c[0];
+        if (!isfinite(c0)) st |= ST_NONFINITE;
+        const float xl = gx > 0 ? c[-1] : 0.0f, xh = gx < nx - 1 ? c[1] : 0.0f;
+        const float yl = gy > 0 ? c[-nx] : 0.0f, yh = gy < ny - 1 ? c[nx] : 0.0f;
+        const float zl = gz > 0 ? c[-sxy] : 0.0f, zh = gz < nz - 1 ? c[sxy] : 0.0f;
+        float v0 = diff3(xl, c0, xh, gx, nx);
+        float v1 = diff3(yl, c0, yh, gy, ny);
+        float v2 = diff3(zl, c0, zh, gz, nz);
         q0 = to_q3<WIDE>(quant(v0, g.qscale), st);
         q1 = to_q3<WIDE>(quant(v1, g.qscale), st);
         q2 = to_q3<WIDE>(quant(v2, g.qscale), st);
@@ -364,9 +358,7 @@ __global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64
       tris(par, 12, 50, false);
   };
 
-  load_plane(t0);
-  __syncthreads();
-  quantise_plane(t0 & 1);
+  quantise_plane(t0, t0 & 1);
   __syncthreads();
   ordinal_tris(t0 & 1);
 
@@ -375,9 +367,7 @@ __global__ __launch_bounds__(256) void detect3d(Grid3 g, int TT, int nyt, uint64
     const bool has_next = t + 1 < nt;
     __syncthreads();
     if (has_next) {
-      load_plane(t + 1);
-      __syncthreads();
-      quantise_plane(nxp);
+      quantise_plane(t + 1, nxp);
       __syncthreads();
       ordinal_tris(nxp);
       interval_tris(par);
