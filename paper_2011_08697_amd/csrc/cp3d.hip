@@ -216,7 +216,7 @@ struct ItvList {
 // Pass 1: detection.  grid = (ceil(nx/16), ceil(ny/8) * ceil(nz/4), ceil(nt/TT)), block = 256.
 // ---------------------------------------------------------------------------------------------------------------
 template <bool WIDE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void detect3d(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 4))) void detect3d(
     Grid3 g, int TT, int nyt, uint64_t* __restrict__ masks, int* __restrict__ seg_cnt, unsigned* __restrict__ status) {
   typedef typename Q3<WIDE>::T Q;
   constexpr int QX = TX3 + 2, QY = TY3 + 2, QZ = TZ3 + 2;  // quantised vectors: x0 .. x0+TX+1
