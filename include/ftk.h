@@ -290,6 +290,34 @@ void ftk_iso_result_free(ftk_iso_result* r, const ftk_options* opt, ftk_stream_t
  * dims_with_t = (nx, ny, nz, nt).  Returns -1 for bad arguments. */
 int64_t ftk_edge_count(const int64_t* dims_with_t);
 
+/*
+ * Quantum vortex surface tracking in a 3D complex series (Sec. 6.1, two passes on the spacetime mesh).
+ * psi: device pointer, contiguous binary32 [nt][2][nz][ny][nx] (real and imaginary planes per step).  A spacetime
+ * triangle anchored at vertex p (t-major index g) with axis masks (M1, M2) (x = 1, y = 2, z = 4, t = 8; 50 types in
+ * lexicographic order) has the vertices p, p + e(M1), p + e(M1|M2) and the id g * 50 + type.  It is positive when
+ * the phase changes along its edges, each wrapped into (-pi, pi], sum to +-2 pi: exactly when 0 lies inside the
+ * triangle (psi_0, psi_1, psi_2) of the complex plane, decided on q = rint(psi * 2^opt->quant_log2) with the symbolic
+ * perturbation.  The positive triangles of every pentachoron are united into vortex surfaces.  Outputs through
+ * opt->alloc (or hipMallocAsync on stream); release with ftk_vortex_result_free.  Synchronises the stream twice.
+ * Every dimension >= 2; ny and nz * nt at most 65535.  FTK_ERR_NONFINITE for NaN/Inf; FTK_ERR_RANGE when a
+ * quantised value reaches 2^31; FTK_ERR_CAPACITY beyond 2^32 - 2 positive triangles.
+ */
+typedef struct {
+  int64_t n_hits;       /* positive triangles */
+  int64_t n_components; /* vortex surfaces */
+  int64_t* tri_id;      /* [n_hits] ascending */
+  float* pos;           /* [n_hits][4] vortex point (x, y, z, t) from the exact barycentric weights (Eq. 2) */
+  int64_t* label;       /* [n_hits] smallest triangle id of the surface */
+} ftk_vortex_result;
+
+ftk_status ftk_track_vortex3d(const float* psi, int64_t nx, int64_t ny, int64_t nz, int64_t nt,
+                              const ftk_options* opt, ftk_stream_t stream, ftk_vortex_result* out);
+void ftk_vortex_result_free(ftk_vortex_result* r, const ftk_options* opt, ftk_stream_t stream);
+
+/* Number of triangles tested for a 3D grid: sum over the 50 triangle types of prod_a (N_a - [a used]),
+ * dims_with_t = (nx, ny, nz, nt).  Returns -1 for bad arguments. */
+int64_t ftk_triangle_count(const int64_t* dims_with_t);
+
 /* Release the device arrays of a result (with the allocator given in opt, which may be NULL). */
 void ftk_result_free(ftk_cp_result* r, const ftk_options* opt, ftk_stream_t stream);
 

@@ -23,7 +23,7 @@ EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_cr
            "ftk_last_error", "ftk_version", "ftk_traj_table_build", "ftk_traj_table_free", "ftk_cp_slice",
            "ftk_cp_filter_loops", "ftk_buffer_free", "ftk_autotune_cp2d", "ftk_traj_order",
            "ftk_traj_smooth_types", "ftk_traj_simplify_types", "ftk_track_iso3d", "ftk_iso_result_free",
-           "ftk_edge_count"]
+           "ftk_edge_count", "ftk_track_vortex3d", "ftk_vortex_result_free", "ftk_triangle_count"]
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -62,6 +62,11 @@ class IsoResult(ctypes.Structure):
     _fields_ = [("n_hits", ctypes.c_int64), ("n_components", ctypes.c_int64), ("n_tets", ctypes.c_int64),
                 ("edge_id", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("label", ctypes.c_void_p),
                 ("tets", ctypes.c_void_p)]
+
+
+class VortexResult(ctypes.Structure):
+    _fields_ = [("n_hits", ctypes.c_int64), ("n_components", ctypes.c_int64), ("tri_id", ctypes.c_void_p),
+                ("pos", ctypes.c_void_p), ("label", ctypes.c_void_p)]
 
 
 class TrajTable(ctypes.Structure):
@@ -122,6 +127,13 @@ def lib():
         L.ftk_iso_result_free.restype = None
         L.ftk_edge_count.argtypes = [ctypes.POINTER(i64)]
         L.ftk_edge_count.restype = i64
+        L.ftk_track_vortex3d.argtypes = [vp, i64, i64, i64, i64, ctypes.POINTER(Options), vp,
+                                         ctypes.POINTER(VortexResult)]
+        L.ftk_track_vortex3d.restype = ctypes.c_int
+        L.ftk_vortex_result_free.argtypes = [ctypes.POINTER(VortexResult), ctypes.POINTER(Options), vp]
+        L.ftk_vortex_result_free.restype = None
+        L.ftk_triangle_count.argtypes = [ctypes.POINTER(i64)]
+        L.ftk_triangle_count.restype = i64
         L.ftk_traj_order.argtypes = [ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(i64),
                                      ctypes.POINTER(TrajTable), ctypes.POINTER(Options), vp, vp, vp]
         L.ftk_traj_order.restype = ctypes.c_int
@@ -400,6 +412,32 @@ def track_iso3d(field, isovalue):
                 pos=pool.take(r.pos, torch.float32, (max(nh, 1), 4))[:nh],
                 label=pool.take(r.label, torch.int64, (max(nh, 1),))[:nh],
                 tets=pool.take(r.tets, torch.int64, (max(nt4, 1), 4))[:nt4])
+
+
+def track_vortex3d(psi, **opts):
+    """Vortex surfaces of a 3D complex series: psi is a contiguous float32 CUDA tensor [nt][2][nz][ny][nx] (real and
+    imaginary planes).  Returns positive triangles (tri_id ascending, pos [n][4] as x, y, z, t), labels (smallest
+    triangle id of each surface) and n_components."""
+    import torch
+    if not psi.is_contiguous() or psi.dtype != torch.float32 or not psi.is_cuda or psi.dim() != 5 or psi.shape[1] != 2:
+        raise ValueError("psi must be a contiguous float32 device tensor [nt][2][nz][ny][nx]")
+    nt, _, nz, ny, nx = psi.shape
+    pool = _TorchPool(psi.device)
+    o = _options(pool, **opts)
+    r = VortexResult()
+    _check(lib().ftk_track_vortex3d(ctypes.c_void_p(psi.data_ptr()), nx, ny, nz, nt, ctypes.byref(o),
+                                    _stream_handle(psi.device), ctypes.byref(r)))
+    nh = int(r.n_hits)
+    return dict(n_hits=nh, n_components=int(r.n_components),
+                tri_id=pool.take(r.tri_id, torch.int64, (max(nh, 1),))[:nh],
+                pos=pool.take(r.pos, torch.float32, (max(nh, 1), 4))[:nh],
+                label=pool.take(r.label, torch.int64, (max(nh, 1),))[:nh])
+
+
+def triangle_count(dims_with_t):
+    """Spacetime triangles tested for a 3D grid (nx, ny, nz, nt)."""
+    arr = (ctypes.c_int64 * 4)(*dims_with_t)
+    return int(lib().ftk_triangle_count(arr))
 
 
 def edge_count(dims_with_t):

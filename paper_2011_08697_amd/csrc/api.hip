@@ -1628,6 +1628,98 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   return FTK_OK;
 }
 
+int64_t ftk_triangle_count(const int64_t* d) {
+  if (!d) return -1;
+  for (int a = 0; a < 4; ++a)
+    if (d[a] < 2) return -1;
+  int64_t tot = 0;
+  for (int ty = 0; ty < ftk::kTri3.count; ++ty) {
+    const int u = ftk::kTri3.m[ty][0] | ftk::kTri3.m[ty][1];
+    int64_t p = 1;
+    for (int a = 0; a < 4; ++a) p *= d[a] - ((u >> a) & 1);
+    tot += p;
+  }
+  return tot;
+}
+
+void ftk_vortex_result_free(ftk_vortex_result* r, const ftk_options* opt, ftk_stream_t stream) {
+  if (!r) return;
+  ftk_options o;
+  resolve(opt, &o);
+  const Alloc al = make_alloc(o, (hipStream_t)stream);
+  al.put(r->tri_id);
+  al.put(r->pos);
+  al.put(r->label);
+  std::memset(r, 0, sizeof(*r));
+}
+
+ftk_status ftk_track_vortex3d(const float* psi, int64_t nx, int64_t ny, int64_t nz, int64_t nt,
+                              const ftk_options* opt, ftk_stream_t stream, ftk_vortex_result* out) {
+  g_err.clear();
+  if (!out) return fail(FTK_ERR_ARG, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (!psi) return fail(FTK_ERR_ARG, "psi is NULL");
+  if (nx < 2 || ny < 2 || nz < 2 || nt < 2) return fail(FTK_ERR_ARG, "every dimension must be >= 2");
+  if (nx > (1 << 30) || ny > 65535 || nz * nt > 65535) return fail(FTK_ERR_ARG, "grid too large (ny and nz * nt <= 65535)");
+  ftk_options o;
+  resolve(opt, &o);
+  ftk_status st = ftk::validate_options(o);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
+  const long long V = nx * ny * nz * nt;
+  unsigned short* emask = sc.get<unsigned short>((size_t)V);
+  unsigned long long* tmask = sc.get<unsigned long long>((size_t)V);
+  int* cnt = sc.get<int>((size_t)V);
+  long long* hoff = sc.get<long long>((size_t)V);
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(V));
+  Ctl* dctl = sc.get<Ctl>(1);
+  if (!emask || !tmask || !cnt || !hoff || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  const float qscale = std::ldexp(1.0f, o.quant_log2);
+  HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+  HIP_TRY(ftk::launch_vx_detect(psi, (int)nx, (int)ny, (int)nz, (int)nt, qscale, emask, tmask, cnt, &dctl->status, s));
+  HIP_TRY(ftk::launch_scan(cnt, hoff, V, &dctl->total, tmp, s));
+  Ctl h;
+  st = read_ctl(&h, dctl, s);
+  if (st) return st;
+  st = decode_status(h.status);
+  if (st) return st;
+  const long long nh = h.total;
+  if (nh >= 0xffffffffll) return fail(FTK_ERR_CAPACITY, "%lld positive triangles exceed the 32-bit union-find", nh);
+  ftk_vortex_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.n_hits = nh;
+  r.tri_id = (int64_t*)al.get(sizeof(int64_t) * (size_t)(nh > 0 ? nh : 1));
+  r.pos = (float*)al.get(sizeof(float) * 4 * (size_t)(nh > 0 ? nh : 1));
+  r.label = (int64_t*)al.get(sizeof(int64_t) * (size_t)(nh > 0 ? nh : 1));
+  unsigned* parent = sc.get<unsigned>((size_t)(nh > 0 ? nh : 1));
+  if (!r.tri_id || !r.pos || !r.label || !parent) {
+    ftk_vortex_result_free(&r, opt, stream);
+    return fail(FTK_ERR_OOM, "output allocation failed");
+  }
+  hipError_t he = hipSuccess;
+  if (nh > 0) {
+    he = ftk::launch_vx_emit(psi, (int)nx, (int)ny, (int)nz, (int)nt, qscale, tmask, hoff, (long long*)r.tri_id, r.pos,
+                             parent, s);
+    if (he == hipSuccess)
+      he = ftk::launch_uf_label(parent, (const long long*)r.tri_id, (long long*)r.label, nh, dctl->cnt, s);
+  }
+  if (he != hipSuccess) {
+    ftk_vortex_result_free(&r, opt, stream);
+    return fail(FTK_ERR_HIP, "kernel launch: %s", hipGetErrorString(he));
+  }
+  st = read_ctl(&h, dctl, s);
+  if (!st) st = decode_status(h.status);
+  if (st) {
+    ftk_vortex_result_free(&r, opt, stream);
+    return st;
+  }
+  r.n_components = (long long)h.cnt[ftk::CNT_TRAJ];
+  *out = r;
+  return FTK_OK;
+}
+
 void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream) {
   if (!p) return;
   ftk_options o;

@@ -146,6 +146,13 @@ hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, floa
                             long long n_active, const unsigned short* emask, const long long* hoff, const int* tcnt,
                             const long long* toff, unsigned* parent, long long* tets, unsigned* status,
                             hipStream_t s);
+// Quantum vortex surfaces (vortex.hip): edge signs and positive-triangle masks (tmask, 50 bits) with per-vertex
+// counts; then emission of triangle ids, points and identity parents, and the pentachoron unions.  Grids as iso.
+hipError_t launch_vx_detect(const float* psi, int nx, int ny, int nz, int nt, float qscale, unsigned short* emask,
+                            unsigned long long* tmask, int* cnt, unsigned* status, hipStream_t s);
+hipError_t launch_vx_emit(const float* psi, int nx, int ny, int nz, int nt, float qscale,
+                          const unsigned long long* tmask, const long long* hoff, long long* tri_id, float* pos,
+                          unsigned* parent, hipStream_t s);
 // Type smoothing and run simplification along an order (head/heads: [n_hits] int / int64 scratch).
 hipError_t launch_smooth(const long long* order, const long long* offsets, const int* n_ends, long long n_traj,
                          long long n_hits, const uint8_t* type_in, int half, int* head, long long* heads,

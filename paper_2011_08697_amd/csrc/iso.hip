@@ -19,6 +19,7 @@
 #include "common.h"
 #include "internal.h"
 #include "kuhn.h"
+#include "uf_cached.h"
 
 namespace ftk {
 
@@ -165,23 +166,6 @@ __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned sho
     parent[o] = (unsigned)o;
     ++o;
   }
-}
-
-// Unite for this pass, where most pairs are already connected: first a find through plain (cached, possibly stale)
-// loads.  A stale parent is still an ancestor and sets only merge, so equal roots mean the pair is connected now;
-// otherwise the coherent path (uf_unite) decides.
-__device__ __forceinline__ unsigned uf_find_cached(const unsigned* parent, unsigned x) {
-  unsigned p = parent[x];
-  while (p != x) {
-    x = p;
-    p = parent[x];
-  }
-  return x;
-}
-
-__device__ __forceinline__ void uf_unite_cached(unsigned* parent, unsigned a, unsigned b) {
-  if (uf_find_cached(parent, a) == uf_find_cached(parent, b)) return;
-  uf_unite(parent, a, b);
 }
 
 __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* __restrict__ active,

@@ -261,6 +261,35 @@ def spiral_woven(size, nt, extent, dt):
 
 
 # Named workloads (sizes of the paper-shaped synthetic configurations).
+def random_waves_3d(nx, ny, nz, nt, K=8, wavelength=(6.0, 16.0), period=(6.0, 20.0), seed=6):
+    """Complex 3D series whose real and imaginary parts are independent sums of K random cosine waves each
+    (directions uniform on the sphere, wavelengths and periods in the given ranges, amplitudes U(0.5, 1.5), phases
+    uniform); their common zero set is a tangle of moving vortex lines.  Returns float32 [nt][2][nz][ny][nx] (real
+    and imaginary planes), evaluated in float64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = np.arange(nx, dtype=np.float64)
+    Y = np.arange(ny, dtype=np.float64)
+    Z = np.arange(nz, dtype=np.float64)
+    waves = []
+    for part in range(2):
+        d = rng.normal(size=(K, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        kv = d * (2 * np.pi / rng.uniform(*wavelength, size=K))[:, None]
+        w = 2 * np.pi / rng.uniform(*period, size=K)
+        amp = rng.uniform(0.5, 1.5, size=K)
+        phi = rng.uniform(0, 2 * np.pi, size=K)
+        waves.append((kv, w, amp, phi))
+    out = np.zeros((nt, 2, nz, ny, nx), np.float32)
+    for t in range(nt):
+        for part, (kv, w, amp, phi) in enumerate(waves):
+            acc = np.zeros((nz, ny, nx))
+            for k in range(K):
+                acc += amp[k] * np.cos(kv[k, 2] * Z[:, None, None] + kv[k, 1] * Y[None, :, None]
+                                       + kv[k, 0] * X[None, None, :] - w[k] * t + phi[k])
+            out[t, part] = acc
+    return out
+
+
 WORKLOAD_PARAMS = {
     "blobs64": dict(n=2, kind=0, dims=(64, 64, 10), K=8, seed=0),
     "noise1024": dict(n=2, kind=0, dims=(1024, 1024, 100), K=256, seed=1, noise_std=1e-3),

@@ -1,0 +1,101 @@
+"""GPU parity of vortex surface tracking (ftk_track_vortex3d through the C ABI) against the oracle
+(oracle/vortex.py): triangle ids, labels and surface counts bit-exact, vortex points within 1e-5 relative; errors;
+and a sampled check of a larger random-wave series against the oracle's per-triangle predicate."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import vortex as Vx
+from paper_2011_08697_amd import synth
+from parity import assert_pos_close
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2011_08697_amd as F  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def _field(nx, ny, nz, nt, fn):
+    X, Y, Z, T = np.meshgrid(np.arange(nx, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                             np.arange(nz, dtype=np.float64), np.arange(nt, dtype=np.float64), indexing="ij")
+    re, im = fn(X, Y, Z, T)
+    return np.stack([np.transpose(re, (3, 2, 1, 0)), np.transpose(im, (3, 2, 1, 0))], 1).astype(np.float32)
+
+
+def _run(psi):
+    g = F.track_vortex3d(torch.from_numpy(np.ascontiguousarray(psi)).to(DEV))
+    torch.cuda.synchronize()
+    return g
+
+
+CASES = {
+    "moving_line": lambda: _field(9, 9, 4, 5, lambda X, Y, Z, T: (X - 4.3 - 0.5 * T, Y - 3.6 + 0.25 * T)),
+    "tied_0": lambda: np.random.default_rng(0).integers(-1, 2, size=(3, 2, 3, 4, 4)).astype(np.float32) / 2 ** 20,
+    "tied_1": lambda: np.random.default_rng(1).integers(-1, 2, size=(4, 2, 3, 3, 5)).astype(np.float32) / 2 ** 20,
+    "waves": lambda: synth.random_waves_3d(12, 10, 8, 4),
+    "waves_ragged": lambda: synth.random_waves_3d(131, 5, 3, 3, seed=8),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_matches_oracle(case):
+    psi = CASES[case]()
+    g = _run(psi)
+    o = Vx.track_vortex(psi)
+    assert g["n_hits"] == o.n_hits and g["n_components"] == o.n_components
+    assert np.array_equal(g["tri_id"].cpu().numpy(), o.tri_id)
+    assert np.array_equal(g["label"].cpu().numpy(), o.label)
+    assert_pos_close(g["pos"].cpu().numpy(), o.pos)
+
+
+def test_counts_and_errors():
+    assert F.triangle_count((5, 6, 7, 8)) == sum(
+        np.prod([d - (((int(a) | int(b)) >> k) & 1) for k, d in enumerate((5, 6, 7, 8))]) for a, b in O.kuhn_types(4, 2))
+    g = _run(np.ones((3, 2, 3, 4, 5), np.float32))
+    assert g["n_hits"] == 0 and g["n_components"] == 0
+    bad = np.ones((3, 2, 3, 4, 5), np.float32)
+    bad[1, 0, 1, 2, 3] = np.nan
+    with pytest.raises(F.FtkError):
+        _run(bad)
+    with pytest.raises(F.FtkError):
+        _run(np.full((3, 2, 3, 4, 5), 1e4, np.float32))  # 1e4 * 2^20 reaches 2^31
+    with pytest.raises(ValueError):
+        F.track_vortex3d(torch.zeros((3, 3, 3, 4, 5), device=DEV))
+
+
+def test_large_series_sampled():
+    """128 x 96 x 64 x 8 random-wave series: sampled positive triangles re-tested with the oracle's predicate on the
+    host-quantised values, their points against the exact barycentric formula, and ids ascending."""
+    psi = synth.random_waves_3d(128, 96, 64, 8, seed=11)
+    g = _run(psi)
+    nh = g["n_hits"]
+    assert nh > 10000 and g["n_components"] > 0
+    tid = g["tri_id"]
+    assert bool((tid[1:] > tid[:-1]).all())
+    q = Vx.quantise(psi)
+    types = O.kuhn_types(4, 2)
+    nt, _, nz, ny, nx = psi.shape
+    rng = np.random.default_rng(2)
+    ks = rng.integers(0, nh, size=1500)
+    ids = tid[ks].cpu().numpy()
+    pos = g["pos"][ks].cpu().numpy()
+    want = []
+    for e in ids:
+        ty, gv = int(e % 50), int(e // 50)
+        c = [gv % nx, (gv // nx) % ny, (gv // (nx * ny)) % nz, gv // (nx * ny * nz)]
+        a, b = int(types[ty][0]), int(types[ty][0]) | int(types[ty][1])
+        P = [c, [c[k] + ((a >> k) & 1) for k in range(4)], [c[k] + ((b >> k) & 1) for k in range(4)]]
+        V = np.array([q[p[3], p[2], p[1], p[0]] for p in P])
+        assert O.face_punctured(V)
+        C = [int(V[1][0]) * int(V[2][1]) - int(V[1][1]) * int(V[2][0]),
+             -(int(V[0][0]) * int(V[2][1]) - int(V[0][1]) * int(V[2][0])),
+             int(V[0][0]) * int(V[1][1]) - int(V[0][1]) * int(V[1][0])]
+        D = sum(C)
+        mu = [1 / 3] * 3 if D == 0 else [x / D for x in C]
+        want.append(sum(m * np.array(p, float) for m, p in zip(mu, P)))
+    assert_pos_close(pos, np.array(want))
