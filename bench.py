@@ -29,6 +29,8 @@ WORKLOADS = {
     "vortex4096": "2D vector 4096x4096x50, 1024 moving sources/sinks/vortices, seed 4",
     "batch96": "96 uneven 2D scalar series (nx, ny log-uniform 128-2048, 8-64 steps), seeds 3+i; batched vs plain",
     "iso_blobs3d256": "isovolume f = 0.5 of the 3D scalar 256x256x256x16 blob series (512 moving Gaussians, seed 2)",
+    "vortex_waves512": "vortex surfaces of a 3D complex 512x128x64x8 series (independent random cosine waves for the "
+                       "real and imaginary parts, 8 each, seed 6)",
 }
 
 
@@ -225,6 +227,64 @@ def bench_iso(args, F, synth, dev):
     print(json.dumps(line), flush=True)
 
 
+def bench_vortex(args, F, synth, dev):
+    """Vortex surface tracking of a random-wave complex series at the grid shape of the paper's superconductivity
+    case: K calls of ftk_track_vortex3d on the resident series; value = spacetime triangles tested per second."""
+    import numpy as np
+    import torch
+    psi_np = synth.random_waves_3d(512, 128, 64, 8, seed=6)
+    psi = torch.from_numpy(psi_np).to(dev)
+    nt, _, nz, ny, nx = psi.shape
+    dims = (nx, ny, nz, nt)
+    L = F.lib()
+    sh = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    pool = F._TorchPool(dev)
+    opt = F._options(pool)
+
+    def one():
+        r = F.VortexResult()
+        st = L.ftk_track_vortex3d(ctypes.c_void_p(psi.data_ptr()), nx, ny, nz, nt, ctypes.byref(opt), sh,
+                                  ctypes.byref(r))
+        if st != 0:
+            raise F.FtkError(st, F.last_error())
+        out = (int(r.n_hits), int(r.n_components))
+        L.ftk_vortex_result_free(ctypes.byref(r), ctypes.byref(opt), sh)
+        return out
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nh, ncomp = one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    tris = F.triangle_count(dims)
+    V = int(np.prod(dims))
+    alg = 8 * V + 32 * nh  # complex field in (two binary32 per vertex); id 8 B, point 16 B, label 8 B per positive
+    line = {
+        "metric": "spacetime triangles tested/s (vortex surface tracking)", "value": round(tris / (ms * 1e-3), 1),
+        "unit": "triangles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["vortex_waves512"], "dims": list(dims), "n_hits": nh,
+                   "n_components": ncomp, "triangles_per_step": tris},
+        "roofline": {"bound": "hbm", "kernel": "whole call", "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import vortex as OV
+        sample = np.ascontiguousarray(psi_np[:2, :, :6, :10, :12])
+        t0 = time.perf_counter()
+        OV.track_vortex(sample)
+        cpu_s = time.perf_counter() - t0
+        st_ = F.triangle_count((12, 10, 6, 2))
+        line["cpu_baseline"] = {"value": round(st_ / cpu_s, 1), "unit": "triangles/s", "cores": 1, "kind": "oracle",
+                                "sample": f"12x10x6x2 corner of the same series ({st_} triangles, python, {cpu_s:.1f} s)"}
+    print(json.dumps(line), flush=True)
+
+
 def post_report(F, field, n, kind, dims, reps=2):
     """Wall time of each trajectory post-processing call on this workload's result (after the timed region; not part
     of value): table, slice at the middle step, loop filter, order, smoothing (half window 2), simplification."""
@@ -277,6 +337,8 @@ def main():
         return bench_batched(args, F, synth, dev)
     if wl == "iso_blobs3d256":
         return bench_iso(args, F, synth, dev)
+    if wl == "vortex_waves512":
+        return bench_vortex(args, F, synth, dev)
     n = 3 if wl == "blobs3d256" else 2
     kind = 1 if wl == "vortex4096" else 0
     t0 = time.time()
