@@ -14,7 +14,8 @@
 //               b = M1 | M2): signs S01, S02 from the vertex's own edges, S12 from the edge (b ^ a) of p + e(a);
 //               positive iff S12 == S01 and S02 != S01 (cofactor signs +S12, -S02, +S01 agree).
 //   vx_emit  -- triangle ids g * 50 + type, the vortex point from the exact cofactors (Eq. 2), identity parents.
-//   vx_unite -- per pentachoron: unite its positive triangle sides (3, 4 or 5 under the perturbation).
+//   vx_unite -- per 4-cube: the positive sides of its pentachora (3, 4 or 5 per pentachoron under the
+//               perturbation) united group by group.
 // Labels (smallest triangle id of each surface) come from the shared union-find label kernel.
 #include "common.h"
 #include "internal.h"
@@ -168,23 +169,64 @@ __global__ __launch_bounds__(kVxBX) void vx_emit(VxGrid g, const unsigned long l
   }
 }
 
-// chain corners of the 24 pentachoron types
-struct VxPen {
-  unsigned char c[24][5];
+// The triangles of a 4-cube's pentachora are its 110 corner chains ci < cj < ck (sets ordered by inclusion); local
+// index k lists them in lexicographic order of (ci, cj, ck), with the anchor corner ci and the triangle type of
+// masks (cj ^ ci, ck ^ cj); side[pt] is the 110-bit set (two words) of the 10 sides of pentachoron type pt.
+constexpr int kCubeTriN = 110;
+struct CubeTris {
+  unsigned char ci[kCubeTriN], ty[kCubeTriN];
+  unsigned long long side[24][2];
 };
-constexpr VxPen build_vx_pen() {
-  VxPen r{};
-  for (int ty = 0; ty < 24; ++ty) {
-    int acc = 0;
-    r.c[ty][0] = 0;
-    for (int k = 0; k < 4; ++k) {
-      acc |= kPen3.m[ty][k];
-      r.c[ty][k + 1] = (unsigned char)acc;
-    }
+constexpr CubeTris build_cube_tris() {
+  CubeTris r{};
+  int cj_of[kCubeTriN] = {}, ck_of[kCubeTriN] = {};
+  int n = 0;
+  for (int ci = 0; ci < 16; ++ci)
+    for (int cj = 0; cj < 16; ++cj)
+      for (int ck = 0; ck < 16; ++ck) {
+        const bool chain = cj != ci && (cj & ci) == ci && ck != cj && (ck & cj) == cj;
+        if (!chain || n >= kCubeTriN) continue;
+        r.ci[n] = (unsigned char)ci;
+        r.ty[n] = (unsigned char)kTri3Index.idx[cj ^ ci][ck ^ cj];
+        cj_of[n] = cj;
+        ck_of[n] = ck;
+        ++n;
+      }
+  for (int pt = 0; pt < 24; ++pt) {
+    int c[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) c[k + 1] = c[k] | kPen3.m[pt][k];
+    for (int i = 0; i < 3; ++i)
+      for (int j = i + 1; j < 4; ++j)
+        for (int k = j + 1; k < 5; ++k)
+          for (int l = 0; l < kCubeTriN; ++l)
+            if (r.ci[l] == c[i] && cj_of[l] == c[j] && ck_of[l] == c[k]) r.side[pt][l >> 6] |= 1ull << (l & 63);
   }
   return r;
 }
-__constant__ VxPen kVxPen = build_vx_pen();
+constexpr int count_chains() {
+  int n = 0;
+  for (int ci = 0; ci < 16; ++ci)
+    for (int cj = 0; cj < 16; ++cj)
+      for (int ck = 0; ck < 16; ++ck) n += cj != ci && (cj & ci) == ci && ck != cj && (ck & cj) == cj;
+  return n;
+}
+static_assert(count_chains() == kCubeTriN, "110 corner chains (triangles) per 4-cube");
+__constant__ CubeTris kCubeTris = build_cube_tris();
+
+// Per 4-cube (anchor p with the whole cube in the grid): its positive triangles P (local set), grouped by "sides of a
+// common pentachoron" (grow a group from its lowest member through the side sets until it is stable); each group
+// member is united once with the group's first member.  Same connectivity as uniting the positive sides of every
+// pentachoron, with |P| - groups unions instead of one star per pentachoron.
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ u128 side_set(int pt) {
+  return ((u128)kCubeTris.side[pt][1] << 64) | (u128)kCubeTris.side[pt][0];
+}
+
+__device__ __forceinline__ int low_bit(u128 m) {
+  const unsigned long long lo = (unsigned long long)m;
+  return lo ? __ffsll((long long)lo) - 1 : 64 + __ffsll((long long)(unsigned long long)(m >> 64)) - 1;
+}
 
 __global__ __launch_bounds__(kVxBX) void vx_unite(VxGrid g, const unsigned long long* __restrict__ tmask,
                                                    const long long* __restrict__ hoff, unsigned* __restrict__ parent) {
@@ -192,7 +234,7 @@ __global__ __launch_bounds__(kVxBX) void vx_unite(VxGrid g, const unsigned long 
   const int y = blockIdx.y;
   const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
   if (x >= g.nx || x + 1 >= g.nx || y + 1 >= g.ny || z + 1 >= g.nz || t + 1 >= g.nt) return;
-  // triangle sides of the cube's pentachora are anchored at chain corners with at most two axes
+  // triangle sides are anchored at chain corners with at most two axes
   unsigned long long tm[16];
   unsigned long long any = 0;
 #pragma unroll
@@ -203,22 +245,34 @@ __global__ __launch_bounds__(kVxBX) void vx_unite(VxGrid g, const unsigned long 
     any |= tm[a];
   }
   if (!any) return;
-  for (int pt = 0; pt < 24; ++pt) {
-    long long first = -1;
-    for (int i = 0; i < 3; ++i)
-      for (int j = i + 1; j < 4; ++j)
-        for (int k = j + 1; k < 5; ++k) {
-          const unsigned ci = kVxPen.c[pt][i], cj = kVxPen.c[pt][j], ck = kVxPen.c[pt][k];
-          const int ty = kTri3Index.idx[cj ^ ci][ck ^ cj];
-          const unsigned long long mk = tm[ci];
-          if (!((mk >> ty) & 1ull)) continue;
-          const long long w = vx_vidx(g, x + (ci & 1u), y + ((ci >> 1) & 1u), z + ((ci >> 2) & 1u), t + ((ci >> 3) & 1u));
-          const long long h = hoff[w] + __popcll(mk & ((1ull << ty) - 1ull));
-          if (first < 0)
-            first = h;
-          else
-            uf_unite_cached(parent, (unsigned)first, (unsigned)h);
-        }
+  u128 P = 0;
+  for (int k = 0; k < kCubeTriN; ++k)
+    if ((tm[kCubeTris.ci[k]] >> kCubeTris.ty[k]) & 1ull) P |= (u128)1 << k;
+  auto hit = [&](int k) -> long long {
+    const unsigned a = kCubeTris.ci[k];
+    const int ty = kCubeTris.ty[k];
+    const long long w = vx_vidx(g, x + (a & 1u), y + ((a >> 1) & 1u), z + ((a >> 2) & 1u), t + ((a >> 3) & 1u));
+    return hoff[w] + __popcll(tm[a] & ((1ull << ty) - 1ull));
+  };
+  u128 R = P;
+  while (R) {
+    u128 C = (u128)1 << low_bit(R), prev;
+    do {
+      prev = C;
+      for (int pt = 0; pt < 24; ++pt) {
+        const u128 S = side_set(pt) & P;
+        if (S & C) C |= S;
+      }
+    } while (C != prev);
+    R &= ~C;
+    const int k0 = low_bit(C);
+    const long long h0 = hit(k0);
+    C &= ~((u128)1 << k0);
+    while (C) {
+      const int k = low_bit(C);
+      C &= ~((u128)1 << k);
+      uf_unite_cached(parent, (unsigned)h0, (unsigned)hit(k));
+    }
   }
 }
 
