@@ -11,10 +11,11 @@
 //                its side, 1 tetrahedron; case II: two, 3 tetrahedra).
 //   iso_emit  -- edge ids and intersection points p + mu e(M), mu = (c - f(p)) / (f(q) - f(p)), from the scanned
 //                counts; union-find parents start as the identity.
-//   iso_unite -- per pentachoron with crossings: unite its crossed edges (CAS hooking, larger root under the
-//                smaller), and write its tetrahedra (indices of crossed edges): case I the four edges of the lone
-//                vertex in chain order; case II the prism pair x triple split along the three monotone paths
-//                (staircase), which matches on the quadrilateral shared with the neighbouring pentachoron.
+//   iso_unite -- per 4-cube with crossings (compacted list): unite its crossed edges group by group (CAS hooking,
+//                larger root under the smaller), and per pentachoron write its tetrahedra (indices of crossed
+//                edges): case I the four edges of the lone vertex in chain order; case II the prism pair x triple
+//                split along the three monotone paths (staircase), which matches on the quadrilateral shared with
+//                the neighbouring pentachoron.
 // Labels (smallest edge id of each isovolume) come from the shared union-find label kernel.
 #include "common.h"
 #include "internal.h"
@@ -45,9 +46,14 @@ constexpr PenCorners build_pen_corners() {
 }
 __constant__ PenCorners kPenDev = build_pen_corners();
 
-// Local index (0..64) of the edge between cube corners a and a | M (a & M == 0, M != 0), 255 otherwise.
+// The edges of a 4-cube's pentachora are its 65 corner pairs a < a | M (a & M == 0, M != 0).  idx[a][M] is the local
+// index (255 for no edge), ea / eM its anchor corner and mask, side[pt] the 65-bit set (two words) of the 10 edges of
+// pentachoron type pt.
+constexpr int kCubeEdgeN = 65;
 struct CubeEdges {
   unsigned char idx[16][16];
+  unsigned char ea[kCubeEdgeN], eM[kCubeEdgeN];
+  unsigned long long side[24][2];
 };
 constexpr CubeEdges build_cube_edges() {
   CubeEdges r{};
@@ -56,10 +62,42 @@ constexpr CubeEdges build_cube_edges() {
     for (int M = 0; M < 16; ++M) r.idx[a][M] = 255;
   for (int a = 0; a < 16; ++a)
     for (int M = 1; M < 16; ++M)
-      if (!(a & M)) r.idx[a][M] = (unsigned char)k++;
+      if (!(a & M) && k < kCubeEdgeN) {
+        r.idx[a][M] = (unsigned char)k;
+        r.ea[k] = (unsigned char)a;
+        r.eM[k] = (unsigned char)M;
+        ++k;
+      }
+  for (int pt = 0; pt < 24; ++pt) {
+    int c[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < 4; ++i) c[i + 1] = c[i] | kPen3.m[pt][i];
+    for (int i = 0; i < 5; ++i)
+      for (int j = i + 1; j < 5; ++j) {
+        const int l = r.idx[c[i]][c[j] ^ c[i]];
+        r.side[pt][l >> 6] |= 1ull << (l & 63);
+      }
+  }
   return r;
 }
+constexpr int count_cube_edges() {
+  int k = 0;
+  for (int a = 0; a < 16; ++a)
+    for (int M = 1; M < 16; ++M) k += !(a & M);
+  return k;
+}
+static_assert(count_cube_edges() == kCubeEdgeN, "65 corner pairs (edges) per 4-cube");
 __constant__ CubeEdges kCubeEdges = build_cube_edges();
+
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ u128 edge_side_set(int pt) {
+  return ((u128)kCubeEdges.side[pt][1] << 64) | (u128)kCubeEdges.side[pt][0];
+}
+
+__device__ __forceinline__ int low_bit128(u128 m) {
+  const unsigned long long lo = (unsigned long long)m;
+  return lo ? __ffsll((long long)lo) - 1 : 64 + __ffsll((long long)(unsigned long long)(m >> 64)) - 1;
+}
 
 struct IsoGrid {
   const float* f;
@@ -195,12 +233,46 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* 
   }
   long long o = toff[v];
   const long long o_end = o + tcnt[v];
-  // When the cube's diagonal (corner 0 to corner 1111) crosses, it is a crossed edge of all 24 pentachora, so the
-  // cube's crossed edges form one set: each is united once with the diagonal.  Otherwise each pentachoron unites
-  // its own crossed edges.
-  const bool diag = ((above ^ (above >> 15)) & 1u) != 0u;
-  const long long dhit = cb[0] + __popc(cm_mask[0] & ((1u << 14) - 1u));
-  unsigned long long seen0 = 0, seen1 = 0;
+  // Unions: the cube's crossed edges P (local set) grouped by "edges of a common pentachoron" (a group grows from
+  // its lowest member through the side sets until it is stable); each member is united once with the group's first.
+  // Same connectivity as uniting the crossed edges of every pentachoron, with |P| - groups unions.
+  {
+    u128 P = 0;
+    for (int k = 0; k < kCubeEdgeN; ++k) {
+      const unsigned a = kCubeEdges.ea[k], b = a | kCubeEdges.eM[k];
+      if (((above >> a) ^ (above >> b)) & 1u) {
+        if (!((cm_mask[a] >> (kCubeEdges.eM[k] - 1)) & 1u)) {  // the count pass took the same decisions
+          atomicOr(status, ST_INVARIANT);
+          return;
+        }
+        P |= (u128)1 << k;
+      }
+    }
+    auto hit = [&](int k) -> long long {
+      const unsigned a = kCubeEdges.ea[k], M = kCubeEdges.eM[k];
+      return cb[a] + __popc(cm_mask[a] & ((1u << (M - 1)) - 1u));
+    };
+    u128 R = P;
+    while (R) {
+      u128 C = (u128)1 << low_bit128(R), prev;
+      do {
+        prev = C;
+        for (int pt = 0; pt < 24; ++pt) {
+          const u128 S = edge_side_set(pt) & P;
+          if (S & C) C |= S;
+        }
+      } while (C != prev);
+      R &= ~C;
+      const int k0 = low_bit128(C);
+      const long long h0 = hit(k0);
+      C &= ~((u128)1 << k0);
+      while (C) {
+        const int k = low_bit128(C);
+        C &= ~((u128)1 << k);
+        uf_unite_cached(parent, (unsigned)h0, (unsigned)hit(k));
+      }
+    }
+  }
   for (int ty = 0; ty < 24; ++ty) {
     unsigned ch[5];
     int k = 0;
@@ -241,28 +313,7 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* 
       atomicOr(status, ST_INVARIANT);
       return;
     }
-    // the crossed edges are exactly the (minority, majority) pairs
-    if (diag) {
-      for (int p = 0; p < nm; ++p)
-        for (int q = 0; q < na; ++q) {
-          const int i = min(mi[p], ma[q]), j = max(mi[p], ma[q]);
-          const unsigned li = kCubeEdges.idx[ch[i]][ch[j] ^ ch[i]];
-          const unsigned long long bit = 1ull << (li & 63u);
-          const bool seen = li < 64u ? (seen0 & bit) != 0 : (seen1 & bit) != 0;
-          if (seen) continue;
-          if (li < 64u)
-            seen0 |= bit;
-          else
-            seen1 |= bit;
-          const long long e = pe(p, q);
-          if (e != dhit) uf_unite_cached(parent, (unsigned)dhit, (unsigned)e);
-        }
-    } else {
-      const long long e0 = pe(0, 0);
-      for (int p = 0; p < nm; ++p)
-        for (int q = 0; q < na; ++q)
-          if (p | q) uf_unite_cached(parent, (unsigned)e0, (unsigned)pe(p, q));
-    }
+    // tetrahedra of the crossed edges (the (minority, majority) pairs)
     const int nt_here = nm == 1 ? 1 : 3;
     if (o + nt_here > o_end) {
       atomicOr(status, ST_INVARIANT);
