@@ -77,3 +77,43 @@ def test_argument_errors_are_reported_before_any_device_work():
 def test_result_free_of_empty_result_is_safe():
     r = F.Result()
     F.lib().ftk_result_free(ctypes.byref(r), None, None)
+
+
+def _brute_count(dims, types):
+    """Anchors whose whole simplex lies in the grid, summed over the types (direct enumeration)."""
+    import itertools
+    tot = 0
+    for masks in types:
+        used = 0
+        for m in masks:
+            used |= int(m)
+        for c in itertools.product(*[range(d) for d in dims]):
+            tot += all(c[a] + ((used >> a) & 1) < dims[a] for a in range(len(dims)))
+    return tot
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (3, 4, 2, 5), (5, 3, 3, 2)])
+def test_edge_and_triangle_counts(dims):
+    arr = (ctypes.c_int64 * 4)(*dims)
+    L = F.lib()
+    assert L.ftk_edge_count(arr) == _brute_count(dims, [[m] for m in range(1, 16)])
+    assert L.ftk_triangle_count(arr) == _brute_count(dims, O.kuhn_types(4, 2))
+    bad = (ctypes.c_int64 * 4)(1, 3, 3, 3)
+    assert L.ftk_edge_count(bad) == -1 and L.ftk_triangle_count(bad) == -1
+
+
+def test_iso_and_vortex_argument_errors():
+    """Host-side checks return before any device work: missing pointers, small or oversized grids."""
+    L = F.lib()
+    o = F.Options()
+    L.ftk_default_options(ctypes.byref(o))
+    ir = F.IsoResult()
+    vr = F.VortexResult()
+    dummy = ctypes.c_void_p(1)
+    assert L.ftk_track_iso3d(None, 4, 4, 4, 4, 0.0, ctypes.byref(o), None, ctypes.byref(ir)) != 0
+    assert L.ftk_track_iso3d(dummy, 1, 4, 4, 4, 0.0, ctypes.byref(o), None, ctypes.byref(ir)) != 0
+    assert L.ftk_track_iso3d(dummy, 4, 70000, 4, 4, 0.0, ctypes.byref(o), None, ctypes.byref(ir)) != 0
+    assert L.ftk_track_iso3d(dummy, 4, 4, 4, 4, float("nan"), ctypes.byref(o), None, ctypes.byref(ir)) != 0
+    assert L.ftk_track_vortex3d(None, 4, 4, 4, 4, ctypes.byref(o), None, ctypes.byref(vr)) != 0
+    assert L.ftk_track_vortex3d(dummy, 4, 4, 300, 300, ctypes.byref(o), None, ctypes.byref(vr)) != 0
+    assert b"dimension" in L.ftk_last_error() or b"large" in L.ftk_last_error()
