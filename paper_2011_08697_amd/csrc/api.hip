@@ -1570,12 +1570,13 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   long long* hoff = sc.get<long long>((size_t)V);
   long long* toff = sc.get<long long>((size_t)V);
   long long* aoff = sc.get<long long>((size_t)V);
+  unsigned long long* bits = sc.get<unsigned long long>((size_t)((nx + 63) / 64) * ny * nz * nt);
   long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(V));
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!emask || !hcnt || !tcnt || !hoff || !toff || !aoff || !tmp || !dctl)
+  if (!emask || !hcnt || !tcnt || !hoff || !toff || !aoff || !bits || !tmp || !dctl)
     return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
-  HIP_TRY(ftk::launch_iso_count(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, emask, hcnt, tcnt,
+  HIP_TRY(ftk::launch_iso_count(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, bits, emask, hcnt, tcnt,
                                 &dctl->status, s));
   HIP_TRY(ftk::launch_scan(hcnt, hoff, V, &dctl->total, tmp, s));
   HIP_TRY(ftk::launch_scan(tcnt, toff, V, (long long*)&dctl->cnt[ftk::CNT_LIST], tmp, s));
@@ -1608,8 +1609,8 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
     if (he == hipSuccess)
       he = ftk::launch_iso_active(tcnt, V, hcnt, aoff, nullptr, nullptr, active, true, s);
     if (he == hipSuccess)
-      he = ftk::launch_iso_unite(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, active, nact, emask, hoff, tcnt,
-                                 toff, parent, (long long*)r.tets, &dctl->status, s);
+      he = ftk::launch_iso_unite(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, bits, active, nact, emask, hoff,
+                                 tcnt, toff, parent, (long long*)r.tets, &dctl->status, s);
     if (he == hipSuccess)
       he = ftk::launch_uf_label(parent, (const long long*)r.edge_id, (long long*)r.label, nh, dctl->cnt, s);
   }

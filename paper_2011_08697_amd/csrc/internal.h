@@ -134,16 +134,18 @@ hipError_t launch_order_place(int n, const int64_t* dims_with_t, const long long
 // Isovolume tracking (iso.hip): per-vertex crossing masks and hit / tetrahedron counts; emission of edge ids,
 // positions and identity parents from the scanned counts; pentachoron unions and tetrahedra over the active
 // vertices.  Per-vertex grids launch as (ceil(nx / 128), ny, nz * nt) blocks (ny, nz * nt <= 65535).
-hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, float c, unsigned short* emask, int* hcnt,
-                            int* tcnt, unsigned* status, hipStream_t s);
+// bits: ceil(nx / 64) * ny * nz * nt words of vertex sides, written by the count launch, read by the unite launch
+hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, float c, unsigned long long* bits,
+                            unsigned short* emask, int* hcnt, int* tcnt, unsigned* status, hipStream_t s);
 hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float c, const unsigned short* emask,
                            const long long* hoff, long long* edge_id, float* pos, unsigned* parent, hipStream_t s);
 // active vertices (a crossed pentachoron in their cube): flags + scan (scatter = false, *total = count), then the
 // ascending list (scatter = true)
 hipError_t launch_iso_active(const int* tcnt, long long V, int* flag, long long* off, long long* total,
                              long long* scan_tmp, long long* list, bool scatter, hipStream_t s);
-hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c, const long long* active,
-                            long long n_active, const unsigned short* emask, const long long* hoff, const int* tcnt,
+hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c,
+                            const unsigned long long* bits, const long long* active, long long n_active,
+                            const unsigned short* emask, const long long* hoff, const int* tcnt,
                             const long long* toff, unsigned* parent, long long* tets, unsigned* status,
                             hipStream_t s);
 // Quantum vortex surfaces (vortex.hip): edge signs and positive-triangle masks (tmask, 50 bits) with per-vertex

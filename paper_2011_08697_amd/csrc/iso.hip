@@ -5,8 +5,9 @@
 // p + e(M); its id is g(p) * 15 + (M - 1) with the t-major vertex index g.  A pentachoron anchored at p with axis
 // order (s1, s2, s3, s4) has the chain vertices p, p + e(s1), p + e(s1|s2), p + e(s1|s2|s3), p + e(1111).
 //
-//   iso_count -- one lane per vertex: the side of the level set at the 16 corners of its unit 4-cube (a value equal
-//                to the isovalue lies above it: the symbolic perturbation of a single entry is positive, Sec. 5.2),
+//   iso_bits  -- the side of the level set of every vertex as one bit, 64 per word (a value equal to the isovalue
+//                lies above it: the symbolic perturbation of a single entry is positive, Sec. 5.2).
+//   iso_count -- one lane per vertex: the sides at the 16 corners of its unit 4-cube (from the bit words),
 //                the crossing mask of its 15 edges, and the tetrahedra of its 24 pentachora (case I: one vertex on
 //                its side, 1 tetrahedron; case II: two, 3 tetrahedra).
 //   iso_emit  -- edge ids and intersection points p + mu e(M), mu = (c - f(p)) / (f(q) - f(p)), from the scanned
@@ -103,27 +104,45 @@ struct IsoGrid {
   const float* f;
   int nx, ny, nz, nt;
   float c;
+  const unsigned long long* bits;  // side of every vertex, one bit per vertex: row-major 64-vertex words
+  int nwx;                         // words per row, ceil(nx / 64)
 };
 
 __device__ __forceinline__ long long vidx(const IsoGrid& g, int x, int y, int z, int t) {
   return (((long long)t * g.nz + z) * g.ny + y) * g.nx + x;
 }
 
+// Side of every vertex as one bit (a value equal to the isovalue counts as above), packed per 64 vertices of a row
+// by a wave ballot: the passes that need the 16 corners of a 4-cube read these words (L2-resident, shared by
+// neighbouring lanes) instead of 16 field values.  Non-finite values are reported here.
+__global__ __launch_bounds__(kIsoBX) void iso_bits(IsoGrid g, unsigned long long* __restrict__ bits,
+                                                    unsigned* __restrict__ status) {
+  const int x = blockIdx.x * kIsoBX + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
+  bool above = false;
+  if (x < g.nx) {
+    const float v = g.f[vidx(g, x, y, z, t)];
+    if (!isfinite(v)) atomicOr(status, ST_NONFINITE);
+    above = v >= g.c;
+  }
+  const unsigned long long w = __ballot(above);
+  if ((threadIdx.x & 63) == 0 && x < g.nx) bits[((long long)blockIdx.z * g.ny + y) * g.nwx + (x >> 6)] = w;
+}
+
 // above bits of the 16 cube corners (bit cm) and their validity (bit cm: corner in the grid)
 __device__ __forceinline__ void corner_bits(const IsoGrid& g, int x, int y, int z, int t, unsigned& above,
-                                            unsigned& valid, float* fv) {
+                                            unsigned& valid) {
   above = 0;
   valid = 0;
 #pragma unroll
   for (int cm = 0; cm < 16; ++cm) {
     const int cx = x + (cm & 1), cy = y + ((cm >> 1) & 1), cz = z + ((cm >> 2) & 1), ct = t + ((cm >> 3) & 1);
-    float v = 0.0f;
     if (cx < g.nx && cy < g.ny && cz < g.nz && ct < g.nt) {
-      v = g.f[vidx(g, cx, cy, cz, ct)];
+      const unsigned long long w = g.bits[(((long long)ct * g.nz + cz) * g.ny + cy) * g.nwx + (cx >> 6)];
       valid |= 1u << cm;
-      above |= (v >= g.c ? 1u : 0u) << cm;
+      above |= (unsigned)((w >> (cx & 63)) & 1ull) << cm;
     }
-    if (fv) fv[cm] = v;
   }
 }
 
@@ -143,8 +162,7 @@ __global__ __launch_bounds__(kIsoBX) void iso_count(IsoGrid g, unsigned short* _
   if (x >= g.nx) return;
   const long long v = vidx(g, x, y, z, t);
   unsigned above, valid;
-  corner_bits(g, x, y, z, t, above, valid, nullptr);
-  if (!isfinite(g.f[v])) atomicOr(status, ST_NONFINITE);
+  corner_bits(g, x, y, z, t, above, valid);
   unsigned m = 0;
 #pragma unroll
   for (int M = 1; M < 16; ++M)
@@ -221,7 +239,7 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* 
   const int t = (int)(v / ((long long)g.nx * g.ny * g.nz));
   if (tcnt[v] == 0) return;
   unsigned above, valid;
-  corner_bits(g, x, y, z, t, above, valid, nullptr);
+  corner_bits(g, x, y, z, t, above, valid);
   // first hit index and crossing mask of every corner that anchors an edge of a pentachoron (all but 1111)
   long long cb[15];
   unsigned cm_mask[15];
@@ -337,16 +355,17 @@ dim3 iso_grid(const IsoGrid& g) { return dim3((unsigned)((g.nx + kIsoBX - 1) / k
 
 }  // namespace
 
-hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, float c, unsigned short* emask, int* hcnt,
-                            int* tcnt, unsigned* status, hipStream_t s) {
-  const IsoGrid g{f, nx, ny, nz, nt, c};
+hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, float c, unsigned long long* bits,
+                            unsigned short* emask, int* hcnt, int* tcnt, unsigned* status, hipStream_t s) {
+  const IsoGrid g{f, nx, ny, nz, nt, c, bits, (nx + 63) / 64};
+  iso_bits<<<iso_grid(g), kIsoBX, 0, s>>>(g, bits, status);
   iso_count<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hcnt, tcnt, status);
   return hipGetLastError();
 }
 
 hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float c, const unsigned short* emask,
                            const long long* hoff, long long* edge_id, float* pos, unsigned* parent, hipStream_t s) {
-  const IsoGrid g{f, nx, ny, nz, nt, c};
+  const IsoGrid g{f, nx, ny, nz, nt, c, nullptr, (nx + 63) / 64};
   iso_emit<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hoff, edge_id, pos, parent);
   return hipGetLastError();
 }
@@ -362,12 +381,13 @@ hipError_t launch_iso_active(const int* tcnt, long long V, int* flag, long long*
   return hipGetLastError();
 }
 
-hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c, const long long* active,
-                            long long n_active, const unsigned short* emask, const long long* hoff, const int* tcnt,
+hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c,
+                            const unsigned long long* bits, const long long* active, long long n_active,
+                            const unsigned short* emask, const long long* hoff, const int* tcnt,
                             const long long* toff, unsigned* parent, long long* tets, unsigned* status,
                             hipStream_t s) {
   if (n_active == 0) return hipSuccess;
-  const IsoGrid g{f, nx, ny, nz, nt, c};
+  const IsoGrid g{f, nx, ny, nz, nt, c, bits, (nx + 63) / 64};
   iso_unite<<<(unsigned)((n_active + kIsoBX - 1) / kIsoBX), kIsoBX, 0, s>>>(g, active, n_active, emask, hoff, tcnt,
                                                                             toff, parent, tets, status);
   return hipGetLastError();
