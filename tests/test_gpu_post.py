@@ -210,3 +210,38 @@ def test_full_size_noise1024_order_properties():
             assert share_a_cell(int(x), int(y), 2, dims)
             checked += 1
     assert checked > 2000
+
+
+def test_full_size_blobs3d256_order_properties():
+    """The order on the full 256^3 x 16 blob result: a permutation grouped by trajectory with the table's offsets,
+    one label per group, paths from their smaller-id end and loops from their label face, consecutive points two
+    sides of one pentachoron (sampled, decoded on the host)."""
+    t = torch.from_numpy(synth.make("blobs3d256", device=DEV)).to(DEV)
+    nt, nz, ny, nx = t.shape
+    dims = (nx, ny, nz, nt)
+    g = F.track_cp3d(t)
+    torch.cuda.synchronize()
+    del t
+    tab = F.trajectory_table(g, dims)
+    order, off = F.trajectory_order(g, dims, tab)
+    nh = g["n_hits"]
+    assert torch.equal(torch.sort(order).values, torch.arange(nh, device=DEV))
+    assert torch.equal(off[1:] - off[:-1], tab["n_points"]) and int(off[-1]) == nh
+    traj = torch.repeat_interleave(torch.arange(tab["n"], device=DEV), tab["n_points"])
+    assert torch.equal(g["label"][order], tab["label"][traj])
+    fid = g["face_id"]
+    first, last = fid[order[off[:-1]]], fid[order[off[1:] - 1]]
+    loop = tab["n_ends"] == 0
+    assert torch.equal(first[loop], tab["label"][loop])
+    assert bool((first[~loop] < last[~loop]).all())
+    rng = np.random.default_rng(6)
+    ks = rng.integers(0, nh - 1, size=2000)
+    same = (traj[ks] == traj[ks + 1]).cpu().numpy()
+    a = fid[order[ks]].cpu().numpy()
+    b = fid[order[ks + 1]].cpu().numpy()
+    checked = 0
+    for x, y, s in zip(a, b, same):
+        if s:
+            assert share_a_cell(int(x), int(y), 3, dims)
+            checked += 1
+    assert checked > 1000
