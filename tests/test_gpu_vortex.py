@@ -99,3 +99,17 @@ def test_large_series_sampled():
         mu = [1 / 3] * 3 if D == 0 else [x / D for x in C]
         want.append(sum(m * np.array(p, float) for m, p in zip(mu, P)))
     assert_pos_close(pos, np.array(want))
+
+
+@pytest.mark.parametrize("qshift", [1, 24])
+def test_other_quantisations_match_oracle(qshift):
+    """A quantum of 1/2 rounds 7% of the components to zero and many more to equal values, so the symbolic
+    perturbation decides many triangles; a fine one (2^-24) keeps every value distinct."""
+    psi = synth.random_waves_3d(14, 9, 6, 3, seed=13)
+    g = F.track_vortex3d(torch.from_numpy(psi).to(DEV), quant_log2=qshift)
+    torch.cuda.synchronize()
+    o = Vx.track_vortex(psi, qshift=qshift)
+    assert g["n_hits"] == o.n_hits and g["n_components"] == o.n_components
+    assert np.array_equal(g["tri_id"].cpu().numpy(), o.tri_id)
+    assert np.array_equal(g["label"].cpu().numpy(), o.label)
+    assert_pos_close(g["pos"].cpu().numpy(), o.pos)
