@@ -290,6 +290,31 @@ def random_waves_3d(nx, ny, nz, nt, K=8, wavelength=(6.0, 16.0), period=(6.0, 20
     return out
 
 
+def delaunay_mesh(n_points, extent=10.0, seed=7):
+    """Unstructured triangle mesh: the Delaunay triangulation of the square's corners and n_points uniform points in
+    [0, extent]^2.  Returns (xy float32 [nv][2], tri int32 [nf][3])."""
+    from scipy.spatial import Delaunay
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = np.concatenate([np.array([[0, 0], [extent, 0], [0, extent], [extent, extent]], np.float64),
+                          rng.uniform(0, extent, size=(n_points, 2))])
+    xy = pts.astype(np.float32)
+    tri = Delaunay(xy.astype(np.float64)).simplices.astype(np.int32)
+    return xy, tri
+
+
+def kuhn_grid_mesh(nx, ny):
+    """The regular nx x ny grid as a triangle mesh (vertex y * nx + x), each cell split along its (0,0)-(1,1)
+    diagonal into the triangles x-then-y and y-then-x."""
+    xy = np.array([(x, y) for y in range(ny) for x in range(nx)], np.float32)
+    tri = []
+    for y in range(ny - 1):
+        for x in range(nx - 1):
+            v = y * nx + x
+            tri.append((v, v + 1, v + nx + 1))
+            tri.append((v, v + nx, v + nx + 1))
+    return xy, np.array(tri, np.int32)
+
+
 WORKLOAD_PARAMS = {
     "blobs64": dict(n=2, kind=0, dims=(64, 64, 10), K=8, seed=0),
     "noise1024": dict(n=2, kind=0, dims=(1024, 1024, 100), K=256, seed=1, noise_std=1e-3),
