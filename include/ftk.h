@@ -318,6 +318,34 @@ void ftk_vortex_result_free(ftk_vortex_result* r, const ftk_options* opt, ftk_st
  * dims_with_t = (nx, ny, nz, nt).  Returns -1 for bad arguments. */
 int64_t ftk_triangle_count(const int64_t* dims_with_t);
 
+/*
+ * Critical-point tracking of a 2D vector field on an unstructured triangle mesh extruded in time (Sec. 3.2,
+ * prismatic subdivision).  xy: device [nv][2] vertex positions; tri: device [nf][3] vertex indices (any order per
+ * row); field: device [nt][2][nv] binary32 vector components per step.  Each triangle v0 < v1 < v2 and step interval
+ * becomes a prism split by the staircase into the tetrahedra a0 a1 a2 b2, a0 a1 b1 b2, a0 b0 b1 b2 (global vertex
+ * order g = t nv + v); the quadrilateral of a mesh edge a < b is split along a - b'.  With the mesh edges sorted
+ * (a < b, ascending) and S = 3 nf + 2 ne faces per step, face ids are t * S + local: the triangle T (local T); the
+ * edge faces (a, b, b') and (a, a', b') of edge E (nf + 2E, +1); the interior faces (v0, v1, v2') and (v0, v1', v2')
+ * of T (nf + 2 ne + 2T, +1).  Faces are tested like the regular path (quantised with opt->quant_log2, SoS); points
+ * are (x, y, t) from the exact barycentric weights; the two punctured faces of every tetrahedron are united, labels
+ * = smallest face id.  No critical-point types (the field's Jacobian on a mesh is out of scope here).  Builds the
+ * mesh topology on the host (tri is copied back), synchronises the stream.  nv >= 3, nf >= 1, 2 <= nt <= 65535;
+ * FTK_ERR_ARG for indices out of range or repeated within a triangle; errors otherwise as ftk_track_cp2d.
+ */
+typedef struct {
+  int64_t n_hits;          /* punctured faces */
+  int64_t n_trajectories;  /* connected components */
+  int64_t faces_per_step;  /* S */
+  int64_t n_edges;         /* ne */
+  int64_t* face_id;        /* [n_hits] ascending */
+  float* pos;              /* [n_hits][3] (x, y, t) */
+  int64_t* label;          /* [n_hits] smallest face id of the trajectory */
+} ftk_mesh_result;
+
+ftk_status ftk_track_cp_mesh2d(const float* xy, int64_t nv, const int32_t* tri, int64_t nf, const float* field,
+                               int64_t nt, const ftk_options* opt, ftk_stream_t stream, ftk_mesh_result* out);
+void ftk_mesh_result_free(ftk_mesh_result* r, const ftk_options* opt, ftk_stream_t stream);
+
 /* Release the device arrays of a result (with the allocator given in opt, which may be NULL). */
 void ftk_result_free(ftk_cp_result* r, const ftk_options* opt, ftk_stream_t stream);
 

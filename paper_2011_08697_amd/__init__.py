@@ -23,7 +23,8 @@ EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_cr
            "ftk_last_error", "ftk_version", "ftk_traj_table_build", "ftk_traj_table_free", "ftk_cp_slice",
            "ftk_cp_filter_loops", "ftk_buffer_free", "ftk_autotune_cp2d", "ftk_traj_order",
            "ftk_traj_smooth_types", "ftk_traj_simplify_types", "ftk_track_iso3d", "ftk_iso_result_free",
-           "ftk_edge_count", "ftk_track_vortex3d", "ftk_vortex_result_free", "ftk_triangle_count"]
+           "ftk_edge_count", "ftk_track_vortex3d", "ftk_vortex_result_free", "ftk_triangle_count",
+           "ftk_track_cp_mesh2d", "ftk_mesh_result_free"]
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -67,6 +68,12 @@ class IsoResult(ctypes.Structure):
 class VortexResult(ctypes.Structure):
     _fields_ = [("n_hits", ctypes.c_int64), ("n_components", ctypes.c_int64), ("tri_id", ctypes.c_void_p),
                 ("pos", ctypes.c_void_p), ("label", ctypes.c_void_p)]
+
+
+class MeshResult(ctypes.Structure):
+    _fields_ = [("n_hits", ctypes.c_int64), ("n_trajectories", ctypes.c_int64), ("faces_per_step", ctypes.c_int64),
+                ("n_edges", ctypes.c_int64), ("face_id", ctypes.c_void_p), ("pos", ctypes.c_void_p),
+                ("label", ctypes.c_void_p)]
 
 
 class TrajTable(ctypes.Structure):
@@ -134,6 +141,11 @@ def lib():
         L.ftk_vortex_result_free.restype = None
         L.ftk_triangle_count.argtypes = [ctypes.POINTER(i64)]
         L.ftk_triangle_count.restype = i64
+        L.ftk_track_cp_mesh2d.argtypes = [vp, i64, vp, i64, vp, i64, ctypes.POINTER(Options), vp,
+                                          ctypes.POINTER(MeshResult)]
+        L.ftk_track_cp_mesh2d.restype = ctypes.c_int
+        L.ftk_mesh_result_free.argtypes = [ctypes.POINTER(MeshResult), ctypes.POINTER(Options), vp]
+        L.ftk_mesh_result_free.restype = None
         L.ftk_traj_order.argtypes = [ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(i64),
                                      ctypes.POINTER(TrajTable), ctypes.POINTER(Options), vp, vp, vp]
         L.ftk_traj_order.restype = ctypes.c_int
@@ -431,6 +443,30 @@ def track_vortex3d(psi, **opts):
     return dict(n_hits=nh, n_components=int(r.n_components),
                 tri_id=pool.take(r.tri_id, torch.int64, (max(nh, 1),))[:nh],
                 pos=pool.take(r.pos, torch.float32, (max(nh, 1), 4))[:nh],
+                label=pool.take(r.label, torch.int64, (max(nh, 1),))[:nh])
+
+
+def track_cp_mesh2d(xy, tri, field, **opts):
+    """Critical points of a 2D vector field on a triangle mesh extruded in time: xy float32 [nv][2], tri int32
+    [nf][3], field float32 [nt][2][nv], all contiguous CUDA tensors.  Returns punctured faces (face_id ascending, pos
+    [n][3] as x, y, t), labels, n_trajectories, faces_per_step and n_edges."""
+    import torch
+    ok = (xy.is_cuda and tri.is_cuda and field.is_cuda and xy.dtype == torch.float32 and tri.dtype == torch.int32
+          and field.dtype == torch.float32 and xy.is_contiguous() and tri.is_contiguous() and field.is_contiguous()
+          and xy.dim() == 2 and xy.shape[1] == 2 and tri.dim() == 2 and tri.shape[1] == 3 and field.dim() == 3
+          and field.shape[1] == 2 and field.shape[2] == xy.shape[0])
+    if not ok:
+        raise ValueError("need contiguous CUDA tensors xy float32 [nv][2], tri int32 [nf][3], field float32 [nt][2][nv]")
+    pool = _TorchPool(xy.device)
+    o = _options(pool, **opts)
+    r = MeshResult()
+    _check(lib().ftk_track_cp_mesh2d(ctypes.c_void_p(xy.data_ptr()), xy.shape[0], ctypes.c_void_p(tri.data_ptr()),
+                                     tri.shape[0], ctypes.c_void_p(field.data_ptr()), field.shape[0], ctypes.byref(o),
+                                     _stream_handle(xy.device), ctypes.byref(r)))
+    nh = int(r.n_hits)
+    return dict(n_hits=nh, n_trajectories=int(r.n_trajectories), faces_per_step=int(r.faces_per_step),
+                n_edges=int(r.n_edges), face_id=pool.take(r.face_id, torch.int64, (max(nh, 1),))[:nh],
+                pos=pool.take(r.pos, torch.float32, (max(nh, 1), 3))[:nh],
                 label=pool.take(r.label, torch.int64, (max(nh, 1),))[:nh])
 
 

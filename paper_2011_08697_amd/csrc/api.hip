@@ -1,6 +1,7 @@
 // api.hip -- the C ABI (include/ftk.h): argument checks, device memory, launch sequence, status decoding.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -1717,6 +1718,116 @@ ftk_status ftk_track_vortex3d(const float* psi, int64_t nx, int64_t ny, int64_t 
     return st;
   }
   r.n_components = (long long)h.cnt[ftk::CNT_TRAJ];
+  *out = r;
+  return FTK_OK;
+}
+
+void ftk_mesh_result_free(ftk_mesh_result* r, const ftk_options* opt, ftk_stream_t stream) {
+  if (!r) return;
+  ftk_options o;
+  resolve(opt, &o);
+  const Alloc al = make_alloc(o, (hipStream_t)stream);
+  al.put(r->face_id);
+  al.put(r->pos);
+  al.put(r->label);
+  std::memset(r, 0, sizeof(*r));
+}
+
+ftk_status ftk_track_cp_mesh2d(const float* xy, int64_t nv, const int32_t* tri, int64_t nf, const float* field,
+                               int64_t nt, const ftk_options* opt, ftk_stream_t stream, ftk_mesh_result* out) {
+  g_err.clear();
+  if (!out) return fail(FTK_ERR_ARG, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (!xy || !tri || !field) return fail(FTK_ERR_ARG, "xy, tri and field must be given");
+  if (nv < 3 || nf < 1 || nt < 2 || nt > 65535) return fail(FTK_ERR_ARG, "need nv >= 3, nf >= 1, 2 <= nt <= 65535");
+  if (nv >= (1ll << 31) || nf >= (1ll << 29)) return fail(FTK_ERR_ARG, "mesh too large");
+  ftk_options o;
+  resolve(opt, &o);
+  ftk_status st = ftk::validate_options(o);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // mesh topology on the host: rows sorted, unique edges (a < b) ascending, edges (v0 v1), (v1 v2), (v0 v2) per row
+  std::vector<int> ht((size_t)(3 * nf));
+  HIP_TRY(hipMemcpyAsync(ht.data(), tri, sizeof(int) * 3 * (size_t)nf, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<unsigned long long> keys((size_t)(3 * nf));
+  for (long long T = 0; T < nf; ++T) {
+    int* r = &ht[(size_t)(3 * T)];
+    for (int k = 0; k < 3; ++k)
+      if (r[k] < 0 || r[k] >= nv) return fail(FTK_ERR_ARG, "triangle %lld: vertex index out of range", T);
+    std::sort(r, r + 3);
+    if (r[0] == r[1] || r[1] == r[2]) return fail(FTK_ERR_ARG, "triangle %lld repeats a vertex", T);
+    keys[(size_t)(3 * T)] = ((unsigned long long)r[0] << 32) | (unsigned)r[1];
+    keys[(size_t)(3 * T + 1)] = ((unsigned long long)r[1] << 32) | (unsigned)r[2];
+    keys[(size_t)(3 * T + 2)] = ((unsigned long long)r[0] << 32) | (unsigned)r[2];
+  }
+  std::vector<unsigned long long> ukeys(keys);
+  std::sort(ukeys.begin(), ukeys.end());
+  ukeys.erase(std::unique(ukeys.begin(), ukeys.end()), ukeys.end());
+  const long long ne = (long long)ukeys.size();
+  std::vector<int> he((size_t)(2 * ne)), hte((size_t)(3 * nf));
+  for (long long E = 0; E < ne; ++E) {
+    he[(size_t)(2 * E)] = (int)(ukeys[(size_t)E] >> 32);
+    he[(size_t)(2 * E + 1)] = (int)(ukeys[(size_t)E] & 0xffffffffull);
+  }
+  for (size_t k = 0; k < keys.size(); ++k)
+    hte[k] = (int)(std::lower_bound(ukeys.begin(), ukeys.end(), keys[k]) - ukeys.begin());
+  const long long S = 3 * nf + 2 * ne, NF = S * nt;
+  const Alloc al = make_alloc(o, s);
+  Scratch sc(al);
+  int* dtri = sc.get<int>((size_t)(3 * nf));
+  int* dedge = sc.get<int>((size_t)(2 * ne));
+  int* dte = sc.get<int>((size_t)(3 * nf));
+  int* flag = sc.get<int>((size_t)NF);
+  long long* off = sc.get<long long>((size_t)NF);
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(NF));
+  Ctl* dctl = sc.get<Ctl>(1);
+  if (!dtri || !dedge || !dte || !flag || !off || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  HIP_TRY(hipMemcpyAsync(dtri, ht.data(), sizeof(int) * 3 * (size_t)nf, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dedge, he.data(), sizeof(int) * 2 * (size_t)ne, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dte, hte.data(), sizeof(int) * 3 * (size_t)nf, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+  const float qscale = std::ldexp(1.0f, o.quant_log2);
+  HIP_TRY(ftk::launch_pm_test(xy, dtri, dedge, dte, field, nv, nf, ne, (int)nt, qscale, flag, &dctl->status, s));
+  HIP_TRY(ftk::launch_scan(flag, off, NF, &dctl->total, tmp, s));
+  Ctl h;
+  st = read_ctl(&h, dctl, s);
+  if (st) return st;
+  st = decode_status(h.status);
+  if (st) return st;
+  const long long nh = h.total;
+  if (nh >= 0xffffffffll) return fail(FTK_ERR_CAPACITY, "%lld punctured faces exceed the 32-bit union-find", nh);
+  ftk_mesh_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.n_hits = nh;
+  r.faces_per_step = S;
+  r.n_edges = ne;
+  r.face_id = (int64_t*)al.get(sizeof(int64_t) * (size_t)(nh > 0 ? nh : 1));
+  r.pos = (float*)al.get(sizeof(float) * 3 * (size_t)(nh > 0 ? nh : 1));
+  r.label = (int64_t*)al.get(sizeof(int64_t) * (size_t)(nh > 0 ? nh : 1));
+  unsigned* parent = sc.get<unsigned>((size_t)(nh > 0 ? nh : 1));
+  if (!r.face_id || !r.pos || !r.label || !parent) {
+    ftk_mesh_result_free(&r, opt, stream);
+    return fail(FTK_ERR_OOM, "output allocation failed");
+  }
+  hipError_t hr = hipSuccess;
+  if (nh > 0) {
+    hr = ftk::launch_pm_emit(xy, dtri, dedge, dte, field, nv, nf, ne, (int)nt, qscale, flag, off,
+                             (long long*)r.face_id, r.pos, parent, &dctl->status, s);
+    if (hr == hipSuccess)
+      hr = ftk::launch_uf_label(parent, (const long long*)r.face_id, (long long*)r.label, nh, dctl->cnt, s);
+  }
+  if (hr != hipSuccess) {
+    ftk_mesh_result_free(&r, opt, stream);
+    return fail(FTK_ERR_HIP, "kernel launch: %s", hipGetErrorString(hr));
+  }
+  st = read_ctl(&h, dctl, s);
+  if (!st) st = decode_status(h.status);
+  if (st) {
+    ftk_mesh_result_free(&r, opt, stream);
+    return st;
+  }
+  r.n_trajectories = (long long)h.cnt[ftk::CNT_TRAJ];
   *out = r;
   return FTK_OK;
 }

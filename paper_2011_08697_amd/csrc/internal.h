@@ -155,6 +155,15 @@ hipError_t launch_vx_detect(const float* psi, int nx, int ny, int nz, int nt, fl
 hipError_t launch_vx_emit(const float* psi, int nx, int ny, int nz, int nt, float qscale,
                           const unsigned long long* tmask, const long long* hoff, long long* tri_id, float* pos,
                           unsigned* parent, hipStream_t s);
+// Critical points on an extruded triangle mesh (prism.hip): face tests over nt * S faces (flag), then emission and
+// the tetrahedron unions from the scanned flags.
+hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
+                          long long nv, long long nf, long long ne, int nt, float qscale, int* flag, unsigned* status,
+                          hipStream_t s);
+hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
+                          long long nv, long long nf, long long ne, int nt, float qscale, const int* flag,
+                          const long long* off, long long* face_id, float* pos, unsigned* parent, unsigned* status,
+                          hipStream_t s);
 // Type smoothing and run simplification along an order (head/heads: [n_hits] int / int64 scratch).
 hipError_t launch_smooth(const long long* order, const long long* offsets, const int* n_ends, long long n_traj,
                          long long n_hits, const uint8_t* type_in, int half, int* head, long long* heads,

@@ -1,0 +1,193 @@
+// prism.hip -- critical-point tracking of a 2D vector field on an unstructured triangle mesh extruded in time
+// (Sec. 3.2, prismatic subdivision; Sec. 4.2 two passes).
+//
+// Every mesh triangle v0 < v1 < v2 becomes, between steps t and t + 1, the prism a0 a1 a2 - b0 b1 b2 split by the
+// staircase into a0 a1 a2 b2, a0 a1 b1 b2 and a0 b0 b1 b2 (global vertex order g = t nv + v); the quadrilateral of
+// a mesh edge a < b is split along its monotone diagonal a - b'.  Faces of step t are numbered t * S + local,
+// S = nf + 2 ne + 2 nf: the mesh triangle T (local T), the edge faces (a, b, b') and (a, a', b') of edge E (nf + 2E,
+// +1), and the interior faces (v0, v1, v2') and (v0, v1', v2') of T (nf + 2 ne + 2T, +1); interval faces exist for
+// t < nt - 1.
+//
+//   pm_test  -- one lane per (face, step): the puncture test of the quantised 2D vectors at its three vertices in
+//               global order (SoS signs of the three vertex-pair determinants, as in the regular path).
+//   pm_emit  -- face ids, points from the exact cofactors (Eq. 2) in (x, y, t), identity parents.
+//   pm_unite -- one lane per (prism, step): the two punctured faces of each of its three tetrahedra are united.
+#include "common.h"
+#include "internal.h"
+#include "uf_cached.h"
+
+namespace ftk {
+
+namespace {
+
+struct PmMesh {
+  const float* xy;      // [nv][2]
+  const int* tri;       // [nf][3], ascending per row
+  const int* edge;      // [ne][2], a < b, ascending
+  const int* tri_edge;  // [nf][3]: edges (v0 v1), (v1 v2), (v0 v2)
+  const float* field;   // [nt][2][nv]
+  long long nv, nf, ne, S;
+  int nt;
+  float qscale;
+};
+
+// vertices (vertex, step offset) of local face f of a step, in global order; false for an interval face at the last
+// step
+__device__ __forceinline__ void pm_face(const PmMesh& m, long long f, int* v, int* dt) {
+  if (f < m.nf) {
+    const int* a = m.tri + 3 * f;
+    v[0] = a[0], v[1] = a[1], v[2] = a[2];
+    dt[0] = dt[1] = dt[2] = 0;
+  } else if (f < m.nf + 2 * m.ne) {
+    const long long E = (f - m.nf) >> 1;
+    const int up = (int)((f - m.nf) & 1);
+    const int a = m.edge[2 * E], b = m.edge[2 * E + 1];
+    v[0] = a, dt[0] = 0;
+    v[1] = up ? a : b, dt[1] = up ? 1 : 0;
+    v[2] = b, dt[2] = 1;
+  } else {
+    const long long T = (f - m.nf - 2 * m.ne) >> 1;
+    const int up = (int)((f - m.nf - 2 * m.ne) & 1);
+    const int* a = m.tri + 3 * T;
+    v[0] = a[0], dt[0] = 0;
+    v[1] = a[1], dt[1] = up;
+    v[2] = a[2], dt[2] = 1;
+  }
+}
+
+__device__ __forceinline__ void pm_q(const PmMesh& m, int v, int t, long long* q, unsigned& st) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const float x = m.field[((long long)t * 2 + c) * m.nv + v] * m.qscale;
+    if (!isfinite(x)) {
+      st |= ST_NONFINITE;
+      q[c] = 0;
+    } else if (!(fabsf(x) < 2147483648.0f)) {
+      st |= ST_RANGE;
+      q[c] = 0;
+    } else {
+      q[c] = (long long)rintf(x);
+    }
+  }
+}
+
+// SoS sign of det(a, b), columns in global vertex order: first nonzero of (a0 b1 - a1 b0, b1, -b0, -a1, -1)
+__device__ __forceinline__ unsigned pm_sos2(const long long* a, const long long* b) {
+  const long long d = a[0] * b[1] - a[1] * b[0];
+  if (d != 0) return d > 0;
+  if (b[1] != 0) return b[1] > 0;
+  if (b[0] != 0) return b[0] < 0;
+  if (a[1] != 0) return a[1] < 0;
+  return 0u;
+}
+
+__global__ void pm_test(PmMesh m, int* __restrict__ flag, unsigned* __restrict__ status) {
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (f >= m.S) return;
+  const long long id = (long long)t * m.S + f;
+  if (f >= m.nf && t == m.nt - 1) {  // interval faces need step t + 1
+    flag[id] = 0;
+    return;
+  }
+  int v[3], dt[3];
+  pm_face(m, f, v, dt);
+  unsigned st = 0;
+  long long q[3][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pm_q(m, v[i], t + dt[i], q[i], st);
+  // cofactor signs +S(1,2), -S(0,2), +S(0,1) agree
+  const unsigned s01 = pm_sos2(q[0], q[1]), s02 = pm_sos2(q[0], q[2]), s12 = pm_sos2(q[1], q[2]);
+  flag[id] = (s12 == s01 && s02 != s01) ? 1 : 0;
+  // every vertex value is checked by the ordinal faces of its triangles (each vertex belongs to one)
+  if (st && f < m.nf) atomicOr(status, st);
+}
+
+__global__ void pm_emit(PmMesh m, const int* __restrict__ flag, const long long* __restrict__ off,
+                        long long* __restrict__ face_id, float* __restrict__ pos, unsigned* __restrict__ parent) {
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (f >= m.S) return;
+  const long long id = (long long)t * m.S + f;
+  if (!flag[id]) return;
+  int v[3], dt[3];
+  pm_face(m, f, v, dt);
+  unsigned st = 0;
+  long long q[3][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pm_q(m, v[i], t + dt[i], q[i], st);
+  const long long C0 = q[1][0] * q[2][1] - q[1][1] * q[2][0];
+  const long long C1 = -(q[0][0] * q[2][1] - q[0][1] * q[2][0]);
+  const long long C2 = q[0][0] * q[1][1] - q[0][1] * q[1][0];
+  double mu[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0};
+  if (C0 != 0 || C1 != 0 || C2 != 0) {
+    const double D = ((double)C0 + (double)C1) + (double)C2;
+    mu[0] = (double)C0 / D;
+    mu[1] = (double)C1 / D;
+    mu[2] = (double)C2 / D;
+  }
+  const long long o = off[id];
+  face_id[o] = id;
+  if (pos) {
+    double p[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double c[3] = {(double)m.xy[2 * v[i]], (double)m.xy[2 * v[i] + 1], (double)(t + dt[i])};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) p[k] = i == 0 ? mu[0] * c[k] : p[k] + mu[i] * c[k];
+    }
+    pos[o * 3 + 0] = (float)p[0];
+    pos[o * 3 + 1] = (float)p[1];
+    pos[o * 3 + 2] = (float)p[2];
+  }
+  parent[o] = (unsigned)o;
+}
+
+__global__ void pm_unite(PmMesh m, const int* __restrict__ flag, const long long* __restrict__ off,
+                         unsigned* __restrict__ parent, unsigned* __restrict__ status) {
+  const long long T = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (T >= m.nf || t >= m.nt - 1) return;
+  const long long base = (long long)t * m.S;
+  const int* te = m.tri_edge + 3 * T;
+  const long long e01 = base + m.nf + 2LL * te[0], e12 = base + m.nf + 2LL * te[1], e02 = base + m.nf + 2LL * te[2];
+  const long long in = base + m.nf + 2 * m.ne + 2 * T;
+  const long long ord0 = base + T, ord1 = base + m.S + T;
+  // sides of a0 a1 a2 b2, a0 a1 b1 b2, a0 b0 b1 b2 (lower / upper edge and interior faces are +0 / +1)
+  const long long tet[3][4] = {{ord0, in, e02, e12}, {e01, in, in + 1, e12 + 1}, {e01 + 1, e02 + 1, in + 1, ord1}};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    long long h[4];
+    int n = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (flag[tet[k][j]]) h[n++] = off[tet[k][j]];
+    if (n == 2)
+      uf_unite_cached(parent, (unsigned)h[0], (unsigned)h[1]);
+    else if (n != 0)
+      atomicOr(status, ST_INVARIANT);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
+                          long long nv, long long nf, long long ne, int nt, float qscale, int* flag, unsigned* status,
+                          hipStream_t s) {
+  const PmMesh m{xy, tri, edge, tri_edge, field, nv, nf, ne, nf + 2 * ne + 2 * nf, nt, qscale};
+  pm_test<<<dim3((unsigned)((m.S + 255) / 256), (unsigned)nt), 256, 0, s>>>(m, flag, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
+                          long long nv, long long nf, long long ne, int nt, float qscale, const int* flag,
+                          const long long* off, long long* face_id, float* pos, unsigned* parent, unsigned* status,
+                          hipStream_t s) {
+  const PmMesh m{xy, tri, edge, tri_edge, field, nv, nf, ne, nf + 2 * ne + 2 * nf, nt, qscale};
+  pm_emit<<<dim3((unsigned)((m.S + 255) / 256), (unsigned)nt), 256, 0, s>>>(m, flag, off, face_id, pos, parent);
+  if (nt > 1)
+    pm_unite<<<dim3((unsigned)((nf + 255) / 256), (unsigned)(nt - 1)), 256, 0, s>>>(m, flag, off, parent, status);
+  return hipGetLastError();
+}
+
+}  // namespace ftk
