@@ -31,6 +31,8 @@ WORKLOADS = {
     "iso_blobs3d256": "isovolume f = 0.5 of the 3D scalar 256x256x256x16 blob series (512 moving Gaussians, seed 2)",
     "vortex_waves512": "vortex surfaces of a 3D complex 512x128x64x8 series (independent random cosine waves for the "
                        "real and imaginary parts, 8 each, seed 6)",
+    "mesh500k": "2D vector field on a 500,000-point Delaunay mesh of [0,100]^2 extruded over 40 steps (moving "
+                "sources and vortices, seed 9)",
 }
 
 
@@ -285,6 +287,75 @@ def bench_vortex(args, F, synth, dev):
     print(json.dumps(line), flush=True)
 
 
+def bench_mesh(args, F, synth, dev):
+    """Critical points on an extruded unstructured mesh: K calls of ftk_track_cp_mesh on a mesh handle (topology
+    built once) and a resident field; value = spacetime faces tested per second (S per step, interval faces for all
+    but the last step)."""
+    import numpy as np
+    import torch
+    xy, tri = synth.delaunay_mesh(500000, extent=100.0, seed=9)
+    nt = 40
+    rng = np.random.Generator(np.random.PCG64(9))
+    P = xy.astype(np.float64) / 10.0
+    f = np.zeros((nt, 2, len(xy)), np.float64)
+    for _ in range(16):
+        c, v, rot = rng.uniform(1, 9, 2), rng.uniform(-0.1, 0.1, 2), rng.uniform(0, np.pi)
+        for t in range(nt):
+            d = P - (c + v * t)
+            w = np.exp(-(d ** 2).sum(1) / 2.0)
+            f[t, 0] += w * (np.cos(rot) * d[:, 0] - np.sin(rot) * d[:, 1])
+            f[t, 1] += w * (np.sin(rot) * d[:, 0] + np.cos(rot) * d[:, 1])
+    dxy = torch.from_numpy(xy).to(dev)
+    dtri = torch.from_numpy(np.ascontiguousarray(tri, np.int32)).to(dev)
+    dfield = torch.from_numpy(f.astype(np.float32)).to(dev)
+    L = F.lib()
+    sh = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    pool = F._TorchPool(dev)
+    opt = F._options(pool)
+
+    mesh = ctypes.c_void_p()  # topology built once, outside the timed calls (as a mesh is set up once per dataset)
+    st0 = L.ftk_mesh_create(ctypes.c_void_p(dxy.data_ptr()), len(xy), ctypes.c_void_p(dtri.data_ptr()), len(tri), sh,
+                            ctypes.byref(mesh))
+    if st0 != 0:
+        raise F.FtkError(st0, F.last_error())
+
+    def one():
+        r = F.MeshResult()
+        st = L.ftk_track_cp_mesh(mesh, ctypes.c_void_p(dfield.data_ptr()), nt, ctypes.byref(opt), sh,
+                                 ctypes.byref(r))
+        if st != 0:
+            raise F.FtkError(st, F.last_error())
+        out = (int(r.n_hits), int(r.n_trajectories), int(r.faces_per_step), int(r.n_edges))
+        L.ftk_mesh_result_free(ctypes.byref(r), ctypes.byref(opt), sh)
+        return out
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nh, ntraj, S, ne = one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    L.ftk_mesh_destroy(mesh)
+    nf = len(tri)
+    faces = nt * nf + (nt - 1) * (2 * ne + 2 * nf)
+    alg = 8 * len(xy) * nt + 12 * nf + 8 * len(xy) + 28 * nh  # field, mesh in; id, point, label out
+    line = {
+        "metric": "spacetime faces tested/s (critical points on an extruded triangle mesh)",
+        "value": round(faces / (ms * 1e-3), 1), "unit": "faces/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["mesh500k"], "vertices": len(xy), "triangles": nf, "edges": ne, "steps": nt,
+                   "n_hits": nh, "n_trajectories": ntraj, "faces_per_call": faces},
+        "roofline": {"bound": "hbm", "kernel": "whole call", "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def post_report(F, field, n, kind, dims, reps=2):
     """Wall time of each trajectory post-processing call on this workload's result (after the timed region; not part
     of value): table, slice at the middle step, loop filter, order, smoothing (half window 2), simplification."""
@@ -339,6 +410,8 @@ def main():
         return bench_iso(args, F, synth, dev)
     if wl == "vortex_waves512":
         return bench_vortex(args, F, synth, dev)
+    if wl == "mesh500k":
+        return bench_mesh(args, F, synth, dev)
     n = 3 if wl == "blobs3d256" else 2
     kind = 1 if wl == "vortex4096" else 0
     t0 = time.time()

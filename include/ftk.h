@@ -328,8 +328,8 @@ int64_t ftk_triangle_count(const int64_t* dims_with_t);
  * edge faces (a, b, b') and (a, a', b') of edge E (nf + 2E, +1); the interior faces (v0, v1, v2') and (v0, v1', v2')
  * of T (nf + 2 ne + 2T, +1).  Faces are tested like the regular path (quantised with opt->quant_log2, SoS); points
  * are (x, y, t) from the exact barycentric weights; the two punctured faces of every tetrahedron are united, labels
- * = smallest face id.  No critical-point types (the field's Jacobian on a mesh is out of scope here).  Builds the
- * mesh topology on the host (tri is copied back), synchronises the stream.  nv >= 3, nf >= 1, 2 <= nt <= 65535;
+ * = smallest face id.  No critical-point types (the field's Jacobian on a mesh is out of scope here).
+ * Synchronises the stream.  nv >= 3, nf >= 1, 2 <= nt <= 65535;
  * FTK_ERR_ARG for indices out of range or repeated within a triangle; errors otherwise as ftk_track_cp2d.
  */
 typedef struct {
@@ -342,6 +342,16 @@ typedef struct {
   int64_t* label;          /* [n_hits] smallest face id of the trajectory */
 } ftk_mesh_result;
 
+/* Mesh handle: the topology (sorted triangles, unique edges, triangle edges) built once on the host from tri
+ * (copied back) and kept on the device; xy is referenced, so it must outlive the handle.  Errors as above. */
+typedef struct ftk_mesh ftk_mesh;
+ftk_status ftk_mesh_create(const float* xy, int64_t nv, const int32_t* tri, int64_t nf, ftk_stream_t stream,
+                           ftk_mesh** m);
+void ftk_mesh_destroy(ftk_mesh* m);
+/* Tracking on a mesh handle (no host work besides the two count read-backs). */
+ftk_status ftk_track_cp_mesh(const ftk_mesh* m, const float* field, int64_t nt, const ftk_options* opt,
+                             ftk_stream_t stream, ftk_mesh_result* out);
+/* One-shot form: create, track, destroy. */
 ftk_status ftk_track_cp_mesh2d(const float* xy, int64_t nv, const int32_t* tri, int64_t nf, const float* field,
                                int64_t nt, const ftk_options* opt, ftk_stream_t stream, ftk_mesh_result* out);
 void ftk_mesh_result_free(ftk_mesh_result* r, const ftk_options* opt, ftk_stream_t stream);

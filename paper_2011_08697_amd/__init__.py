@@ -24,7 +24,8 @@ EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_cr
            "ftk_cp_filter_loops", "ftk_buffer_free", "ftk_autotune_cp2d", "ftk_traj_order",
            "ftk_traj_smooth_types", "ftk_traj_simplify_types", "ftk_track_iso3d", "ftk_iso_result_free",
            "ftk_edge_count", "ftk_track_vortex3d", "ftk_vortex_result_free", "ftk_triangle_count",
-           "ftk_track_cp_mesh2d", "ftk_mesh_result_free"]
+           "ftk_track_cp_mesh2d", "ftk_mesh_result_free", "ftk_mesh_create", "ftk_mesh_destroy",
+           "ftk_track_cp_mesh"]
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -146,6 +147,12 @@ def lib():
         L.ftk_track_cp_mesh2d.restype = ctypes.c_int
         L.ftk_mesh_result_free.argtypes = [ctypes.POINTER(MeshResult), ctypes.POINTER(Options), vp]
         L.ftk_mesh_result_free.restype = None
+        L.ftk_mesh_create.argtypes = [vp, i64, vp, i64, vp, ctypes.POINTER(vp)]
+        L.ftk_mesh_create.restype = ctypes.c_int
+        L.ftk_mesh_destroy.argtypes = [vp]
+        L.ftk_mesh_destroy.restype = None
+        L.ftk_track_cp_mesh.argtypes = [vp, vp, i64, ctypes.POINTER(Options), vp, ctypes.POINTER(MeshResult)]
+        L.ftk_track_cp_mesh.restype = ctypes.c_int
         L.ftk_traj_order.argtypes = [ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(i64),
                                      ctypes.POINTER(TrajTable), ctypes.POINTER(Options), vp, vp, vp]
         L.ftk_traj_order.restype = ctypes.c_int

@@ -1722,6 +1722,18 @@ ftk_status ftk_track_vortex3d(const float* psi, int64_t nx, int64_t ny, int64_t 
   return FTK_OK;
 }
 
+}  // extern "C"
+
+struct ftk_mesh {
+  const float* xy = nullptr;  // caller's device array, referenced (not copied)
+  long long nv = 0, nf = 0, ne = 0;
+  int* tri = nullptr;       // [nf][3] ascending per row
+  int* edge = nullptr;      // [ne][2] a < b, ascending
+  int* tri_edge = nullptr;  // [nf][3] edges (v0 v1), (v1 v2), (v0 v2)
+};
+
+extern "C" {
+
 void ftk_mesh_result_free(ftk_mesh_result* r, const ftk_options* opt, ftk_stream_t stream) {
   if (!r) return;
   ftk_options o;
@@ -1733,18 +1745,14 @@ void ftk_mesh_result_free(ftk_mesh_result* r, const ftk_options* opt, ftk_stream
   std::memset(r, 0, sizeof(*r));
 }
 
-ftk_status ftk_track_cp_mesh2d(const float* xy, int64_t nv, const int32_t* tri, int64_t nf, const float* field,
-                               int64_t nt, const ftk_options* opt, ftk_stream_t stream, ftk_mesh_result* out) {
+ftk_status ftk_mesh_create(const float* xy, int64_t nv, const int32_t* tri, int64_t nf, ftk_stream_t stream,
+                           ftk_mesh** out) {
   g_err.clear();
   if (!out) return fail(FTK_ERR_ARG, "out is NULL");
-  std::memset(out, 0, sizeof(*out));
-  if (!xy || !tri || !field) return fail(FTK_ERR_ARG, "xy, tri and field must be given");
-  if (nv < 3 || nf < 1 || nt < 2 || nt > 65535) return fail(FTK_ERR_ARG, "need nv >= 3, nf >= 1, 2 <= nt <= 65535");
+  *out = nullptr;
+  if (!xy || !tri) return fail(FTK_ERR_ARG, "xy and tri must be given");
+  if (nv < 3 || nf < 1) return fail(FTK_ERR_ARG, "need nv >= 3 and nf >= 1");
   if (nv >= (1ll << 31) || nf >= (1ll << 29)) return fail(FTK_ERR_ARG, "mesh too large");
-  ftk_options o;
-  resolve(opt, &o);
-  ftk_status st = ftk::validate_options(o);
-  if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   // mesh topology on the host: rows sorted, unique edges (a < b) ascending, edges (v0 v1), (v1 v2), (v0 v2) per row
   std::vector<int> ht((size_t)(3 * nf));
@@ -1772,23 +1780,60 @@ ftk_status ftk_track_cp_mesh2d(const float* xy, int64_t nv, const int32_t* tri, 
   }
   for (size_t k = 0; k < keys.size(); ++k)
     hte[k] = (int)(std::lower_bound(ukeys.begin(), ukeys.end(), keys[k]) - ukeys.begin());
+  ftk_mesh* m = new ftk_mesh();
+  m->xy = xy;
+  m->nv = nv;
+  m->nf = nf;
+  m->ne = ne;
+  hipError_t e = hipMalloc((void**)&m->tri, sizeof(int) * 3 * (size_t)nf);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->edge, sizeof(int) * 2 * (size_t)ne);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->tri_edge, sizeof(int) * 3 * (size_t)nf);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->tri, ht.data(), sizeof(int) * 3 * (size_t)nf, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->edge, he.data(), sizeof(int) * 2 * (size_t)ne, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->tri_edge, hte.data(), sizeof(int) * 3 * (size_t)nf, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors die on return
+  if (e != hipSuccess) {
+    ftk_mesh_destroy(m);
+    return fail(FTK_ERR_HIP, "mesh upload: %s", hipGetErrorString(e));
+  }
+  *out = m;
+  return FTK_OK;
+}
+
+void ftk_mesh_destroy(ftk_mesh* m) {
+  if (!m) return;
+  if (m->tri) (void)hipFree(m->tri);
+  if (m->edge) (void)hipFree(m->edge);
+  if (m->tri_edge) (void)hipFree(m->tri_edge);
+  delete m;
+}
+
+ftk_status ftk_track_cp_mesh(const ftk_mesh* m, const float* field, int64_t nt, const ftk_options* opt,
+                             ftk_stream_t stream, ftk_mesh_result* out) {
+  g_err.clear();
+  if (!out) return fail(FTK_ERR_ARG, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (!m || !field) return fail(FTK_ERR_ARG, "mesh and field must be given");
+  if (nt < 2 || nt > 65535) return fail(FTK_ERR_ARG, "need 2 <= nt <= 65535");
+  ftk_options o;
+  resolve(opt, &o);
+  ftk_status st = ftk::validate_options(o);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const long long nv = m->nv, nf = m->nf, ne = m->ne;
   const long long S = 3 * nf + 2 * ne, NF = S * nt;
   const Alloc al = make_alloc(o, s);
   Scratch sc(al);
-  int* dtri = sc.get<int>((size_t)(3 * nf));
-  int* dedge = sc.get<int>((size_t)(2 * ne));
-  int* dte = sc.get<int>((size_t)(3 * nf));
   int* flag = sc.get<int>((size_t)NF);
   long long* off = sc.get<long long>((size_t)NF);
   long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(NF));
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!dtri || !dedge || !dte || !flag || !off || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
-  HIP_TRY(hipMemcpyAsync(dtri, ht.data(), sizeof(int) * 3 * (size_t)nf, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(dedge, he.data(), sizeof(int) * 2 * (size_t)ne, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(dte, hte.data(), sizeof(int) * 3 * (size_t)nf, hipMemcpyHostToDevice, s));
+  if (!flag || !off || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   const float qscale = std::ldexp(1.0f, o.quant_log2);
-  HIP_TRY(ftk::launch_pm_test(xy, dtri, dedge, dte, field, nv, nf, ne, (int)nt, qscale, flag, &dctl->status, s));
+  HIP_TRY(ftk::launch_pm_test(m->xy, m->tri, m->edge, m->tri_edge, field, nv, nf, ne, (int)nt, qscale, flag,
+                              &dctl->status, s));
   HIP_TRY(ftk::launch_scan(flag, off, NF, &dctl->total, tmp, s));
   Ctl h;
   st = read_ctl(&h, dctl, s);
@@ -1812,7 +1857,7 @@ ftk_status ftk_track_cp_mesh2d(const float* xy, int64_t nv, const int32_t* tri, 
   }
   hipError_t hr = hipSuccess;
   if (nh > 0) {
-    hr = ftk::launch_pm_emit(xy, dtri, dedge, dte, field, nv, nf, ne, (int)nt, qscale, flag, off,
+    hr = ftk::launch_pm_emit(m->xy, m->tri, m->edge, m->tri_edge, field, nv, nf, ne, (int)nt, qscale, flag, off,
                              (long long*)r.face_id, r.pos, parent, &dctl->status, s);
     if (hr == hipSuccess)
       hr = ftk::launch_uf_label(parent, (const long long*)r.face_id, (long long*)r.label, nh, dctl->cnt, s);
@@ -1830,6 +1875,22 @@ ftk_status ftk_track_cp_mesh2d(const float* xy, int64_t nv, const int32_t* tri, 
   r.n_trajectories = (long long)h.cnt[ftk::CNT_TRAJ];
   *out = r;
   return FTK_OK;
+}
+
+ftk_status ftk_track_cp_mesh2d(const float* xy, int64_t nv, const int32_t* tri, int64_t nf, const float* field,
+                               int64_t nt, const ftk_options* opt, ftk_stream_t stream, ftk_mesh_result* out) {
+  g_err.clear();
+  if (!out) return fail(FTK_ERR_ARG, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (!field) return fail(FTK_ERR_ARG, "field must be given");
+  if (nt < 2 || nt > 65535) return fail(FTK_ERR_ARG, "need 2 <= nt <= 65535");
+  ftk_mesh* m = nullptr;
+  ftk_status st = ftk_mesh_create(xy, nv, tri, nf, stream, &m);
+  if (st) return st;
+  st = ftk_track_cp_mesh(m, field, nt, opt, stream, out);
+  (void)hipStreamSynchronize((hipStream_t)stream);
+  ftk_mesh_destroy(m);
+  return st;
 }
 
 void ftk_buffer_free(void* p, const ftk_options* opt, ftk_stream_t stream) {

@@ -125,3 +125,34 @@ def test_large_delaunay_mesh_sampled():
         mu = [1 / 3] * 3 if D == 0 else [c / D for c in C]
         want = sum(m * np.array([xy[v, 0], xy[v, 1], tt], float) for m, (v, tt) in zip(mu, vs))
         assert_pos_close(pos[k:k + 1], want[None, :])
+
+
+def test_mesh_handle_tracks_several_fields():
+    """One mesh handle, two fields: each result equals the one-shot call."""
+    import ctypes
+    xy, tri = synth.delaunay_mesh(80, seed=4)
+    dxy = torch.from_numpy(np.ascontiguousarray(xy)).to(DEV)
+    dtri = torch.from_numpy(np.ascontiguousarray(tri, np.int32)).to(DEV)
+    L = F.lib()
+    sh = F._stream_handle(DEV)
+    mesh = ctypes.c_void_p()
+    assert L.ftk_mesh_create(ctypes.c_void_p(dxy.data_ptr()), len(xy), ctypes.c_void_p(dtri.data_ptr()), len(tri), sh,
+                             ctypes.byref(mesh)) == 0
+    try:
+        for seed in (1, 2):
+            field = _swirl(xy.astype(np.float64), 5, seed)
+            df = torch.from_numpy(field).to(DEV)
+            pool = F._TorchPool(DEV)
+            o = F._options(pool)
+            r = F.MeshResult()
+            assert L.ftk_track_cp_mesh(mesh, ctypes.c_void_p(df.data_ptr()), 5, ctypes.byref(o), sh,
+                                       ctypes.byref(r)) == 0
+            nh = int(r.n_hits)
+            fid = pool.take(r.face_id, torch.int64, (max(nh, 1),))[:nh].cpu().numpy()
+            lab = pool.take(r.label, torch.int64, (max(nh, 1),))[:nh].cpu().numpy()
+            g = _run(xy, tri, field)
+            assert nh == g["n_hits"] and int(r.n_trajectories) == g["n_trajectories"]
+            assert np.array_equal(fid, g["face_id"].cpu().numpy())
+            assert np.array_equal(lab, g["label"].cpu().numpy())
+    finally:
+        L.ftk_mesh_destroy(mesh)
