@@ -353,6 +353,22 @@ def bench_mesh(args, F, synth, dev):
                      "traffic": None},
         "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        from oracle import mesh as OM
+        sub = np.nonzero((xy[:, 0] < 12.0) & (xy[:, 1] < 12.0))[0]  # a corner patch of the same mesh and field
+        keep = np.all(np.isin(tri, sub), axis=1)
+        remap = -np.ones(len(xy), np.int64)
+        remap[sub] = np.arange(len(sub))
+        stri = remap[tri[keep]]
+        sf = np.ascontiguousarray(f[:3][:, :, sub].astype(np.float32))
+        t0 = time.perf_counter()
+        OM.track_cp_mesh(xy[sub], stri, sf)
+        cpu_s = time.perf_counter() - t0
+        se = len(OM.mesh_edges(stri))
+        sfaces = 3 * len(stri) + 2 * (2 * se + 2 * len(stri))
+        line["cpu_baseline"] = {"value": round(sfaces / cpu_s, 1), "unit": "faces/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{len(sub)}-vertex corner patch of the same mesh, 3 steps ({sfaces} faces, "
+                                          f"python, {cpu_s:.1f} s)"}
     print(json.dumps(line), flush=True)
 
 

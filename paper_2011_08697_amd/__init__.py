@@ -477,6 +477,50 @@ def track_cp_mesh2d(xy, tri, field, **opts):
                 label=pool.take(r.label, torch.int64, (max(nh, 1),))[:nh])
 
 
+class Mesh:
+    """Mesh handle: the topology of a triangle mesh (xy float32 [nv][2], tri int32 [nf][3], contiguous CUDA
+    tensors) built once; track(field) then runs on the device only.  xy is referenced, not copied."""
+
+    def __init__(self, xy, tri):
+        import torch
+        if not (xy.is_cuda and tri.is_cuda and xy.dtype == torch.float32 and tri.dtype == torch.int32
+                and xy.is_contiguous() and tri.is_contiguous() and xy.dim() == 2 and xy.shape[1] == 2
+                and tri.dim() == 2 and tri.shape[1] == 3):
+            raise ValueError("need contiguous CUDA tensors xy float32 [nv][2] and tri int32 [nf][3]")
+        self.xy, self.tri, self.device = xy, tri, xy.device
+        self.h = ctypes.c_void_p()
+        _check(lib().ftk_mesh_create(ctypes.c_void_p(xy.data_ptr()), xy.shape[0], ctypes.c_void_p(tri.data_ptr()),
+                                     tri.shape[0], _stream_handle(xy.device), ctypes.byref(self.h)))
+
+    def track(self, field, **opts):
+        """field: contiguous float32 CUDA tensor [nt][2][nv]; returns the same dict as track_cp_mesh2d."""
+        import torch
+        if not (field.is_cuda and field.dtype == torch.float32 and field.is_contiguous() and field.dim() == 3
+                and field.shape[1] == 2 and field.shape[2] == self.xy.shape[0]):
+            raise ValueError("field must be a contiguous float32 CUDA tensor [nt][2][nv]")
+        pool = _TorchPool(self.device)
+        o = _options(pool, **opts)
+        r = MeshResult()
+        _check(lib().ftk_track_cp_mesh(self.h, ctypes.c_void_p(field.data_ptr()), field.shape[0], ctypes.byref(o),
+                                       _stream_handle(self.device), ctypes.byref(r)))
+        nh = int(r.n_hits)
+        return dict(n_hits=nh, n_trajectories=int(r.n_trajectories), faces_per_step=int(r.faces_per_step),
+                    n_edges=int(r.n_edges), face_id=pool.take(r.face_id, torch.int64, (max(nh, 1),))[:nh],
+                    pos=pool.take(r.pos, torch.float32, (max(nh, 1), 3))[:nh],
+                    label=pool.take(r.label, torch.int64, (max(nh, 1),))[:nh])
+
+    def close(self):
+        if self.h:
+            lib().ftk_mesh_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def triangle_count(dims_with_t):
     """Spacetime triangles tested for a 3D grid (nx, ny, nz, nt)."""
     arr = (ctypes.c_int64 * 4)(*dims_with_t)

@@ -156,3 +156,14 @@ def test_mesh_handle_tracks_several_fields():
             assert np.array_equal(lab, g["label"].cpu().numpy())
     finally:
         L.ftk_mesh_destroy(mesh)
+
+
+def test_mesh_class_binding():
+    xy, tri = synth.delaunay_mesh(50, seed=6)
+    m = F.Mesh(torch.from_numpy(xy).to(DEV), torch.from_numpy(np.ascontiguousarray(tri, np.int32)).to(DEV))
+    field = _swirl(xy.astype(np.float64), 4, 3)
+    g = m.track(torch.from_numpy(field).to(DEV))
+    o = M.track_cp_mesh(xy, tri, field)
+    assert np.array_equal(g["face_id"].cpu().numpy(), o.face_id)
+    assert np.array_equal(g["label"].cpu().numpy(), o.label)
+    m.close()
