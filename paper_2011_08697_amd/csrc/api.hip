@@ -1566,8 +1566,8 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   Scratch sc(al);
   const long long V = nx * ny * nz * nt;
   unsigned short* emask = sc.get<unsigned short>((size_t)V);
-  int* hcnt = sc.get<int>((size_t)V);
-  int* tcnt = sc.get<int>((size_t)V);
+  unsigned char* hcnt = sc.get<unsigned char>((size_t)V);
+  unsigned char* tcnt = sc.get<unsigned char>((size_t)V);
   long long* hoff = sc.get<long long>((size_t)V);
   long long* toff = sc.get<long long>((size_t)V);
   long long* aoff = sc.get<long long>((size_t)V);
@@ -1579,8 +1579,8 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   HIP_TRY(ftk::launch_iso_count(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, bits, emask, hcnt, tcnt,
                                 &dctl->status, s));
-  HIP_TRY(ftk::launch_scan(hcnt, hoff, V, &dctl->total, tmp, s));
-  HIP_TRY(ftk::launch_scan(tcnt, toff, V, (long long*)&dctl->cnt[ftk::CNT_LIST], tmp, s));
+  HIP_TRY(ftk::launch_scan_u8(hcnt, hoff, V, &dctl->total, tmp, s));
+  HIP_TRY(ftk::launch_scan_u8(tcnt, toff, V, (long long*)&dctl->cnt[ftk::CNT_LIST], tmp, s));
   HIP_TRY(ftk::launch_iso_active(tcnt, V, hcnt, aoff, (long long*)&dctl->cnt[ftk::CNT_WORK], tmp, nullptr, false, s));
   Ctl h;
   ftk_status st = read_ctl(&h, dctl, s);
@@ -1673,7 +1673,7 @@ ftk_status ftk_track_vortex3d(const float* psi, int64_t nx, int64_t ny, int64_t 
   const long long V = nx * ny * nz * nt;
   unsigned short* emask = sc.get<unsigned short>((size_t)V);
   unsigned long long* tmask = sc.get<unsigned long long>((size_t)V);
-  int* cnt = sc.get<int>((size_t)V);
+  unsigned char* cnt = sc.get<unsigned char>((size_t)V);
   long long* hoff = sc.get<long long>((size_t)V);
   long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(V));
   Ctl* dctl = sc.get<Ctl>(1);
@@ -1681,7 +1681,7 @@ ftk_status ftk_track_vortex3d(const float* psi, int64_t nx, int64_t ny, int64_t 
   const float qscale = std::ldexp(1.0f, o.quant_log2);
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   HIP_TRY(ftk::launch_vx_detect(psi, (int)nx, (int)ny, (int)nz, (int)nt, qscale, emask, tmask, cnt, &dctl->status, s));
-  HIP_TRY(ftk::launch_scan(cnt, hoff, V, &dctl->total, tmp, s));
+  HIP_TRY(ftk::launch_scan_u8(cnt, hoff, V, &dctl->total, tmp, s));
   Ctl h;
   st = read_ctl(&h, dctl, s);
   if (st) return st;
@@ -1825,7 +1825,7 @@ ftk_status ftk_track_cp_mesh(const ftk_mesh* m, const float* field, int64_t nt, 
   const long long S = 3 * nf + 2 * ne, NF = S * nt;
   const Alloc al = make_alloc(o, s);
   Scratch sc(al);
-  int* flag = sc.get<int>((size_t)NF);
+  unsigned char* flag = sc.get<unsigned char>((size_t)NF);
   long long* off = sc.get<long long>((size_t)NF);
   long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(NF));
   Ctl* dctl = sc.get<Ctl>(1);
@@ -1834,7 +1834,7 @@ ftk_status ftk_track_cp_mesh(const ftk_mesh* m, const float* field, int64_t nt, 
   const float qscale = std::ldexp(1.0f, o.quant_log2);
   HIP_TRY(ftk::launch_pm_test(m->xy, m->tri, m->edge, m->tri_edge, field, nv, nf, ne, (int)nt, qscale, flag,
                               &dctl->status, s));
-  HIP_TRY(ftk::launch_scan(flag, off, NF, &dctl->total, tmp, s));
+  HIP_TRY(ftk::launch_scan_u8(flag, off, NF, &dctl->total, tmp, s));
   Ctl h;
   st = read_ctl(&h, dctl, s);
   if (st) return st;

@@ -89,6 +89,9 @@ hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const
 // scan_tmp_elems(n) int64 values.
 size_t scan_tmp_elems(long long n);
 hipError_t launch_scan(const int* in, long long* out, long long n, long long* total, long long* tmp, hipStream_t s);
+// the same over byte counts (per-vertex or per-face counts below 256)
+hipError_t launch_scan_u8(const unsigned char* in, long long* out, long long n, long long* total, long long* tmp,
+                          hipStream_t s);
 
 // Trajectory post-processing (post.hip).
 hipError_t launch_traj_table(int n, const int64_t* dims_with_t, const long long* face_id, const long long* label,
@@ -136,32 +139,33 @@ hipError_t launch_order_place(int n, const int64_t* dims_with_t, const long long
 // vertices.  Per-vertex grids launch as (ceil(nx / 128), ny, nz * nt) blocks (ny, nz * nt <= 65535).
 // bits: ceil(nx / 64) * ny * nz * nt words of vertex sides, written by the count launch, read by the unite launch
 hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, float c, unsigned long long* bits,
-                            unsigned short* emask, int* hcnt, int* tcnt, unsigned* status, hipStream_t s);
+                            unsigned short* emask, unsigned char* hcnt, unsigned char* tcnt, unsigned* status,
+                            hipStream_t s);
 hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float c, const unsigned short* emask,
                            const long long* hoff, long long* edge_id, float* pos, unsigned* parent, hipStream_t s);
 // active vertices (a crossed pentachoron in their cube): flags + scan (scatter = false, *total = count), then the
 // ascending list (scatter = true)
-hipError_t launch_iso_active(const int* tcnt, long long V, int* flag, long long* off, long long* total,
+hipError_t launch_iso_active(const unsigned char* tcnt, long long V, unsigned char* flag, long long* off, long long* total,
                              long long* scan_tmp, long long* list, bool scatter, hipStream_t s);
 hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c,
                             const unsigned long long* bits, const long long* active, long long n_active,
-                            const unsigned short* emask, const long long* hoff, const int* tcnt,
+                            const unsigned short* emask, const long long* hoff, const unsigned char* tcnt,
                             const long long* toff, unsigned* parent, long long* tets, unsigned* status,
                             hipStream_t s);
 // Quantum vortex surfaces (vortex.hip): edge signs and positive-triangle masks (tmask, 50 bits) with per-vertex
 // counts; then emission of triangle ids, points and identity parents, and the pentachoron unions.  Grids as iso.
 hipError_t launch_vx_detect(const float* psi, int nx, int ny, int nz, int nt, float qscale, unsigned short* emask,
-                            unsigned long long* tmask, int* cnt, unsigned* status, hipStream_t s);
+                            unsigned long long* tmask, unsigned char* cnt, unsigned* status, hipStream_t s);
 hipError_t launch_vx_emit(const float* psi, int nx, int ny, int nz, int nt, float qscale,
                           const unsigned long long* tmask, const long long* hoff, long long* tri_id, float* pos,
                           unsigned* parent, hipStream_t s);
 // Critical points on an extruded triangle mesh (prism.hip): face tests over nt * S faces (flag), then emission and
 // the tetrahedron unions from the scanned flags.
 hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
-                          long long nv, long long nf, long long ne, int nt, float qscale, int* flag, unsigned* status,
-                          hipStream_t s);
+                          long long nv, long long nf, long long ne, int nt, float qscale, unsigned char* flag,
+                          unsigned* status, hipStream_t s);
 hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
-                          long long nv, long long nf, long long ne, int nt, float qscale, const int* flag,
+                          long long nv, long long nf, long long ne, int nt, float qscale, const unsigned char* flag,
                           const long long* off, long long* face_id, float* pos, unsigned* parent, unsigned* status,
                           hipStream_t s);
 // Type smoothing and run simplification along an order (head/heads: [n_hits] int / int64 scratch).

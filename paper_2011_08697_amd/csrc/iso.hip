@@ -154,7 +154,7 @@ __device__ __forceinline__ int pen_above(unsigned above, int ty) {
 }
 
 __global__ __launch_bounds__(kIsoBX) void iso_count(IsoGrid g, unsigned short* __restrict__ emask,
-                                                     int* __restrict__ hcnt, int* __restrict__ tcnt,
+                                                     unsigned char* __restrict__ hcnt, unsigned char* __restrict__ tcnt,
                                                      unsigned* __restrict__ status) {
   const int x = blockIdx.x * kIsoBX + threadIdx.x;
   const int y = blockIdx.y;
@@ -176,18 +176,18 @@ __global__ __launch_bounds__(kIsoBX) void iso_count(IsoGrid g, unsigned short* _
     }
   }
   emask[v] = (unsigned short)m;
-  hcnt[v] = __popc(m);
-  tcnt[v] = tets;
+  hcnt[v] = (unsigned char)__popc(m);
+  tcnt[v] = (unsigned char)tets;
 }
 
 // list of the vertices whose cube has crossed pentachora (about one in sixteen on smooth fields), so that the
 // pentachoron pass runs on busy lanes only
-__global__ void iso_active_flags(const int* __restrict__ tcnt, long long V, int* __restrict__ flag) {
+__global__ void iso_active_flags(const unsigned char* __restrict__ tcnt, long long V, unsigned char* __restrict__ flag) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < V) flag[v] = tcnt[v] > 0 ? 1 : 0;
 }
 
-__global__ void iso_active_list(const int* __restrict__ flag, const long long* __restrict__ off, long long V,
+__global__ void iso_active_list(const unsigned char* __restrict__ flag, const long long* __restrict__ off, long long V,
                                 long long* __restrict__ list) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < V && flag[v]) list[off[v]] = v;
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned sho
 __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* __restrict__ active,
                                                      long long n_active, const unsigned short* __restrict__ emask,
                                                      const long long* __restrict__ hoff,
-                                                     const int* __restrict__ tcnt, const long long* __restrict__ toff,
+                                                     const unsigned char* __restrict__ tcnt, const long long* __restrict__ toff,
                                                      unsigned* __restrict__ parent, long long* __restrict__ tets,
                                                      unsigned* __restrict__ status) {
   const long long a_i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -356,7 +356,8 @@ dim3 iso_grid(const IsoGrid& g) { return dim3((unsigned)((g.nx + kIsoBX - 1) / k
 }  // namespace
 
 hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, float c, unsigned long long* bits,
-                            unsigned short* emask, int* hcnt, int* tcnt, unsigned* status, hipStream_t s) {
+                            unsigned short* emask, unsigned char* hcnt, unsigned char* tcnt, unsigned* status,
+                            hipStream_t s) {
   const IsoGrid g{f, nx, ny, nz, nt, c, bits, (nx + 63) / 64};
   iso_bits<<<iso_grid(g), kIsoBX, 0, s>>>(g, bits, status);
   iso_count<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hcnt, tcnt, status);
@@ -370,12 +371,12 @@ hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float
   return hipGetLastError();
 }
 
-hipError_t launch_iso_active(const int* tcnt, long long V, int* flag, long long* off, long long* total,
+hipError_t launch_iso_active(const unsigned char* tcnt, long long V, unsigned char* flag, long long* off, long long* total,
                              long long* scan_tmp, long long* list, bool scatter, hipStream_t s) {
   const unsigned b = (unsigned)((V + 255) / 256);
   if (!scatter) {
     iso_active_flags<<<b, 256, 0, s>>>(tcnt, V, flag);
-    return launch_scan(flag, off, V, total, scan_tmp, s);
+    return launch_scan_u8(flag, off, V, total, scan_tmp, s);
   }
   iso_active_list<<<b, 256, 0, s>>>(flag, off, V, list);
   return hipGetLastError();
@@ -383,7 +384,7 @@ hipError_t launch_iso_active(const int* tcnt, long long V, int* flag, long long*
 
 hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c,
                             const unsigned long long* bits, const long long* active, long long n_active,
-                            const unsigned short* emask, const long long* hoff, const int* tcnt,
+                            const unsigned short* emask, const long long* hoff, const unsigned char* tcnt,
                             const long long* toff, unsigned* parent, long long* tets, unsigned* status,
                             hipStream_t s) {
   if (n_active == 0) return hipSuccess;

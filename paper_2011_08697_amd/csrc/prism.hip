@@ -31,8 +31,7 @@ struct PmMesh {
   float qscale;
 };
 
-// vertices (vertex, step offset) of local face f of a step, in global order; false for an interval face at the last
-// step
+// vertices (vertex, step offset) of local face f of a step, in global order
 __device__ __forceinline__ void pm_face(const PmMesh& m, long long f, int* v, int* dt) {
   if (f < m.nf) {
     const int* a = m.tri + 3 * f;
@@ -81,7 +80,7 @@ __device__ __forceinline__ unsigned pm_sos2(const long long* a, const long long*
   return 0u;
 }
 
-__global__ void pm_test(PmMesh m, int* __restrict__ flag, unsigned* __restrict__ status) {
+__global__ void pm_test(PmMesh m, unsigned char* __restrict__ flag, unsigned* __restrict__ status) {
   const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
   if (f >= m.S) return;
@@ -103,7 +102,7 @@ __global__ void pm_test(PmMesh m, int* __restrict__ flag, unsigned* __restrict__
   if (st && f < m.nf) atomicOr(status, st);
 }
 
-__global__ void pm_emit(PmMesh m, const int* __restrict__ flag, const long long* __restrict__ off,
+__global__ void pm_emit(PmMesh m, const unsigned char* __restrict__ flag, const long long* __restrict__ off,
                         long long* __restrict__ face_id, float* __restrict__ pos, unsigned* __restrict__ parent) {
   const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
@@ -143,7 +142,7 @@ __global__ void pm_emit(PmMesh m, const int* __restrict__ flag, const long long*
   parent[o] = (unsigned)o;
 }
 
-__global__ void pm_unite(PmMesh m, const int* __restrict__ flag, const long long* __restrict__ off,
+__global__ void pm_unite(PmMesh m, const unsigned char* __restrict__ flag, const long long* __restrict__ off,
                          unsigned* __restrict__ parent, unsigned* __restrict__ status) {
   const long long T = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
@@ -172,15 +171,15 @@ __global__ void pm_unite(PmMesh m, const int* __restrict__ flag, const long long
 }  // namespace
 
 hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
-                          long long nv, long long nf, long long ne, int nt, float qscale, int* flag, unsigned* status,
-                          hipStream_t s) {
+                          long long nv, long long nf, long long ne, int nt, float qscale, unsigned char* flag,
+                          unsigned* status, hipStream_t s) {
   const PmMesh m{xy, tri, edge, tri_edge, field, nv, nf, ne, nf + 2 * ne + 2 * nf, nt, qscale};
   pm_test<<<dim3((unsigned)((m.S + 255) / 256), (unsigned)nt), 256, 0, s>>>(m, flag, status);
   return hipGetLastError();
 }
 
 hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
-                          long long nv, long long nf, long long ne, int nt, float qscale, const int* flag,
+                          long long nv, long long nf, long long ne, int nt, float qscale, const unsigned char* flag,
                           const long long* off, long long* face_id, float* pos, unsigned* parent, unsigned* status,
                           hipStream_t s) {
   const PmMesh m{xy, tri, edge, tri_edge, field, nv, nf, ne, nf + 2 * ne + 2 * nf, nt, qscale};

@@ -1,5 +1,5 @@
-// scan.hip -- exclusive prefix sum of per-segment hit counts (int32 -> int64 offsets), the compaction step that
-// gives every punctured simplex its position in the face-id-sorted output.
+// scan.hip -- exclusive prefix sum of per-segment hit counts (int32 or byte counts -> int64 offsets), the compaction
+// step that gives every punctured simplex its position in the face-id-sorted output.
 #include "common.h"
 #include "internal.h"
 
@@ -32,7 +32,8 @@ __device__ __forceinline__ long long block_excl_scan(long long v, long long* tot
   return before + x - v;
 }
 
-__global__ __launch_bounds__(kThreads) void scan_reduce(const int* __restrict__ in, long long n,
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scan_reduce(const T* __restrict__ in, long long n,
                                                         long long* __restrict__ tmp) {
   const long long base = (long long)blockIdx.x * kTile + threadIdx.x * kItems;
   long long s = 0;
@@ -59,7 +60,8 @@ __global__ __launch_bounds__(kThreads) void scan_blocks(long long* __restrict__ 
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ __launch_bounds__(kThreads) void scan_down(const int* __restrict__ in, long long* __restrict__ out,
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scan_down(const T* __restrict__ in, long long* __restrict__ out,
                                                       long long n, const long long* __restrict__ tmp) {
   const long long base = (long long)blockIdx.x * kTile + threadIdx.x * kItems;
   int v[kItems];
@@ -81,13 +83,25 @@ __global__ __launch_bounds__(kThreads) void scan_down(const int* __restrict__ in
 
 size_t scan_tmp_elems(long long n) { return (size_t)((n + kTile - 1) / kTile) + 1; }
 
-hipError_t launch_scan(const int* in, long long* out, long long n, long long* total, long long* tmp, hipStream_t s) {
+namespace {
+template <typename T>
+hipError_t scan_any(const T* in, long long* out, long long n, long long* total, long long* tmp, hipStream_t s) {
   long long nb = (n + kTile - 1) / kTile;
   if (nb == 0) nb = 1;
-  scan_reduce<<<(unsigned)nb, kThreads, 0, s>>>(in, n, tmp);
+  scan_reduce<T><<<(unsigned)nb, kThreads, 0, s>>>(in, n, tmp);
   scan_blocks<<<1, kThreads, 0, s>>>(tmp, nb, total);
-  scan_down<<<(unsigned)nb, kThreads, 0, s>>>(in, out, n, tmp);
+  scan_down<T><<<(unsigned)nb, kThreads, 0, s>>>(in, out, n, tmp);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_scan(const int* in, long long* out, long long n, long long* total, long long* tmp, hipStream_t s) {
+  return scan_any<int>(in, out, n, total, tmp, s);
+}
+
+hipError_t launch_scan_u8(const unsigned char* in, long long* out, long long n, long long* total, long long* tmp,
+                          hipStream_t s) {
+  return scan_any<unsigned char>(in, out, n, total, tmp, s);
 }
 
 }  // namespace ftk

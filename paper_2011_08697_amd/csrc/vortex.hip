@@ -96,7 +96,8 @@ __global__ __launch_bounds__(kVxBX) void vx_edges(VxGrid g, unsigned short* __re
 }
 
 __global__ __launch_bounds__(kVxBX) void vx_tris(VxGrid g, const unsigned short* __restrict__ emask,
-                                                  unsigned long long* __restrict__ tmask, int* __restrict__ cnt) {
+                                                  unsigned long long* __restrict__ tmask,
+                                                  unsigned char* __restrict__ cnt) {
   const int x = blockIdx.x * kVxBX + threadIdx.x;
   const int y = blockIdx.y;
   const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(kVxBX) void vx_tris(VxGrid g, const unsigned short*
     if (s12 == s01 && s02 != s01) m |= 1ull << ty;
   }
   tmask[v] = m;
-  cnt[v] = __popcll(m);
+  cnt[v] = (unsigned char)__popcll(m);
 }
 
 __global__ __launch_bounds__(kVxBX) void vx_emit(VxGrid g, const unsigned long long* __restrict__ tmask,
@@ -283,7 +284,7 @@ dim3 vx_grid(const VxGrid& g) {
 }  // namespace
 
 hipError_t launch_vx_detect(const float* psi, int nx, int ny, int nz, int nt, float qscale, unsigned short* emask,
-                            unsigned long long* tmask, int* cnt, unsigned* status, hipStream_t s) {
+                            unsigned long long* tmask, unsigned char* cnt, unsigned* status, hipStream_t s) {
   const VxGrid g{psi, nx, ny, nz, nt, qscale};
   vx_edges<<<vx_grid(g), kVxBX, 0, s>>>(g, emask, status);
   vx_tris<<<vx_grid(g), kVxBX, 0, s>>>(g, emask, tmask, cnt);
