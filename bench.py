@@ -205,7 +205,7 @@ def bench_iso(args, F, synth, dev):
     ms = el * 1e3 / args.steps
     edges = F.edge_count(dims)
     V = int(np.prod(dims))
-    alg = 4 * V + 32 * nh + 32 * ntets  # field in; edge id, position and label per crossing; 4 indices per tet
+    alg = 4 * V + 32 * nh + 16 * ntets  # field in; edge id, position and label per crossing; 4 int32 per tet
     line = {
         "metric": "spacetime edges tested/s (isovolume tracking)", "value": round(edges / (ms * 1e-3), 1),
         "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),

@@ -270,7 +270,8 @@ ftk_status ftk_autotune_cp2d(const float* field, ftk_field_kind kind, int64_t nx
  * on its side) or three (two vertices: the prism of crossed edges split along monotone paths in vertex order).
  * Outputs are allocated through opt->alloc (or hipMallocAsync on stream); release with ftk_iso_result_free.
  * Synchronises the stream twice (hit and tetrahedron counts, component count).  Every dimension >= 2; ny and
- * nz * nt at most 65535.  FTK_ERR_NONFINITE for NaN/Inf in the field; FTK_ERR_CAPACITY beyond 2^32 - 2 crossings.
+ * nz * nt at most 65535.  FTK_ERR_NONFINITE for NaN/Inf in the field; FTK_ERR_CAPACITY beyond 2^31 - 1 crossings
+ * (tetrahedra hold 32-bit indices).
  */
 typedef struct {
   int64_t n_hits;       /* crossed edges */
@@ -279,7 +280,7 @@ typedef struct {
   int64_t* edge_id;     /* [n_hits] ascending */
   float* pos;           /* [n_hits][4] intersection point (x, y, z, t): p + mu e(M), mu = (c - f(p)) / (f(q) - f(p)) */
   int64_t* label;       /* [n_hits] smallest edge id of the isovolume */
-  int64_t* tets;        /* [n_tets][4] indices into the hit arrays, by pentachoron (g * 24 + type) */
+  int32_t* tets;        /* [n_tets][4] indices into the hit arrays, by pentachoron (g * 24 + type) */
 } ftk_iso_result;
 
 ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t nz, int64_t nt, float isovalue,

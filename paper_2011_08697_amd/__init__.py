@@ -430,7 +430,7 @@ def track_iso3d(field, isovalue):
                 edge_id=pool.take(r.edge_id, torch.int64, (max(nh, 1),))[:nh],
                 pos=pool.take(r.pos, torch.float32, (max(nh, 1), 4))[:nh],
                 label=pool.take(r.label, torch.int64, (max(nh, 1),))[:nh],
-                tets=pool.take(r.tets, torch.int64, (max(nt4, 1), 4))[:nt4])
+                tets=pool.take(r.tets, torch.int32, (max(nt4, 1), 4))[:nt4])
 
 
 def track_vortex3d(psi, **opts):

@@ -1588,7 +1588,7 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   st = decode_status(h.status);
   if (st) return st;
   const long long nh = h.total, ntets = (long long)h.cnt[ftk::CNT_LIST], nact = (long long)h.cnt[ftk::CNT_WORK];
-  if (nh >= 0xffffffffll) return fail(FTK_ERR_CAPACITY, "%lld crossed edges exceed the 32-bit union-find", nh);
+  if (nh > 0x7fffffffll) return fail(FTK_ERR_CAPACITY, "%lld crossed edges exceed the 32-bit tetrahedron indices", nh);
   ftk_iso_result r;
   std::memset(&r, 0, sizeof(r));
   r.n_hits = nh;
@@ -1596,7 +1596,7 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   r.edge_id = (int64_t*)al.get(sizeof(int64_t) * (size_t)(nh > 0 ? nh : 1));
   r.pos = (float*)al.get(sizeof(float) * 4 * (size_t)(nh > 0 ? nh : 1));
   r.label = (int64_t*)al.get(sizeof(int64_t) * (size_t)(nh > 0 ? nh : 1));
-  r.tets = (int64_t*)al.get(sizeof(int64_t) * 4 * (size_t)(ntets > 0 ? ntets : 1));
+  r.tets = (int32_t*)al.get(sizeof(int32_t) * 4 * (size_t)(ntets > 0 ? ntets : 1));
   unsigned* parent = sc.get<unsigned>((size_t)(nh > 0 ? nh : 1));
   long long* active = sc.get<long long>((size_t)(nact > 0 ? nact : 1));
   if (!r.edge_id || !r.pos || !r.label || !r.tets || !parent || !active) {
@@ -1611,7 +1611,7 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
       he = ftk::launch_iso_active(tcnt, V, hcnt, aoff, nullptr, nullptr, active, true, s);
     if (he == hipSuccess)
       he = ftk::launch_iso_unite(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, bits, active, nact, emask, hoff,
-                                 tcnt, toff, parent, (long long*)r.tets, &dctl->status, s);
+                                 tcnt, toff, parent, (int*)r.tets, &dctl->status, s);
     if (he == hipSuccess)
       he = ftk::launch_uf_label(parent, (const long long*)r.edge_id, (long long*)r.label, nh, dctl->cnt, s);
   }

@@ -150,7 +150,7 @@ hipError_t launch_iso_active(const unsigned char* tcnt, long long V, unsigned ch
 hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c,
                             const unsigned long long* bits, const long long* active, long long n_active,
                             const unsigned short* emask, const long long* hoff, const unsigned char* tcnt,
-                            const long long* toff, unsigned* parent, long long* tets, unsigned* status,
+                            const long long* toff, unsigned* parent, int* tets, unsigned* status,
                             hipStream_t s);
 // Quantum vortex surfaces (vortex.hip): edge signs and positive-triangle masks (tmask, 50 bits) with per-vertex
 // counts; then emission of triangle ids, points and identity parents, and the pentachoron unions.  Grids as iso.

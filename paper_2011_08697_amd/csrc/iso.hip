@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* 
                                                      long long n_active, const unsigned short* __restrict__ emask,
                                                      const long long* __restrict__ hoff,
                                                      const unsigned char* __restrict__ tcnt, const long long* __restrict__ toff,
-                                                     unsigned* __restrict__ parent, long long* __restrict__ tets,
+                                                     unsigned* __restrict__ parent, int* __restrict__ tets,
                                                      unsigned* __restrict__ status) {
   const long long a_i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (a_i >= n_active) return;
@@ -337,15 +337,15 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* 
       atomicOr(status, ST_INVARIANT);
       return;
     }
-    long long* T = tets + o * 4;
+    int* T = tets + o * 4;
     if (nm == 1) {
-      for (int q = 0; q < 4; ++q) T[q] = pe(0, q);
+      for (int q = 0; q < 4; ++q) T[q] = (int)pe(0, q);
     } else {
       const long long p1m1 = pe(0, 0), p1m2 = pe(0, 1), p1m3 = pe(0, 2);
       const long long p2m1 = pe(1, 0), p2m2 = pe(1, 1), p2m3 = pe(1, 2);
-      T[0] = p1m1; T[1] = p1m2; T[2] = p1m3; T[3] = p2m3;
-      T[4] = p1m1; T[5] = p1m2; T[6] = p2m2; T[7] = p2m3;
-      T[8] = p1m1; T[9] = p2m1; T[10] = p2m2; T[11] = p2m3;
+      T[0] = (int)p1m1; T[1] = (int)p1m2; T[2] = (int)p1m3; T[3] = (int)p2m3;
+      T[4] = (int)p1m1; T[5] = (int)p1m2; T[6] = (int)p2m2; T[7] = (int)p2m3;
+      T[8] = (int)p1m1; T[9] = (int)p2m1; T[10] = (int)p2m2; T[11] = (int)p2m3;
     }
     o += nt_here;
   }
@@ -385,7 +385,7 @@ hipError_t launch_iso_active(const unsigned char* tcnt, long long V, unsigned ch
 hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c,
                             const unsigned long long* bits, const long long* active, long long n_active,
                             const unsigned short* emask, const long long* hoff, const unsigned char* tcnt,
-                            const long long* toff, unsigned* parent, long long* tets, unsigned* status,
+                            const long long* toff, unsigned* parent, int* tets, unsigned* status,
                             hipStream_t s) {
   if (n_active == 0) return hipSuccess;
   const IsoGrid g{f, nx, ny, nz, nt, c, bits, (nx + 63) / 64};
