@@ -43,7 +43,7 @@ typedef enum {
   FTK_ERR_ARG = 1,        /* bad dimensions, null pointer, unsupported kind/option */
   FTK_ERR_NONFINITE = 2,  /* NaN or Inf in the input */
   FTK_ERR_RANGE = 3,      /* a quantised vector component beyond the exact-arithmetic bound */
-  FTK_ERR_CAPACITY = 4,   /* more punctured simplices than the index type holds (2^32 - 2) */
+  FTK_ERR_CAPACITY = 4,   /* more hits than the 32-bit index types hold (each entry point states its limit) */
   FTK_ERR_OOM = 5,        /* an allocation failed (device memory or the caller's allocator) */
   FTK_ERR_HIP = 6,        /* a HIP runtime call failed */
   FTK_ERR_INVARIANT = 7,  /* a cell with 1 or >= 3 punctured sides: impossible under SoS; internal error */
