@@ -129,7 +129,8 @@ void ftk_default_options(ftk_options* opt);
  *   hipMallocAsync); release them with ftk_result_free using the same options.
  * Scalar input: the gradient (central differences inside, one-sided at the first/last index, float32) is
  * quantised to integers q = rint(g * 2^quant_log2); vector input is quantised directly.  Errors:
- * FTK_ERR_NONFINITE, FTK_ERR_RANGE (|q| >= 2^62), FTK_ERR_ARG, FTK_ERR_OOM, FTK_ERR_HIP, FTK_ERR_CAPACITY.
+ * FTK_ERR_NONFINITE, FTK_ERR_RANGE (|q| >= 2^62), FTK_ERR_ARG, FTK_ERR_OOM, FTK_ERR_HIP, FTK_ERR_CAPACITY (more
+ * than 2^32 - 2 punctured simplices).
  */
 ftk_status ftk_track_cp2d(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,
                           const ftk_options* opt, ftk_stream_t stream, ftk_cp_result* out);
