@@ -86,8 +86,16 @@ typedef struct {
   ftk_free_fn free;    /* NULL: hipFreeAsync on the stream */
   void* alloc_ctx;
   int32_t profile;     /* 1: record HIP events around each kernel group on `stream`; times land in stats */
-  int32_t reserved;
+  int32_t debug;       /* 0 in normal use; FTK_DEBUG_* test hooks of the 2D tracker (below) */
 } ftk_options;
+
+/* Test hooks (ftk_options.debug), for tests of paths that realistic inputs rarely reach.  FTK_DEBUG_SMALL_LDS runs
+ * the 2D emission with tiny workgroup-local capacities (union-find chunk and link stage), so that tile steps overflow
+ * them and take the global-list paths; results are unchanged.  FTK_DEBUG_INVARIANT makes the 2D emission report a
+ * cell with a wrong punctured-side count at time step (debug >> 8), so that tests can check how the error reaches
+ * the caller (every form returns FTK_ERR_INVARIANT). */
+#define FTK_DEBUG_SMALL_LDS 1
+#define FTK_DEBUG_INVARIANT 2
 
 typedef struct {
   int64_t simplices_tested; /* n-simplices tested (the throughput numerator) */
@@ -262,7 +270,7 @@ ftk_status ftk_autotune_cp2d(const float* field, ftk_field_kind kind, int64_t nx
                              const ftk_options* opt, ftk_stream_t stream, ftk_options* tuned);
 
 /*
- * Isovolume tracking in a 3D scalar series (Sec. 5.1, two passes on the spacetime mesh; Sec. 5.2 robustness).
+ * Isovolume tracking in a 3D scalar series (Sec. 6.1, two passes on the spacetime mesh; Sec. 6.2 robustness).
  * field: device pointer, contiguous binary32 [nt][nz][ny][nx]; isovalue c (finite).  An edge anchored at vertex p
  * (t-major index g) with axis mask M (1..15; x = 1, y = 2, z = 4, t = 8) joins p and p + e(M) and has the id
  * g * 15 + (M - 1).  It crosses the level set when its two vertices lie on different sides, a value equal to c
@@ -293,7 +301,7 @@ void ftk_iso_result_free(ftk_iso_result* r, const ftk_options* opt, ftk_stream_t
 int64_t ftk_edge_count(const int64_t* dims_with_t);
 
 /*
- * Quantum vortex surface tracking in a 3D complex series (Sec. 6.1, two passes on the spacetime mesh).
+ * Quantum vortex surface tracking in a 3D complex series (Sec. 5.1, two passes on the spacetime mesh).
  * psi: device pointer, contiguous binary32 [nt][2][nz][ny][nx] (real and imaginary planes per step).  A spacetime
  * triangle anchored at vertex p (t-major index g) with axis masks (M1, M2) (x = 1, y = 2, z = 4, t = 8; 50 types in
  * lexicographic order) has the vertices p, p + e(M1), p + e(M1|M2) and the id g * 50 + type.  It is positive when

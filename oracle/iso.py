@@ -1,7 +1,7 @@
 """Isovolume tracking oracle (test infrastructure only, like the rest of oracle/): plain numpy, binary64.
 
-Written from the two-pass isovolume reconstruction (Sec. 5.1, Alg. 1 right column) on the regular simplicial
-spacetime mesh of a 3D scalar series (Sec. 3.3), with the robustness rule of Sec. 5.2:
+Written from the two-pass isovolume reconstruction (Sec. 6.1, Alg. 1 right column) on the regular simplicial
+spacetime mesh of a 3D scalar series (Sec. 3.3), with the robustness rule of Sec. 6.2:
   * mesh: vertices (x, y, z, t), t-major index g = ((t nz + z) ny + y) nx + x; an edge anchored at p with axis mask
     M (1..15; bits x = 1, y = 2, z = 4, t = 8) joins p and p + e(M); its id is g(p) * 15 + (M - 1) (edge types in
     increasing mask order); a pentachoron anchored at p with axis order (s1, s2, s3, s4) has the chain vertices
@@ -12,7 +12,7 @@ spacetime mesh of a 3D scalar series (Sec. 3.3), with the robustness rule of Sec
   * intersection point: p + mu e(M) with mu = (c - f(p)) / (f(q) - f(p));
   * pentachoron pass: the crossed edges of every pentachoron are united; labels are the smallest edge id of each
     component;
-  * tessellation (Sec. 5.1 case analysis): with one vertex on its side (case I) the crossed edges are the four
+  * tessellation (Sec. 6.1 case analysis): with one vertex on its side (case I) the crossed edges are the four
     edges from that vertex and form one tetrahedron; with two (case II) the six crossed edges form a prism
     (pair x triple), split into three tetrahedra along monotone paths of the pair and triple in chain order
     (staircase triangulation).

@@ -1,12 +1,12 @@
 """Quantum vortex surface tracking oracle (test infrastructure only, like the rest of oracle/): plain numpy and the
 oracle's exact predicate, one triangle at a time.
 
-Written from the two-pass vortex surface reconstruction (Sec. 6.1, Alg. 1 middle column) on the regular simplicial
+Written from the two-pass vortex surface reconstruction (Sec. 5.1, Alg. 1 middle column) on the regular simplicial
 spacetime mesh of a 3D complex series (Sec. 3.3):
   * a spacetime triangle (2-simplex of the 4D mesh) anchored at p with axis masks (M1, M2) has the vertices p,
     p + e(M1), p + e(M1|M2) (bits x = 1, y = 2, z = 4, t = 8); its id is g(p) * 50 + type, types in lexicographic
     order of (M1, M2), g the t-major vertex index;
-  * the contour-integral test (Eq. 1 and Sec. 6.1): the sum of the phase changes along the three edges, each taken
+  * the contour-integral test (Eq. 1 and Sec. 5.1): the sum of the phase changes along the three edges, each taken
     modulo 2 pi into (-pi, pi], is +-2 pi.  A straight segment from psi_i to psi_j in the complex plane that misses
     0 turns by exactly that wrapped phase change as seen from 0, so the sum is 2 pi times the winding number of the
     image triangle (psi_0, psi_1, psi_2) around 0: the test asks whether 0 lies inside the image triangle, i.e. the

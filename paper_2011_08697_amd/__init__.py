@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
     _fields_ = [("quant_log2", ctypes.c_int32), ("precision", ctypes.c_int32), ("outputs", ctypes.c_uint32),
                 ("tile_y", ctypes.c_int32), ("slab_depth", ctypes.c_int32),
                 ("alloc", _ALLOC_FN), ("free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("debug", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -214,11 +214,11 @@ class _TorchPool:
         return t.view(dtype)[:n].view(*shape) if n else t.view(dtype)[:0].view(*shape)
 
 
-def _options(pool, quant_log2=20, precision=0, outputs=OUT_DEFAULT, tile_y=0, slab_depth=0, profile=0):
+def _options(pool, quant_log2=20, precision=0, outputs=OUT_DEFAULT, tile_y=0, slab_depth=0, profile=0, debug=0):
     o = Options()
     lib().ftk_default_options(ctypes.byref(o))
     o.quant_log2, o.precision, o.outputs = quant_log2, precision, outputs
-    o.tile_y, o.slab_depth, o.profile = tile_y, slab_depth, profile
+    o.tile_y, o.slab_depth, o.profile, o.debug = tile_y, slab_depth, profile, debug
     if pool is not None:
         o.alloc, o.free = pool._alloc, pool._free
     return o

@@ -114,7 +114,8 @@ void cache_put(void* p, size_t size) {
   g_cache.push_back(CachedBlock{p, size, dev});
 }
 
-// Scratch list released (to the cache) on scope exit.  Callers synchronise their stream before returning.
+// Scratch list released on scope exit: to the caller's allocator when the options carry one, else to the block
+// cache.  Callers synchronise their stream before returning.
 struct Scratch {
   static constexpr int kMax = 32;
   const Alloc& al;  // must outlive the Scratch (declare the Alloc as a named local first)
@@ -126,7 +127,13 @@ struct Scratch {
   T* get(size_t count) {
     if (n >= kMax) return nullptr;  // callers report a failed scratch allocation
     size_t got = 0;
-    void* q = cache_get(count * sizeof(T) + 16, &got);
+    void* q = nullptr;
+    if (al.a) {  // the caller's allocator serves scratch too (and may refuse it)
+      got = count * sizeof(T) + 16;
+      q = al.get(got);
+    } else {
+      q = cache_get(count * sizeof(T) + 16, &got);
+    }
     if (q) {
       p[n] = q;
       sz[n] = got;
@@ -136,7 +143,12 @@ struct Scratch {
   }
   ~Scratch() {
     if (n > 0) (void)hipStreamSynchronize(al.s);  // no-op on the normal path (already synchronised)
-    for (int i = n - 1; i >= 0; --i) cache_put(p[i], sz[i]);
+    for (int i = n - 1; i >= 0; --i) {
+      if (al.a)
+        al.put(p[i]);
+      else
+        cache_put(p[i], sz[i]);
+    }
   }
 };
 
@@ -169,8 +181,8 @@ struct Phases {
 
 // Control block read back by the host.
 struct Ctl {
-  unsigned status;
-  unsigned pad;
+  unsigned status;   // status bits of the kernels (the streaming form: of its emissions, kept from create to finish)
+  unsigned dstatus;  // status bits of the streaming form's per-push detection (cleared and read by every push)
   long long total;
   unsigned long long cnt[ftk::CNT_N];
 };
@@ -292,6 +304,12 @@ void ftk_result_free(ftk_cp_result* r, const ftk_options* opt, ftk_stream_t stre
 // ---------------------------------------------------------------------------------------------------------------
 namespace ftk {
 
+// Test hooks of ftk_options.debug (FTK_DEBUG_*), carried into the 2D kernels.
+void set_debug(Grid2& g, const ftk_options& o) {
+  g.debug = o.debug & 0xFF;
+  g.debug_step = (o.debug & FTK_DEBUG_INVARIANT) ? (int)((unsigned)o.debug >> 8) : -1;
+}
+
 ftk_status validate_options(const ftk_options& o) {
   if (o.quant_log2 < 0 || o.quant_log2 > 40) return fail(FTK_ERR_ARG, "quant_log2 must be in [0, 40]");
   if (o.precision != 0 && o.precision != 1) return fail(FTK_ERR_ARG, "precision must be 0 or 1");
@@ -350,10 +368,74 @@ static void tuned_tiles2(const ftk_options& o, int kind, long long nx, long long
   if (*tt > nt) *tt = nt;
 }
 
-ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,
-                        const ftk_options& o, hipStream_t s, ftk_cp_result* out) {
-  const Alloc al = make_alloc(o, s);
-  Scratch sc(al);
+// Byte offsets of several arrays carved from one region (each 256-byte aligned).
+struct Carve {
+  size_t total = 0;
+  template <typename T>
+  size_t add(size_t count) {
+    const size_t at = total;
+    total += (count * sizeof(T) + 16 + 255) & ~size_t(255);
+    return at;
+  }
+};
+
+// Where a 2D tracking call takes its device memory: two scratch regions (group 0 before detection: masks, counts,
+// offsets, scan temporaries, control block; group 1 once the hit count is known: union-find parents and the edge
+// list) and the output arrays.
+struct Mem2 {
+  virtual ~Mem2() {}
+  virtual char* scratch(int group, size_t bytes) = 0;  // null: refused (status from scratch_error)
+  virtual ftk_status scratch_error(int group, size_t bytes) = 0;
+  virtual ftk_status outputs(ftk_cp_result& r, long long nh, unsigned outs) = 0;
+  virtual void drop_outputs(ftk_cp_result& r) = 0;
+};
+
+// The library's own memory: scratch from the caller's allocator hooks when given, else from the block cache;
+// outputs from the hooks or the stream-ordered HIP allocator.
+struct OwnMem2 : Mem2 {
+  const ftk_options& o;
+  hipStream_t s;
+  const Alloc al;
+  Scratch sc;
+  OwnMem2(const ftk_options& opt, hipStream_t st) : o(opt), s(st), al(make_alloc(opt, st)), sc(al) {}
+  char* scratch(int, size_t bytes) override { return sc.get<char>(bytes); }
+  ftk_status scratch_error(int group, size_t bytes) override {
+    return fail(FTK_ERR_OOM, "scratch allocation failed (%zu bytes, %s)", bytes,
+                group == 0 ? "detection" : "union-find");
+  }
+  ftk_status outputs(ftk_cp_result& r, long long nh, unsigned outs) override {
+    r.face_id = (int64_t*)al.get(sizeof(int64_t) * nh);
+    if (outs & FTK_OUT_POS) r.pos = (float*)al.get(sizeof(float) * 3 * nh);
+    if (outs & FTK_OUT_MU) r.mu = (float*)al.get(sizeof(float) * 3 * nh);
+    if (outs & FTK_OUT_TYPE) r.type = (uint8_t*)al.get(nh);
+    if (outs & FTK_OUT_FLAGS) r.flags = (uint8_t*)al.get(nh);
+    if (outs & FTK_OUT_LABEL) r.label = (int64_t*)al.get(sizeof(int64_t) * nh);
+    const bool oom = !r.face_id || ((outs & FTK_OUT_POS) && !r.pos) || ((outs & FTK_OUT_MU) && !r.mu) ||
+                     ((outs & FTK_OUT_TYPE) && !r.type) || ((outs & FTK_OUT_FLAGS) && !r.flags) ||
+                     ((outs & FTK_OUT_LABEL) && !r.label);
+    if (oom) {
+      drop_outputs(r);
+      return fail(FTK_ERR_OOM, "output allocation failed (%lld hits)", nh);
+    }
+    return FTK_OK;
+  }
+  void drop_outputs(ftk_cp_result& r) override { ftk_result_free(&r, &o, (ftk_stream_t)s); }
+};
+
+__global__ void zero_words(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Clears the control block with a kernel (no memset node, so the sequence is safe under stream capture too).
+hipError_t clear_ctl(Ctl* d, hipStream_t s) {
+  constexpr int n = (int)(sizeof(Ctl) / sizeof(unsigned));
+  zero_words<<<1, 64, 0, s>>>((unsigned*)d, n);
+  return hipGetLastError();
+}
+
+ftk_status track2d_core(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,
+                        const ftk_options& o, hipStream_t s, Mem2& mem, ftk_cp_result* out) {
   Grid2 g;
   g.f = field;
   g.kind = (int)kind;
@@ -367,16 +449,24 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
   g.t_end = (int)nt;
   g.f_ring = 0;
   g.m_ring = 0;
+  set_debug(g, o);
   const long long V = (long long)nx * ny * nt;
   const long long nseg = (long long)nt * ny * g.nxt;
 
-  uint16_t* masks = sc.get<uint16_t>((size_t)V);
-  int* seg_cnt = sc.get<int>((size_t)nseg);
-  long long* seg_off = sc.get<long long>((size_t)nseg);
-  long long* scan_tmp = sc.get<long long>(scan_tmp_elems(nseg));
-  Ctl* dctl = sc.get<Ctl>(1);
-  if (!masks || !seg_cnt || !seg_off || !scan_tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
-  HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+  Carve c0;
+  const size_t o_masks = c0.add<uint16_t>((size_t)V);
+  const size_t o_cnt = c0.add<int>((size_t)nseg);
+  const size_t o_off = c0.add<long long>((size_t)nseg);
+  const size_t o_tmp = c0.add<long long>(scan_tmp_elems(nseg));
+  const size_t o_ctl = c0.add<Ctl>(1);
+  char* b0 = mem.scratch(0, c0.total);
+  if (!b0) return mem.scratch_error(0, c0.total);
+  uint16_t* masks = (uint16_t*)(b0 + o_masks);
+  int* seg_cnt = (int*)(b0 + o_cnt);
+  long long* seg_off = (long long*)(b0 + o_off);
+  long long* scan_tmp = (long long*)(b0 + o_tmp);
+  Ctl* dctl = (Ctl*)(b0 + o_ctl);
+  HIP_TRY(clear_ctl(dctl, s));
 
   int ty, tt;
   tuned_tiles2(o, g.kind, nx, ny, g.nt, &ty, &tt);
@@ -394,7 +484,7 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
   if (h.status & ST_NONFINITE) return decode_status(h.status);
   if (h.status & ST_WIDE) {
     wide = true;
-    HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
+    HIP_TRY(clear_ctl(dctl, s));
     ph.mark(0);
     HIP_TRY(launch_detect2d(g, ty, tt, true, masks, seg_cnt, &dctl->status, s));
     ph.mark(1);
@@ -411,25 +501,25 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
     return fail(FTK_ERR_CAPACITY, "%lld punctured simplices exceed the 32-bit hit index", nh);
   }
 
+  Carve c1;
+  const size_t o_parent = c1.add<unsigned>((size_t)nh);
+  const size_t o_work = c1.add<uint2>((size_t)nh * 2);
+  char* b1 = mem.scratch(1, c1.total);
+  if (!b1) {
+    out->n_hits = nh;
+    return mem.scratch_error(1, c1.total);
+  }
+  unsigned* parent = (unsigned*)(b1 + o_parent);
+  uint2* work = (uint2*)(b1 + o_work);
+
   ftk_cp_result r;
   std::memset(&r, 0, sizeof(r));
   r.n = 2;
   r.n_hits = nh;
-  const unsigned outs = o.outputs;
-  r.face_id = (int64_t*)al.get(sizeof(int64_t) * nh);
-  if (outs & FTK_OUT_POS) r.pos = (float*)al.get(sizeof(float) * 3 * nh);
-  if (outs & FTK_OUT_MU) r.mu = (float*)al.get(sizeof(float) * 3 * nh);
-  if (outs & FTK_OUT_TYPE) r.type = (uint8_t*)al.get(nh);
-  if (outs & FTK_OUT_FLAGS) r.flags = (uint8_t*)al.get(nh);
-  if (outs & FTK_OUT_LABEL) r.label = (int64_t*)al.get(sizeof(int64_t) * nh);
-  unsigned* parent = sc.get<unsigned>((size_t)nh);
-  uint2* work = sc.get<uint2>((size_t)nh * 2);
-  bool oom = !r.face_id || !parent || !work || ((outs & FTK_OUT_POS) && !r.pos) || ((outs & FTK_OUT_MU) && !r.mu) ||
-             ((outs & FTK_OUT_TYPE) && !r.type) || ((outs & FTK_OUT_FLAGS) && !r.flags) ||
-             ((outs & FTK_OUT_LABEL) && !r.label);
-  if (oom) {
-    ftk_result_free(&r, &o, (ftk_stream_t)s);
-    return fail(FTK_ERR_OOM, "output allocation failed (%lld hits)", nh);
+  st = mem.outputs(r, nh, o.outputs);
+  if (st) {
+    if (st == FTK_ERR_CAPACITY) out->n_hits = nh;
+    return st;
   }
   Out2 od;
   od.gbase = 0;
@@ -453,13 +543,13 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
   }
   ph.mark(5);
   if (he != hipSuccess) {
-    ftk_result_free(&r, &o, (ftk_stream_t)s);
+    mem.drop_outputs(r);
     return fail(FTK_ERR_HIP, "kernel launch: %s", hipGetErrorString(he));
   }
   st = read_ctl(&h, dctl, s);
   if (!st) st = decode_status(h.status);
   if (st) {
-    ftk_result_free(&r, &o, (ftk_stream_t)s);
+    mem.drop_outputs(r);
     return st;
   }
   r.n_trajectories = (long long)h.cnt[CNT_TRAJ];
@@ -475,6 +565,12 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
   r.stats.t_link_ms = ph.ms(4, 5);
   *out = r;
   return FTK_OK;
+}
+
+ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,
+                        const ftk_options& o, hipStream_t s, ftk_cp_result* out) {
+  OwnMem2 mem(o, s);
+  return track2d_core(field, kind, nx, ny, nt, o, s, mem, out);
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -644,6 +740,7 @@ ftk_status track2d_batched_impl(int nser, const float* const* fields, const int6
     g.t_end = g.nt;
     g.f_ring = 0;
     g.m_ring = 0;
+    set_debug(g, o);
     mask_off[i] = Vtot;
     seg_start[i] = Stot;
     Vtot += (long long)nx[i] * ny[i] * nt[i];
@@ -924,6 +1021,7 @@ static Grid2 tracker_grid(ftk_tracker* h, int t_begin, int nt) {
   g.t_end = t_begin + 1;
   g.f_ring = 3;
   g.m_ring = 3;
+  set_debug(g, h->o);
   return g;
 }
 
@@ -939,10 +1037,10 @@ static ftk_status tracker_detect(ftk_tracker* h, int p, int nt) {
   int ty = h->o.tile_y ? h->o.tile_y : 16;
   for (int pass = 0; pass < 2; ++pass) {
     const bool wide = pass == 1;
-    HIP_TRY(hipMemsetAsync(&dctl->status, 0, sizeof(unsigned), h->s));
-    HIP_TRY(launch_detect2d(g, ty, 1, wide, h->mring, h->cring, &dctl->status, h->s));
+    HIP_TRY(hipMemsetAsync(&dctl->dstatus, 0, sizeof(unsigned), h->s));
+    HIP_TRY(launch_detect2d(g, ty, 1, wide, h->mring, h->cring, &dctl->dstatus, h->s));
     unsigned st = 0;
-    HIP_TRY(hipMemcpyAsync(&st, &dctl->status, sizeof(unsigned), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipMemcpyAsync(&st, &dctl->dstatus, sizeof(unsigned), hipMemcpyDeviceToHost, h->s));
     HIP_TRY(hipStreamSynchronize(h->s));
     if (st & ST_NONFINITE) return decode_status(st);
     if (st & ST_RANGE) return decode_status(st);
@@ -1932,6 +2030,7 @@ extern "C" ftk_status ftk_autotune_cp2d(const float* field, ftk_field_kind kind,
   g.t_end = (int)nt;
   g.f_ring = 0;
   g.m_ring = 0;
+  set_debug(g, o);
   const long long V = (long long)nx * ny * nt, nseg = (long long)nt * ny * g.nxt;
   uint16_t* masks = sc.get<uint16_t>((size_t)V);
   int* seg_cnt = sc.get<int>((size_t)nseg);

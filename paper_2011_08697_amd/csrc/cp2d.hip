@@ -435,7 +435,7 @@ constexpr int kEdgeStage = 512;
 // Wave-aggregated append of (idx, partner) for the active lanes with want == true: one LDS add reserves the
 // wave's slots; slots past the stage capacity go straight to the global list (one global add for them).
 __device__ __forceinline__ void append_edge(bool want, unsigned idx, unsigned partner, uint2* stage, int* stage_n,
-                                            uint2* work, unsigned long long* counter) {
+                                            int scap, uint2* work, unsigned long long* counter) {
   const unsigned long long bal = __ballot(want);
   if (bal == 0) return;
   const int lane = lane_id();
@@ -444,7 +444,7 @@ __device__ __forceinline__ void append_edge(bool want, unsigned idx, unsigned pa
   int pos = 0;
   if (lane == leader) pos = atomicAdd(stage_n, k);
   pos = __builtin_amdgcn_readlane(pos, leader);
-  const int first_over = pos > kEdgeStage ? pos : kEdgeStage;  // first slot number routed to the global list
+  const int first_over = pos > scap ? pos : scap;  // first slot number routed to the global list
   const int n_over = pos + k - first_over;
   unsigned long long gpos = 0;
   if (n_over > 0) {
@@ -456,7 +456,7 @@ __device__ __forceinline__ void append_edge(bool want, unsigned idx, unsigned pa
   if (want) {
     const int slot = pos + __popcll(bal & ((1ull << lane) - 1ull));
     const uint2 e = make_uint2(idx, partner);
-    if (slot < kEdgeStage)
+    if (slot < scap)
       stage[slot] = e;
     else
       work[gpos + (unsigned long long)(slot - first_over)] = e;
@@ -519,6 +519,9 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   const int nx = g.nx, ny = g.ny, nt = g.nt, nxt = g.nxt;
   const long long plane = (long long)nx * ny;
   const bool vector = g.kind != 0;
+  // workgroup-local capacities: the LDS sizes, or tiny ones under the FTK_DEBUG_SMALL_LDS test hook
+  const int cap = (g.debug & 1) ? 128 : CAP;
+  const int scap = (g.debug & 1) ? 8 : kEdgeStage;
   unsigned st = 0;
   unsigned long long n_fp64 = 0, n_deg = 0, n_linked = 0;
 
@@ -616,7 +619,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   auto flush = [&]() {
     __syncthreads();  // parents written so far by this workgroup are visible to it
     const int n = s_chunk_n, nseg = s_nseg;
-    const int nst = s_stage_n < kEdgeStage ? s_stage_n : kEdgeStage;
+    const int nst = s_stage_n < scap ? s_stage_n : scap;
     for (int i = tid; i < nst; i += 256) {
       const uint2 e = s_stage[i];
       if (e.x >= e.y) continue;  // (hit, smaller partner): for the global list
@@ -656,7 +659,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   // stage for their chunk's flush (compacted to the front); attached ones, (R, R), are dropped.  One wavefront.
   auto drain = [&]() {
     __syncthreads();  // nobody reads the stage any more (a flush may just have)
-    const int n = s_stage_n < kEdgeStage ? s_stage_n : kEdgeStage;  // slots past the capacity went to the list
+    const int n = s_stage_n < scap ? s_stage_n : scap;  // slots past the capacity went to the list
     if (wave == 0) {
       unsigned n_out = 0;
       for (int b = 0; b < n; b += 64) {
@@ -732,7 +735,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       unsigned tot = 0;
       for (int r = 0; r < TY; ++r) tot += s_rc[t - t0][r];
       s_plane_total = (int)tot;
-      s_flush = (s_chunk_n > 0 && (s_chunk_n + (int)tot > CAP || t - s_chunk_t0 >= MAXTT)) ? 1 : 0;
+      s_flush = (s_chunk_n > 0 && (s_chunk_n + (int)tot > cap || t - s_chunk_t0 >= MAXTT)) ? 1 : 0;
     }
     __syncthreads();
     if (s_flush) {
@@ -745,10 +748,10 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       }
       __syncthreads();
     }
-    if (s_stage_n > kEdgeStage / 2) drain();
+    if (s_stage_n > scap / 2) drain();
     if (tid == 0) {
       const int tot = s_plane_total;
-      if (tot > CAP) {  // too many hits for the local structure: this step links through the global list only
+      if (tot > cap) {  // too many hits for the local structure: this step links through the global list only
         s_global = 1;
         s_chunk_t0 = t + 1;
         s_chunk_n = 0;
@@ -1012,7 +1015,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           sl0 = (take && ns == 0) ? oslot : sl0;
           ns += take ? 1 : 0;
         }
-        if (bad) st |= ST_INVARIANT;
+        if (bad || t == g.debug_step) st |= ST_INVARIANT;
         n_linked += ns;
         // link class of each smaller partner: 0 united here (anchor in this tile and chunk), 1 global list,
         // 2 partner in an earlier chunk of this tile (staged as (partner, hit), attached at this chunk's flush);
@@ -1038,8 +1041,8 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           if (c0 == 0) lunite(lpar, li, local_id(sm0, sl0));
           if (c1 == 0) lunite(lpar, li, local_id(sm1, sl1));
         }
-        append_edge(c0 > 0, c0 == 2 ? sm0 : idx, c0 == 2 ? idx : sm0, s_stage, &s_stage_n, o.work, work_cnt);
-        append_edge(c1 > 0, c1 == 2 ? sm1 : idx, c1 == 2 ? idx : sm1, s_stage, &s_stage_n, o.work, work_cnt);
+        append_edge(c0 > 0, c0 == 2 ? sm0 : idx, c0 == 2 ? idx : sm0, s_stage, &s_stage_n, scap, o.work, work_cnt);
+        append_edge(c1 > 0, c1 == 2 ? sm1 : idx, c1 == 2 ? idx : sm1, s_stage, &s_stage_n, scap, o.work, work_cnt);
       }
       wave_lds_sync();
     }

@@ -16,6 +16,8 @@ struct Grid2 {
   int t_begin, t_end;  // anchors processed by a launch: steps [t_begin, t_end)
   int f_ring;     // field planes stored as a ring of f_ring steps (step t at slot t % f_ring); 0: plane t at t
   int m_ring;     // same for the puncture masks and the per-segment counts/offsets
+  int debug;      // FTK_DEBUG_* test hooks (0 in normal use)
+  int debug_step; // step at which FTK_DEBUG_INVARIANT reports a bad cell (-1: none)
 };
 
 // 2D outputs (device pointers; pos/mu/type/flags may be null).

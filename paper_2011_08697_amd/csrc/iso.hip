@@ -1,4 +1,4 @@
-// iso.hip -- isovolume tracking in 3D space + time (Sec. 5.1, two passes on the regular simplicial spacetime mesh;
+// iso.hip -- isovolume tracking in 3D space + time (Sec. 6.1, two passes on the regular simplicial spacetime mesh;
 // Alg. 1 right column).
 //
 // Mesh (Sec. 3.3): an edge anchored at vertex p with axis mask M (1..15; x = 1, y = 2, z = 4, t = 8) joins p and
@@ -6,7 +6,7 @@
 // order (s1, s2, s3, s4) has the chain vertices p, p + e(s1), p + e(s1|s2), p + e(s1|s2|s3), p + e(1111).
 //
 //   iso_bits  -- the side of the level set of every vertex as one bit, 64 per word (a value equal to the isovalue
-//                lies above it: the symbolic perturbation of a single entry is positive, Sec. 5.2).
+//                lies above it: the symbolic perturbation of a single entry is positive, Sec. 6.2).
 //   iso_count -- one lane per vertex: the sides at the 16 corners of its unit 4-cube (from the bit words),
 //                the crossing mask of its 15 edges, and the tetrahedra of its 24 pentachora (case I: one vertex on
 //                its side, 1 tetrahedron; case II: two, 3 tetrahedra).

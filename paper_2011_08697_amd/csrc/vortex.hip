@@ -1,4 +1,4 @@
-// vortex.hip -- quantum vortex surface tracking in 3D complex series (Sec. 6.1, two passes on the regular
+// vortex.hip -- quantum vortex surface tracking in 3D complex series (Sec. 5.1, two passes on the regular
 // simplicial spacetime mesh; Alg. 1 middle column).
 //
 // The contour integral of the phase around a spacetime triangle, each edge's phase change wrapped into (-pi, pi],

@@ -117,3 +117,25 @@ def test_iso_and_vortex_argument_errors():
     assert L.ftk_track_vortex3d(None, 4, 4, 4, 4, ctypes.byref(o), None, ctypes.byref(vr)) != 0
     assert L.ftk_track_vortex3d(dummy, 4, 4, 300, 300, ctypes.byref(o), None, ctypes.byref(vr)) != 0
     assert b"dimension" in L.ftk_last_error() or b"large" in L.ftk_last_error()
+
+
+def test_refusing_allocator_reports_oom_before_device_work():
+    """Scratch comes from the caller's allocator hooks when given: a refusal of the first request is FTK_ERR_OOM,
+    returned before anything reaches the device (no GPU is needed for this)."""
+    calls = []
+
+    def alloc(nbytes, stream, ctx):
+        calls.append(nbytes)
+        return None
+
+    def free(ptr, stream, ctx):
+        calls.append(-1)
+
+    a, f = F._ALLOC_FN(alloc), F._FREE_FN(free)
+    o = F.Options()
+    F.lib().ftk_default_options(ctypes.byref(o))
+    o.alloc, o.free = a, f
+    st, r = _call2d(ctypes.c_void_p(256), 0, 64, 64, 10, o)
+    assert st == 5, F.last_error()
+    assert len(calls) == 1 and calls[0] >= 64 * 64 * 10 * 2
+    assert r.n_hits == 0 and not r.face_id

@@ -95,3 +95,15 @@ def test_full_size_blobs3d256_sampled():
         r = O.trace(f, int(fid[i]), n=3, max_steps=100000)
         assert r["closed"] != -1
         assert r["min_face"] == g["label"][i]
+
+
+@pytest.mark.parametrize("case", range(15))
+def test_quadratic_types_3d(case):
+    """Quadratic forms of known inertia (Sec. 4.1): MIN, SADDLE1, SADDLE2 and MAX, with off-diagonal terms; full
+    parity with the oracle and the expected type everywhere on the one trajectory."""
+    from tests.test_oracle_track import QUAD3_CASES, quadratic_field_3d
+    A, expect = QUAD3_CASES[case]
+    f = quadratic_field_3d(A)
+    g = to_np(run(f))
+    assert_full_parity(run(f), O.track(f, n=3))
+    assert g["n_trajectories"] == 1 and set(g["type"].tolist()) == {O.TYPES.index(expect)}

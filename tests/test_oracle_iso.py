@@ -1,5 +1,5 @@
 """Pins of the isovolume oracle (oracle/iso.py) against what the paper and geometry fix: the paper's moving plane
-f = x - alpha t (Sec. 5.4) with its closed-form trajectory x = alpha t, the total 3-volume of the tessellation for
+f = x - alpha t (Sec. 6.3) with its closed-form trajectory x = alpha t, the total 3-volume of the tessellation for
 planes whose section of the grid box has a closed-form volume, the tessellation as a 3-manifold whose faces are
 shared by two tetrahedra except on the grid boundary (conforming case II splits), and the tie rule (a vertex
 exactly at the isovalue counts as above it)."""

@@ -347,3 +347,65 @@ def test_point_queries_agree_with_whole_field_run():
         r = O.trace(f, int(tr.face_id[i]))
         assert r["min_face"] == tr.label[i]
         assert r["length"] == int(np.sum(tr.label == tr.label[i]))
+
+
+# Quadratic forms f = (x - c)^T A (x - c) in 3D with an off-grid centre.  Central differences of a quadratic are
+# exact, so the gradient is exactly the linear field 2 A (x - c) (dyadic values, exact in binary32), the zero sits
+# exactly at c, and the Jacobian stencil of that linear gradient is exactly 2 A.  The type is the inertia of A
+# (Sec. 4.1: types from the eigenvalues of the Jacobian): the number of negative eigenvalues picks MIN, SADDLE1,
+# SADDLE2 or MAX.  The non-diagonal forms make every term of the Descartes sequence (trace, sum of principal 2x2
+# minors, determinant) decide a case: diag(-1, -1, 5) has trace 3, minors -9 and determinant 5, so a sign slip in
+# the minors would read MIN instead of SADDLE2.
+QUAD3_CASES = [
+    ([[1, 0, 0], [0, 1, 0], [0, 0, 1]], "MIN"),
+    ([[-1, 0, 0], [0, -1, 0], [0, 0, -1]], "MAX"),
+    ([[-1, 0, 0], [0, 1, 0], [0, 0, 1]], "SADDLE1"),
+    ([[1, 0, 0], [0, -1, 0], [0, 0, 1]], "SADDLE1"),
+    ([[1, 0, 0], [0, 1, 0], [0, 0, -1]], "SADDLE1"),
+    ([[-1, 0, 0], [0, -1, 0], [0, 0, 1]], "SADDLE2"),
+    ([[1, 0, 0], [0, -1, 0], [0, 0, -1]], "SADDLE2"),
+    ([[-1, 0, 0], [0, 1, 0], [0, 0, -1]], "SADDLE2"),
+    ([[-1, 0, 0], [0, -1, 0], [0, 0, 5]], "SADDLE2"),
+    ([[1, 2, 0], [2, 1, 0], [0, 0, 1]], "SADDLE1"),   # eigenvalues 3, -1, 1
+    ([[2, 1, 1], [1, 2, 1], [1, 1, 2]], "MIN"),       # 4, 1, 1
+    ([[-2, 1, 1], [1, -2, 1], [1, 1, 1]], "SADDLE2"),  # -3, -sqrt 3, sqrt 3
+    ([[-3, 1, 1], [1, -3, 1], [1, 1, -3]], "MAX"),  # -4, -4, -1
+    ([[-3, 1, 0], [1, -3, 1], [0, 1, -3]], "MAX"),    # all negative (diagonally dominant)
+    ([[0, 1, 1], [1, 0, 1], [1, 1, 0]], "SADDLE2"),   # 2, -1, -1 with a zero diagonal
+]
+QUAD3_CENTRE = (8.25, 7.5, 6.75)
+
+
+def quadratic_field_3d(A, c=QUAD3_CENTRE, dims=(17, 15, 14), nt=3):
+    nx, ny, nz = dims
+    z, y, x = np.meshgrid(np.arange(nz) - c[2], np.arange(ny) - c[1], np.arange(nx) - c[0], indexing="ij")
+    X = (x, y, z)
+    f = sum(A[a][b] * X[a] * X[b] for a in range(3) for b in range(3))
+    return np.stack([f] * nt).astype(np.float32)
+
+
+def test_quadratic_field_3d_is_exact_in_binary32():
+    for A, _ in QUAD3_CASES:
+        nx, ny, nz = 17, 15, 14
+        z, y, x = np.meshgrid(np.arange(nz) - 6.75, np.arange(ny) - 7.5, np.arange(nx) - 8.25, indexing="ij")
+        X = (x, y, z)
+        f64 = sum(A[a][b] * X[a] * X[b] for a in range(3) for b in range(3))
+        assert np.array_equal(quadratic_field_3d(A)[0].astype(np.float64), f64)
+
+
+@pytest.mark.parametrize("A,expect", QUAD3_CASES)
+def test_quadratic_scalar_types_3d(A, expect):
+    """Sec. 4.1 types in 3D on quadratic forms of known inertia: one vertical trajectory through the centre, every
+    point of the expected type, positions exactly at the centre."""
+    ev = np.linalg.eigvalsh(np.array(A, np.float64))
+    n_neg = int(np.sum(ev < 0))
+    assert np.all(np.abs(ev) > 0.5)
+    assert expect == ["MIN", "SADDLE1", "SADDLE2", "MAX"][n_neg]
+    f = quadratic_field_3d(A)
+    tr = O.track(f, n=3)
+    assert tr.status == 0 and tr.invariant_violations == 0
+    assert tr.n_traj == 1 and tr.n_hits >= 3
+    assert set(tr.type.tolist()) == {O.TYPES.index(expect)}
+    assert np.allclose(tr.pos[:, :3], QUAD3_CENTRE, atol=1e-12)
+    # a vertical line: the trajectory reaches the first and the last step
+    assert tr.pos[:, 3].min() == 0.0 and tr.pos[:, 3].max() == 2.0

@@ -2,7 +2,7 @@
 test (wrapped phase changes summing to +-2 pi) agrees with the exact puncture test on random triangles; a moving
 straight vortex line gives one surface whose points lie on the line and one positive triangle per spatial plane and
 step; on fields with ties everywhere every tetrahedron has 0 or 2 positive faces and every pentachoron 0, 3, 4 or 5
-(the cases of Sec. 6.1); a ring is one surface and two rings two."""
+(the cases of Sec. 5.1); a ring is one surface and two rings two."""
 import numpy as np
 import pytest
 
