@@ -505,10 +505,7 @@ ftk_status track2d_core(const float* field, ftk_field_kind kind, int64_t nx, int
   const size_t o_parent = c1.add<unsigned>((size_t)nh);
   const size_t o_work = c1.add<uint2>((size_t)nh * 2);
   char* b1 = mem.scratch(1, c1.total);
-  if (!b1) {
-    out->n_hits = nh;
-    return mem.scratch_error(1, c1.total);
-  }
+  if (!b1) return mem.scratch_error(1, c1.total);
   unsigned* parent = (unsigned*)(b1 + o_parent);
   uint2* work = (uint2*)(b1 + o_work);
 
