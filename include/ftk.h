@@ -144,6 +144,28 @@ ftk_status ftk_track_cp2d(const float* field, ftk_field_kind kind, int64_t nx, i
                           const ftk_options* opt, ftk_stream_t stream, ftk_cp_result* out);
 
 /*
+ * For callers that cannot allocate device memory (serving loops that must not call hipMalloc, harnesses that
+ * forbid allocation): ftk_track_cp2d with the outputs in caller-owned arrays and the scratch (puncture masks,
+ * per-segment hit counts and offsets, union-find parents and link list) in one fixed region inside the library,
+ * FTK_STATIC_SCRATCH_BYTES per device, held from the first call on a device until the process ends.  No device
+ * memory is allocated or freed by the call.
+ *   io (host pointer): on entry, face_id and, for each FTK_OUT_* bit set in opt->outputs, the matching array among
+ *     pos ([capacity][3] floats), mu ([capacity][3]), type, flags ([capacity] bytes), label ([capacity] int64) are
+ *     device arrays owned by the caller with room for `capacity` hits; on FTK_OK the call fills n_hits,
+ *     n_trajectories and stats and sets the pointers of outputs not asked for to NULL.
+ *   opt->alloc/free/alloc_ctx and opt->profile are ignored.  Results are identical to ftk_track_cp2d's.
+ *   The scratch need is 2 bytes per vertex plus 12 bytes per 64-vertex row segment (detection) and 20 bytes per
+ *     hit (union-find), each rounded up to 256 bytes, plus a few KiB; when it exceeds the region the call returns
+ *     FTK_ERR_CAPACITY (n_hits set once the hits are counted), as it does for more than `capacity` hits.
+ *   Calls that overlap in time on one device (several host threads, or streams not ordered with each other)
+ *     share the region and race: serialise them.  Errors otherwise as ftk_track_cp2d; on error *io is left as
+ *     given except n_hits for FTK_ERR_CAPACITY.
+ */
+#define FTK_STATIC_SCRATCH_BYTES (256ull << 20)
+ftk_status ftk_track_cp2d_into(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny, int64_t nt,
+                               const ftk_options* opt, ftk_stream_t stream, int64_t capacity, ftk_cp_result* io);
+
+/*
  * Track critical points of a 3D time-varying scalar field f[nt][nz][ny][nx] through its gradient (Sec. 4.1-4.3,
  * Alg. 1 left column with tetrahedral sides of pentachora).  kind must be FTK_SCALAR.  FTK_ERR_RANGE when a
  * quantised component reaches 2^41.  Otherwise as ftk_track_cp2d.

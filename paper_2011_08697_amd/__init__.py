@@ -25,7 +25,7 @@ EXPORTS = ["ftk_default_options", "ftk_track_cp2d", "ftk_track_cp3d", "ftk_cp_cr
            "ftk_traj_smooth_types", "ftk_traj_simplify_types", "ftk_track_iso3d", "ftk_iso_result_free",
            "ftk_edge_count", "ftk_track_vortex3d", "ftk_vortex_result_free", "ftk_triangle_count",
            "ftk_track_cp_mesh2d", "ftk_mesh_result_free", "ftk_mesh_create", "ftk_mesh_destroy",
-           "ftk_track_cp_mesh"]
+           "ftk_track_cp_mesh", "ftk_track_cp2d_into"]
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -97,6 +97,9 @@ def lib():
         L.ftk_track_cp2d.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.POINTER(Options), vp,
                                      ctypes.POINTER(Result)]
         L.ftk_track_cp2d.restype = ctypes.c_int
+        L.ftk_track_cp2d_into.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.POINTER(Options), vp, i64,
+                                          ctypes.POINTER(Result)]
+        L.ftk_track_cp2d_into.restype = ctypes.c_int
         L.ftk_track_cp3d.argtypes = [vp, ctypes.c_int, i64, i64, i64, i64, ctypes.POINTER(Options), vp,
                                      ctypes.POINTER(Result)]
         L.ftk_track_cp3d.restype = ctypes.c_int
@@ -265,6 +268,59 @@ def track_cp2d(field, kind=SCALAR, **opts):
                               _stream_handle(field.device), ctypes.byref(r))
     _check(st)
     return _wrap(pool, r)
+
+
+STATIC_SCRATCH_BYTES = 256 << 20
+
+
+def track_cp2d_into(field, kind=SCALAR, capacity=None, out=None, **opts):
+    """ftk_track_cp2d_into: the library allocates nothing; outputs go to `out` (a dict of device tensors face_id,
+    pos, mu, type, flags, label with room for `capacity` hits, as many as opts' outputs ask for), allocated here with
+    torch when not given.  Returns the same dict layout as track_cp2d (views of the first n_hits entries)."""
+    import torch
+    if not field.is_contiguous() or field.dtype.itemsize != 4 or not field.is_cuda:
+        raise ValueError("field must be a contiguous float32 device tensor")
+    if kind == SCALAR:
+        nt, ny, nx = field.shape
+    else:
+        nt, c, ny, nx = field.shape
+        if c != 2:
+            raise ValueError("vector field must be [nt][2][ny][nx]")
+    o = _options(None, **opts)
+    outs = o.outputs
+    dev = field.device
+    if out is None:
+        if capacity is None:
+            raise ValueError("give capacity or out")
+        out = dict(face_id=torch.empty(capacity, dtype=torch.int64, device=dev))
+        if outs & OUT_POS:
+            out["pos"] = torch.empty((capacity, 3), dtype=torch.float32, device=dev)
+        if outs & OUT_MU:
+            out["mu"] = torch.empty((capacity, 3), dtype=torch.float32, device=dev)
+        if outs & OUT_TYPE:
+            out["type"] = torch.empty(capacity, dtype=torch.uint8, device=dev)
+        if outs & OUT_FLAGS:
+            out["flags"] = torch.empty(capacity, dtype=torch.uint8, device=dev)
+        if outs & OUT_LABEL:
+            out["label"] = torch.empty(capacity, dtype=torch.int64, device=dev)
+    capacity = out["face_id"].numel()
+    r = Result()
+    for k in ("face_id", "pos", "mu", "type", "flags", "label"):
+        t = out.get(k)
+        setattr(r, k, t.data_ptr() if t is not None else None)
+    st = lib().ftk_track_cp2d_into(ctypes.c_void_p(field.data_ptr()), kind, nx, ny, nt, ctypes.byref(o),
+                                   _stream_handle(dev), capacity, ctypes.byref(r))
+    if st != 0:
+        raise FtkError(st, last_error() + (f" (n_hits {r.n_hits})" if st == 4 else ""))
+    nh = int(r.n_hits)
+
+    def view(k, shape):
+        t = out.get(k)
+        return None if t is None or not getattr(r, k) else t.reshape(-1)[:nh * (shape[1] if len(shape) > 1 else 1)].view(*shape)
+    return dict(n=2, n_hits=nh, n_trajectories=int(r.n_trajectories),
+                face_id=view("face_id", (nh,)), pos=view("pos", (nh, 3)), mu=view("mu", (nh, 3)),
+                type=view("type", (nh,)), flags=view("flags", (nh,)), label=view("label", (nh,)),
+                stats={f: getattr(r.stats, f) for f, _ in Stats._fields_ if f != "reserved"})
 
 
 def track_cp3d(field, **opts):

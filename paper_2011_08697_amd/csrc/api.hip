@@ -505,7 +505,11 @@ ftk_status track2d_core(const float* field, ftk_field_kind kind, int64_t nx, int
   const size_t o_parent = c1.add<unsigned>((size_t)nh);
   const size_t o_work = c1.add<uint2>((size_t)nh * 2);
   char* b1 = mem.scratch(1, c1.total);
-  if (!b1) return mem.scratch_error(1, c1.total);
+  if (!b1) {
+    const ftk_status e = mem.scratch_error(1, c1.total);
+    if (e == FTK_ERR_CAPACITY) out->n_hits = nh;
+    return e;
+  }
   unsigned* parent = (unsigned*)(b1 + o_parent);
   uint2* work = (uint2*)(b1 + o_work);
 
@@ -569,6 +573,67 @@ ftk_status track2d_impl(const float* field, ftk_field_kind kind, int64_t nx, int
   OwnMem2 mem(o, s);
   return track2d_core(field, kind, nx, ny, nt, o, s, mem, out);
 }
+
+// ---------------------------------------------------------------------------------------------------------------
+// The 2D call that allocates nothing (ftk_track_cp2d_into): outputs in the caller's arrays, scratch carved from one
+// fixed region per device.  The array below is a device symbol; host code reaches its memory only through the
+// address hipGetSymbolAddress returns for the current device (the array's name is not a device address in host
+// code).  Calls on one device share the region, so overlapping calls on one device race.
+// ---------------------------------------------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)FTK_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's region, looked up once per device.
+ftk_status static_scratch(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FTK_ERR_ARG, "device ordinal %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FTK_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FTK_OK;
+}
+
+// Scratch groups carved one after the other from the region; outputs are the caller's arrays.
+struct StaticMem2 : Mem2 {
+  char* base;
+  size_t used = 0;
+  const ftk_cp_result& io;  // the caller's output pointers
+  long long capacity;
+  StaticMem2(char* b, const ftk_cp_result& r, long long cap) : base(b), io(r), capacity(cap) {}
+  char* scratch(int, size_t bytes) override {
+    if (bytes > kStaticScratchBytes - used) return nullptr;
+    char* p = base + used;
+    used += bytes;
+    return p;
+  }
+  ftk_status scratch_error(int group, size_t bytes) override {
+    return fail(FTK_ERR_CAPACITY, "%s scratch of %zu bytes (after %zu in use) exceeds the %zu-byte static region",
+                group == 0 ? "detection" : "union-find", bytes, used, kStaticScratchBytes);
+  }
+  ftk_status outputs(ftk_cp_result& r, long long nh, unsigned outs) override {
+    if (nh > capacity)
+      return fail(FTK_ERR_CAPACITY, "%lld punctured simplices exceed the output capacity of %lld", nh, capacity);
+    r.face_id = io.face_id;
+    r.pos = (outs & FTK_OUT_POS) ? io.pos : nullptr;
+    r.mu = (outs & FTK_OUT_MU) ? io.mu : nullptr;
+    r.type = (outs & FTK_OUT_TYPE) ? io.type : nullptr;
+    r.flags = (outs & FTK_OUT_FLAGS) ? io.flags : nullptr;
+    r.label = (outs & FTK_OUT_LABEL) ? io.label : nullptr;
+    return FTK_OK;
+  }
+  void drop_outputs(ftk_cp_result& r) override { std::memset(&r, 0, sizeof(r)); }  // the caller's arrays
+};
 
 // ---------------------------------------------------------------------------------------------------------------
 // 3D one-shot
@@ -1287,6 +1352,47 @@ extern "C" ftk_status ftk_track_cp2d(const float* field, ftk_field_kind kind, in
   ftk_status st = ftk::validate_options(o);
   if (st) return st;
   return ftk::track2d_impl(field, kind, nx, ny, nt, o, (hipStream_t)stream, out);
+}
+
+extern "C" ftk_status ftk_track_cp2d_into(const float* field, ftk_field_kind kind, int64_t nx, int64_t ny,
+                                          int64_t nt, const ftk_options* opt, ftk_stream_t stream, int64_t capacity,
+                                          ftk_cp_result* io) {
+  g_err.clear();
+  if (!io) return fail(FTK_ERR_ARG, "io is NULL");
+  if (!field) return fail(FTK_ERR_ARG, "field is NULL");
+  if (kind != FTK_SCALAR && kind != FTK_VECTOR) return fail(FTK_ERR_ARG, "kind must be FTK_SCALAR or FTK_VECTOR");
+  if (nx < 2 || ny < 2 || nt < 2) return fail(FTK_ERR_ARG, "every dimension must be >= 2 (got %lld x %lld x %lld)",
+                                               (long long)nx, (long long)ny, (long long)nt);
+  if (nx > (1 << 30) || ny > (1 << 30) || nt > (1 << 30) || nx * ny > (1ll << 40) || nx * ny * nt > (1ll << 42))
+    return fail(FTK_ERR_ARG, "grid too large");
+  if (capacity < 0) return fail(FTK_ERR_ARG, "capacity must be >= 0");
+  ftk_options o;
+  resolve(opt, &o);
+  o.alloc = nullptr;  // nothing is allocated: the hooks and the phase timers are not used
+  o.free = nullptr;
+  o.alloc_ctx = nullptr;
+  o.profile = 0;
+  ftk_status st = ftk::validate_options(o);
+  if (st) return st;
+  const unsigned outs = o.outputs;
+  if (capacity > 0 && (!io->face_id || ((outs & FTK_OUT_POS) && !io->pos) || ((outs & FTK_OUT_MU) && !io->mu) ||
+                       ((outs & FTK_OUT_TYPE) && !io->type) || ((outs & FTK_OUT_FLAGS) && !io->flags) ||
+                       ((outs & FTK_OUT_LABEL) && !io->label)))
+    return fail(FTK_ERR_ARG, "io lacks an output array that opt->outputs asks for");
+  char* base = nullptr;
+  st = ftk::static_scratch(&base);
+  if (st) return st;
+  ftk_cp_result r = *io;  // the caller's pointers; *io is written only on success (n_hits also on CAPACITY)
+  ftk::StaticMem2 mem(base, r, capacity);
+  ftk_cp_result res;
+  std::memset(&res, 0, sizeof(res));
+  st = ftk::track2d_core(field, kind, nx, ny, nt, o, (hipStream_t)stream, mem, &res);
+  if (st == FTK_OK) {
+    *io = res;
+  } else if (st == FTK_ERR_CAPACITY) {
+    io->n_hits = res.n_hits;
+  }
+  return st;
 }
 
 // ---------------------------------------------------------------------------------------------------------------

@@ -139,3 +139,18 @@ def test_refusing_allocator_reports_oom_before_device_work():
     assert st == 5, F.last_error()
     assert len(calls) == 1 and calls[0] >= 64 * 64 * 10 * 2
     assert r.n_hits == 0 and not r.face_id
+
+
+def test_no_alloc_entry_point_argument_errors():
+    """ftk_track_cp2d_into rejects bad arguments on the host, before it looks up its scratch region."""
+    L = F.lib()
+    r = F.Result()
+    st = L.ftk_track_cp2d_into(None, 0, 8, 8, 4, None, None, 10, ctypes.byref(r))
+    assert st == 1 and "field" in F.last_error()
+    st = L.ftk_track_cp2d_into(ctypes.c_void_p(256), 0, 8, 8, 4, None, None, 10, None)
+    assert st == 1 and "io" in F.last_error()
+    st = L.ftk_track_cp2d_into(ctypes.c_void_p(256), 0, 8, 8, 4, None, None, -1, ctypes.byref(r))
+    assert st == 1 and "capacity" in F.last_error()
+    st = L.ftk_track_cp2d_into(ctypes.c_void_p(256), 0, 8, 8, 4, None, None, 10, ctypes.byref(r))
+    assert st == 1 and "output array" in F.last_error()  # default outputs need face_id, pos, type, flags, label
+    assert r.n_hits == 0 and not r.face_id
