@@ -326,12 +326,11 @@ WORKLOAD_PARAMS = {
 def make(name, nt=None, ny=None, device=None):
     """Generate a named workload (optionally only the first nt steps / ny rows; device: torch device for the 3D
     field's float64 evaluation)."""
-    c = WORKLOAD_PARAMS[name]
+    c = WORKLOAD_PARAMS["noise1024" if name == "levels1024" else name]
     if name == "blobs64":
         nx, nyy, ntt = c["dims"]
         return moving_gaussians_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"])
     if name in ("noise1024", "levels1024"):
-        c = WORKLOAD_PARAMS["noise1024"]
         nx, nyy, ntt = c["dims"]
         f = moving_gaussians_2d(nx, ny or nyy, nt or ntt, c["K"], seed=c["seed"], noise_std=c["noise_std"])
         return quantise_levels(f) if name == "levels1024" else f
