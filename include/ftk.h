@@ -176,10 +176,13 @@ ftk_status ftk_track_cp3d(const float* field, ftk_field_kind kind, int64_t nx, i
 /*
  * Streaming form, after the paper's push_field_data() and its two-step sliding window of ordinal and interval
  * elements (Sec. 3.2 "Ordinal and interval mesh elements", Sec. 8 "C++ programming interface").
- *   ftk_cp_create: n = 2 or 3, dims = (nx, ny[, nz]); the tracker keeps the last pushed step on the device.
+ *   ftk_cp_create: n = 2 or 3, dims = (nx, ny[, nz]); the tracker holds a window of the last three steps on the
+ *                  device (field, puncture masks, per-segment counts and offsets), independent of the series length;
+ *                  only the outputs grow with the hits found.
  *   ftk_cp_push:   step = device pointer to one time step in the layout above (for vector input [2][ny][nx]); the
- *                  caller may overwrite it once `stream` has passed the call.  Ordinal simplices of the step and
- *                  interval simplices between the previous and this step are tested.
+ *                  caller may overwrite it once the call returns.  Pushing step s tests the simplices anchored at
+ *                  step s - 1 (its ordinal simplices and the interval ones towards s) and emits the hits anchored at
+ *                  step s - 2 (whose cells reach steps s - 3 .. s - 1).
  *   ftk_cp_finish: stitches, labels and returns the whole trajectory set, identical to the one-shot call on the
  *                  concatenated steps.  The tracker may not be pushed to afterwards (FTK_ERR_STATE).
  */

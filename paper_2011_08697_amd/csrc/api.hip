@@ -651,6 +651,10 @@ ftk_status track3d_impl(const float* field, int64_t nx, int64_t ny, int64_t nz, 
   g.nxt = (int)((nx + 15) / 16);
   g.qscale = std::ldexp(1.0f, o.quant_log2);
   g.precision = o.precision;
+  g.t_begin = 0;
+  g.t_end = (int)nt;
+  g.f_ring = 0;
+  g.m_ring = 0;
   const long long V = (long long)nx * ny * nz * nt;
   const long long nseg = (long long)nt * nz * ny * g.nxt;
   uint64_t* masks = sc.get<uint64_t>((size_t)V);
@@ -980,9 +984,12 @@ struct ftk_tracker {
   int steps = 0;
   int state = 0;  // 0 open, 1 finished, 2 failed
   size_t step_elems = 0;
-  // 2D window
+  // window of the last steps (ring of 3): field steps, puncture masks (2D: 12 bits, 3D: 60 bits per vertex),
+  // per-segment counts and offsets
   float* fring = nullptr;
   uint16_t* mring = nullptr;
+  uint64_t* mring3 = nullptr;
+  long long* list3 = nullptr;  // 3D emission: 64-vertex row chunks with hits of the emitted step
   int* cring = nullptr;
   long long* oring = nullptr;
   long long* scan_tmp = nullptr;
@@ -1001,9 +1008,6 @@ struct ftk_tracker {
   uint8_t* flags = nullptr;
   unsigned* parent = nullptr;
   uint2* work = nullptr;
-  // 3D accumulation
-  float* all = nullptr;
-  size_t all_cap_steps = 0;
 };
 
 namespace ftk {
@@ -1013,11 +1017,13 @@ static Alloc tracker_alloc(ftk_tracker* h) { return make_alloc(h->o, h->s); }
 static void tracker_free_all(ftk_tracker* h) {
   const Alloc al = tracker_alloc(h);
   (void)hipStreamSynchronize(h->s);
-  void* ps[] = {h->fring, h->mring, h->cring, h->oring, h->scan_tmp, h->dctl, h->dplane, h->face_id, h->pos,
-                h->mu, h->type, h->flags, h->parent, h->work, h->all};
+  void* ps[] = {h->fring, h->mring, h->mring3, h->list3, h->cring, h->oring, h->scan_tmp, h->dctl, h->dplane,
+                h->face_id, h->pos, h->mu, h->type, h->flags, h->parent, h->work};
   for (void* p : ps) al.put(p);
   h->fring = nullptr;
   h->mring = nullptr;
+  h->mring3 = nullptr;
+  h->list3 = nullptr;
   h->cring = nullptr;
   h->oring = nullptr;
   h->scan_tmp = nullptr;
@@ -1028,7 +1034,6 @@ static void tracker_free_all(ftk_tracker* h) {
   h->type = h->flags = nullptr;
   h->parent = nullptr;
   h->work = nullptr;
-  h->all = nullptr;
 }
 
 // Grow the output and union-find arrays to hold `need` hits, keeping the first `keep` entries.
@@ -1048,8 +1053,9 @@ static ftk_status tracker_reserve(ftk_tracker* h, long long need, long long keep
     *p = q;
     return true;
   };
-  bool ok = grow((void**)&h->face_id, 8, true) && grow((void**)&h->pos, 12, (outs & FTK_OUT_POS) != 0) &&
-            grow((void**)&h->mu, 12, (outs & FTK_OUT_MU) != 0) && grow((void**)&h->type, 1, (outs & FTK_OUT_TYPE) != 0) &&
+  const size_t pe = 4 * (size_t)(h->n + 1);  // position / barycentric bytes per hit
+  bool ok = grow((void**)&h->face_id, 8, true) && grow((void**)&h->pos, pe, (outs & FTK_OUT_POS) != 0) &&
+            grow((void**)&h->mu, pe, (outs & FTK_OUT_MU) != 0) && grow((void**)&h->type, 1, (outs & FTK_OUT_TYPE) != 0) &&
             grow((void**)&h->flags, 1, (outs & FTK_OUT_FLAGS) != 0) && grow((void**)&h->parent, 4, true);
   if (ok) {
     // the edge list is rebuilt from the device counter, keep all of it
@@ -1141,6 +1147,79 @@ static ftk_status tracker_emit(ftk_tracker* h, int e, int nt) {
   return FTK_OK;
 }
 
+// 3D window: the same schedule on the 4D Kuhn mesh.  Detecting the anchors of step p reads the field steps p and
+// p + 1; emitting step e reads the field steps e and e + 1 and the masks and offsets of the steps e - 1 .. e + 1
+// (the pentachora holding a tetrahedron reach one step either way), so three slots of each suffice.
+static Grid3 tracker_grid3(ftk_tracker* h, int t_begin, int nt) {
+  Grid3 g;
+  g.f = h->fring;
+  g.nx = (int)h->nx;
+  g.ny = (int)h->ny;
+  g.nz = (int)h->nz;
+  g.nt = nt;
+  g.nxt = (int)((h->nx + 15) / 16);
+  g.qscale = std::ldexp(1.0f, h->o.quant_log2);
+  g.precision = h->o.precision;
+  g.t_begin = t_begin;
+  g.t_end = t_begin + 1;
+  g.f_ring = 3;
+  g.m_ring = 3;
+  return g;
+}
+
+static ftk_status tracker_detect3(ftk_tracker* h, int p, int nt) {
+  Ctl* dctl = (Ctl*)h->dctl;
+  const Grid3 g = tracker_grid3(h, p, nt);
+  const int slot = p % 3;
+  int* cnt = h->cring + (size_t)slot * h->nseg_plane;
+  long long* off = h->oring + (size_t)slot * h->nseg_plane;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool wide = pass == 1;
+    zero_words<<<1, 64, 0, h->s>>>(&dctl->dstatus, 1);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_detect3d(g, 1, wide, h->mring3, h->cring, &dctl->dstatus, h->s));
+    unsigned st = 0;
+    HIP_TRY(hipMemcpyAsync(&st, &dctl->dstatus, sizeof(unsigned), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipStreamSynchronize(h->s));
+    if (st & (ST_NONFINITE | ST_RANGE)) return decode_status(st);
+    if (!(st & ST_WIDE)) {
+      h->plane_wide[slot] = wide ? 1 : 0;
+      break;
+    }
+  }
+  HIP_TRY(launch_scan(cnt, off, h->nseg_plane, h->dplane, h->scan_tmp, h->s));
+  add_plane_base<<<(unsigned)((h->nseg_plane + 255) / 256), 256, 0, h->s>>>(off, h->nseg_plane, &dctl->total);
+  bump_running<<<1, 1, 0, h->s>>>(&dctl->total, h->dplane);
+  HIP_TRY(hipGetLastError());
+  long long tot = 0;
+  HIP_TRY(hipMemcpyAsync(&tot, &dctl->total, sizeof(long long), hipMemcpyDeviceToHost, h->s));
+  HIP_TRY(hipStreamSynchronize(h->s));
+  if (tot > 0xFFFFFFFELL) return fail(FTK_ERR_CAPACITY, "%lld punctured simplices exceed 2^32 - 2", tot);
+  h->total_after.push_back(tot);
+  return tracker_reserve(h, tot, h->emitted);
+}
+
+static ftk_status tracker_emit3(ftk_tracker* h, int e, int nt) {
+  Ctl* dctl = (Ctl*)h->dctl;
+  const Grid3 g = tracker_grid3(h, e, nt);
+  Out3 od;
+  od.face_id = h->face_id;
+  od.pos = h->pos;
+  od.mu = h->mu;
+  od.type = h->type;
+  od.flags = h->flags;
+  od.parent = h->parent;
+  od.work = h->work;
+  const long long step_hits = h->total_after[e] - (e > 0 ? h->total_after[e - 1] : 0);
+  zero_words<<<1, 64, 0, h->s>>>((unsigned*)&dctl->cnt[CNT_LIST], 2);
+  HIP_TRY(hipGetLastError());
+  if (step_hits > 0)
+    HIP_TRY(launch_emit3d(g, h->plane_wide[e % 3] != 0, h->mring3, h->oring, step_hits, od, &dctl->status, dctl->cnt,
+                          h->list3, &dctl->cnt[CNT_LIST], h->s));
+  h->emitted = h->total_after[e];
+  return FTK_OK;
+}
+
 }  // namespace ftk
 
 extern "C" ftk_status ftk_cp_create(int32_t n, const int64_t* dims, ftk_field_kind kind, const ftk_options* opt,
@@ -1166,18 +1245,24 @@ extern "C" ftk_status ftk_cp_create(int32_t n, const int64_t* dims, ftk_field_ki
   h->o = o;
   h->s = (hipStream_t)stream;
   h->step_elems = (size_t)h->nx * h->ny * h->nz * (kind == FTK_VECTOR ? 2 : 1);
-  if (n == 2) {
+  {
     const Alloc al = ftk::tracker_alloc(h);
-    const long long plane = h->nx * h->ny;
-    h->nseg_plane = h->ny * ((h->nx + 63) / 64);
+    const long long plane = h->nx * h->ny * h->nz;  // vertices per step
+    h->nseg_plane = n == 2 ? h->ny * ((h->nx + 63) / 64) : h->nz * h->ny * ((h->nx + 15) / 16);
     h->fring = (float*)al.get(sizeof(float) * 3 * h->step_elems);
-    h->mring = (uint16_t*)al.get(sizeof(uint16_t) * 3 * plane);
+    if (n == 2) {
+      h->mring = (uint16_t*)al.get(sizeof(uint16_t) * 3 * plane);
+    } else {
+      h->mring3 = (uint64_t*)al.get(sizeof(uint64_t) * 3 * plane);
+      h->list3 = (long long*)al.get(sizeof(long long) * h->nz * h->ny * ((h->nx + 63) / 64));
+    }
     h->cring = (int*)al.get(sizeof(int) * 3 * h->nseg_plane);
     h->oring = (long long*)al.get(sizeof(long long) * 3 * h->nseg_plane);
     h->scan_tmp = (long long*)al.get(sizeof(long long) * ftk::scan_tmp_elems(h->nseg_plane));
     h->dctl = al.get(sizeof(Ctl));
     h->dplane = (long long*)al.get(sizeof(long long));
-    if (!h->fring || !h->mring || !h->cring || !h->oring || !h->scan_tmp || !h->dctl || !h->dplane) {
+    const bool ring_ok = n == 2 ? h->mring != nullptr : (h->mring3 != nullptr && h->list3 != nullptr);
+    if (!h->fring || !ring_ok || !h->cring || !h->oring || !h->scan_tmp || !h->dctl || !h->dplane) {
       ftk::tracker_free_all(h);
       delete h;
       return fail(FTK_ERR_OOM, "tracker allocation failed");
@@ -1198,29 +1283,17 @@ extern "C" ftk_status ftk_cp_push(ftk_tracker* h, const float* step) {
   if (h->state != 0) return fail(FTK_ERR_STATE, "tracker already finished or failed");
   if (!step) return fail(FTK_ERR_ARG, "step is NULL");
   if (h->steps >= (1 << 28)) return fail(FTK_ERR_ARG, "too many steps");
-  const Alloc al = ftk::tracker_alloc(h);
   const size_t bytes = sizeof(float) * h->step_elems;
-  if (h->n == 3) {
-    if ((size_t)h->steps == h->all_cap_steps) {
-      size_t nc = h->all_cap_steps ? h->all_cap_steps * 2 : 8;
-      float* q = (float*)al.get(bytes * nc);
-      if (!q) return fail(FTK_ERR_OOM, "tracker allocation failed");
-      if (h->all) {
-        HIP_TRY(hipMemcpyAsync(q, h->all, bytes * h->steps, hipMemcpyDeviceToDevice, h->s));
-        al.put(h->all);
-      }
-      h->all = q;
-      h->all_cap_steps = nc;
-    }
-    HIP_TRY(hipMemcpyAsync((char*)h->all + bytes * h->steps, step, bytes, hipMemcpyDeviceToDevice, h->s));
-    ++h->steps;
-    return FTK_OK;
-  }
   const int s = h->steps;
   HIP_TRY(hipMemcpyAsync(h->fring + (size_t)(s % 3) * h->step_elems, step, bytes, hipMemcpyDeviceToDevice, h->s));
   ftk_status st = FTK_OK;
-  if (s >= 1) st = ftk::tracker_detect(h, s - 1, ftk::kOpenNt);
-  if (!st && s >= 2) st = ftk::tracker_emit(h, s - 2, ftk::kOpenNt);
+  if (h->n == 2) {
+    if (s >= 1) st = ftk::tracker_detect(h, s - 1, ftk::kOpenNt);
+    if (!st && s >= 2) st = ftk::tracker_emit(h, s - 2, ftk::kOpenNt);
+  } else {
+    if (s >= 1) st = ftk::tracker_detect3(h, s - 1, ftk::kOpenNt);
+    if (!st && s >= 2) st = ftk::tracker_emit3(h, s - 2, ftk::kOpenNt);
+  }
   if (st) {
     h->state = 2;
     return st;
@@ -1237,15 +1310,18 @@ extern "C" ftk_status ftk_cp_finish(ftk_tracker* h, ftk_cp_result* out) {
   if (h->state != 0) return fail(FTK_ERR_STATE, "tracker already finished or failed");
   if (h->steps < 2) return fail(FTK_ERR_STATE, "at least two steps must be pushed");
   h->state = 1;
-  if (h->n == 3) {
-    ftk_status st = ftk::track3d_impl(h->all, h->nx, h->ny, h->nz, h->steps, h->o, h->s, out);
-    return st;
-  }
   const int N = h->steps;
   Ctl* dctl = (Ctl*)h->dctl;
-  ftk_status st = ftk::tracker_detect(h, N - 1, N);
-  if (!st) st = ftk::tracker_emit(h, N - 2, N);
-  if (!st) st = ftk::tracker_emit(h, N - 1, N);
+  ftk_status st;
+  if (h->n == 2) {
+    st = ftk::tracker_detect(h, N - 1, N);
+    if (!st) st = ftk::tracker_emit(h, N - 2, N);
+    if (!st) st = ftk::tracker_emit(h, N - 1, N);
+  } else {
+    st = ftk::tracker_detect3(h, N - 1, N);
+    if (!st) st = ftk::tracker_emit3(h, N - 2, N);
+    if (!st) st = ftk::tracker_emit3(h, N - 1, N);
+  }
   if (st) return st;
   const long long nh = h->total_after[N - 1];
   const Alloc al = ftk::tracker_alloc(h);
@@ -1264,7 +1340,7 @@ extern "C" ftk_status ftk_cp_finish(ftk_tracker* h, ftk_cp_result* out) {
     return st;
   }
   ftk_cp_result& r = *out;
-  r.n = 2;
+  r.n = h->n;
   r.n_hits = nh;
   r.n_trajectories = (long long)hc.cnt[ftk::CNT_TRAJ];
   r.face_id = (int64_t*)h->face_id;
@@ -1276,8 +1352,8 @@ extern "C" ftk_status ftk_cp_finish(ftk_tracker* h, ftk_cp_result* out) {
   h->face_id = nullptr;
   h->pos = h->mu = nullptr;
   h->type = h->flags = nullptr;
-  int64_t dims[3] = {h->nx, h->ny, N};
-  r.stats.simplices_tested = count_tested(2, dims);
+  int64_t dims[4] = {h->nx, h->ny, h->n == 3 ? h->nz : N, N};
+  r.stats.simplices_tested = count_tested(h->n, dims);
   r.stats.cells_linked = (long long)hc.cnt[ftk::CNT_LINKED];
   r.stats.fp64_fallbacks = (long long)hc.cnt[ftk::CNT_FP64];
   r.stats.degenerate_sublocations = (long long)hc.cnt[ftk::CNT_DEGEN];

@@ -57,6 +57,9 @@ struct Q3<true> {
   typedef long long T;
 };
 
+__device__ __forceinline__ long long fpl3(const Grid3& g, int t) { return g.f_ring ? t % g.f_ring : t; }
+__device__ __forceinline__ long long mpl3(const Grid3& g, int t) { return g.m_ring ? t % g.m_ring : t; }
+
 template <bool WIDE>
 __device__ __forceinline__ typename Q3<WIDE>::T to_q3(float r, unsigned& st) {
   if (!WIDE) {
@@ -242,12 +245,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
   const int x0 = blockIdx.x * TX3;
   const int by = blockIdx.y % nyt, bz = blockIdx.y / nyt;
   const int y0 = by * TY3, z0 = bz * TZ3;
-  const int t0 = blockIdx.z * TT, t1 = min(t0 + TT, nt);
+  const int t0 = g.t_begin + blockIdx.z * TT, t1 = min(t0 + TT, g.t_end);
   const long long plane = (long long)nx * ny * nz;
   unsigned st = 0;
 
   auto quantise_plane = [&](int tq, int par) {
-    const float* src = g.f + (long long)tq * plane;
+    const float* src = g.f + fpl3(g, tq) * plane;
     const long long sxy = (long long)nx * ny;
     for (int e = tid; e < QN; e += 256) {
       int lx = e % QX, r = e / QX, ly = r % QY, lz = r / QY;
@@ -407,14 +410,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
         if (gz == nz - 1) valid &= ~kTetUseZ;
         if (t == nt - 1) valid &= ~kTetUseT;
         m &= valid;
-        masks[(((long long)t * nz + gz) * ny + gy) * nx + gx] = m;
+        masks[((mpl3(g, t) * nz + gz) * ny + gy) * nx + gx] = m;
       }
       // count per 16-lane row segment
       unsigned c = (unsigned)__popcll(m);
 #pragma unroll
       for (int d = 8; d >= 1; d >>= 1) c += __shfl_xor(c, d, 16);
       if (lx == 0 && gy < ny && gz < nz)
-        seg_cnt[(((long long)t * nz + gz) * ny + gy) * g.nxt + blockIdx.x] = (int)c;
+        seg_cnt[((mpl3(g, t) * nz + gz) * ny + gy) * g.nxt + blockIdx.x] = (int)c;
     }
   }
   if (st) atomicOr(status, st);
@@ -429,8 +432,9 @@ struct Field3 {
   const float* f;
   int nx, ny, nz;
   long long plane;
+  int ring;  // steps stored as a ring of `ring` slots (0: step t at t)
   __device__ __forceinline__ float s(int x, int y, int z, int t) const {
-    return f[(long long)t * plane + ((long long)z * ny + y) * nx + x];
+    return f[(long long)(ring ? t % ring : t) * plane + ((long long)z * ny + y) * nx + x];
   }
   __device__ __forceinline__ float grad(int c, int x, int y, int z, int t) const {
     const int N = c == 0 ? nx : (c == 1 ? ny : nz);
@@ -517,9 +521,9 @@ __global__ __launch_bounds__(256) void emit3d_rows(Grid3 g, const uint64_t* __re
   if (row >= nvtx_rows * xblocks) return;
   const long long r = row / xblocks;
   const int x = (int)(row - r * xblocks) * 64 + lane;
-  const int y = (int)(r % ny), z = (int)((r / ny) % nz), t = (int)(r / ((long long)ny * nz));
+  const int y = (int)(r % ny), z = (int)((r / ny) % nz), t = g.t_begin + (int)(r / ((long long)ny * nz));
   const long long plane = (long long)nx * ny * nz;
-  const unsigned long long m = x < nx ? masks[(long long)t * plane + ((long long)z * ny + y) * nx + x] : 0ull;
+  const unsigned long long m = x < nx ? masks[mpl3(g, t) * plane + ((long long)z * ny + y) * nx + x] : 0ull;
   if (__ballot(m != 0) != 0 && lane == 0) list[atomicAdd(list_n, 1ull)] = row;
 }
 
@@ -540,11 +544,12 @@ __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restric
   const long long r = row / xblocks;
   const int xb = (int)(row - r * xblocks);
   const int x = xb * 64 + lane;
-  const int y = (int)(r % ny), z = (int)((r / ny) % nz), t = (int)(r / ((long long)ny * nz));
+  const int y = (int)(r % ny), z = (int)((r / ny) % nz), t = g.t_begin + (int)(r / ((long long)ny * nz));
   const bool in = x < nx;
   const long long plane = (long long)nx * ny * nz;
-  const long long gidx = (long long)t * plane + ((long long)z * ny + y) * nx + x;
-  const unsigned long long m = in ? masks[gidx] : 0ull;
+  const long long vofs = ((long long)z * ny + y) * nx + x;
+  const long long gidx = (long long)t * plane + vofs;  // global vertex index (face ids)
+  const unsigned long long m = in ? masks[mpl3(g, t) * plane + vofs] : 0ull;
   if (__ballot(m != 0) == 0) return;
   unsigned st = 0;
   unsigned long long n_deg = 0, n_linked = 0;
@@ -552,17 +557,17 @@ __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restric
   // first-hit index of vertex u (global coordinates, inside the grid): segment offset + hits of the earlier
   // vertices of its 16-vertex segment
   auto first_hit = [&](int ux, int uy, int uz, int ut) -> unsigned {
-    const long long seg = (((long long)ut * nz + uz) * ny + uy) * nxt + ux / SEG3;
+    const long long seg = ((mpl3(g, ut) * nz + uz) * ny + uy) * nxt + ux / SEG3;
     unsigned off = (unsigned)seg_off[seg];
-    const long long ub = (long long)ut * plane + ((long long)uz * ny + uy) * nx;
+    const long long ub = mpl3(g, ut) * plane + ((long long)uz * ny + uy) * nx;
     for (int xx = (ux / SEG3) * SEG3; xx < ux; ++xx) off += (unsigned)__popcll(masks[ub + xx]);
     return off;
   };
   auto mask_at = [&](int ux, int uy, int uz, int ut) -> unsigned long long {
-    return masks[(long long)ut * plane + ((long long)uz * ny + uy) * nx + ux];
+    return masks[mpl3(g, ut) * plane + ((long long)uz * ny + uy) * nx + ux];
   };
 
-  Field3 F{g.f, nx, ny, nz, plane};
+  Field3 F{g.f, nx, ny, nz, plane, g.f_ring};
   unsigned long long rem = m;
   if (rem) {
     unsigned k = 0;
@@ -754,7 +759,8 @@ __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restric
 hipError_t launch_detect3d(const Grid3& g, int tt, bool wide, uint64_t* masks, int* seg_cnt, unsigned* status,
                            hipStream_t s) {
   const int nyt = (g.ny + TY3 - 1) / TY3, nzt = (g.nz + TZ3 - 1) / TZ3;
-  dim3 grid((unsigned)((g.nx + TX3 - 1) / TX3), (unsigned)(nyt * nzt), (unsigned)((g.nt + tt - 1) / tt));
+  dim3 grid((unsigned)((g.nx + TX3 - 1) / TX3), (unsigned)(nyt * nzt),
+            (unsigned)((g.t_end - g.t_begin + tt - 1) / tt));
   if (wide)
     detect3d<true><<<grid, 256, 0, s>>>(g, tt, nyt, masks, seg_cnt, status);
   else
@@ -765,7 +771,7 @@ hipError_t launch_detect3d(const Grid3& g, int tt, bool wide, uint64_t* masks, i
 hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const long long* seg_off, long long n_hits,
                          const Out3& o, unsigned* status, unsigned long long* cnt, long long* list,
                          unsigned long long* list_n, hipStream_t s) {
-  const long long rows = (long long)g.nt * g.nz * g.ny;
+  const long long rows = (long long)(g.t_end - g.t_begin) * g.nz * g.ny;
   const long long waves = rows * ((g.nx + 63) / 64);
   emit3d_rows<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(g, masks, rows, list, list_n);
   // at most one listed wavefront per hit

@@ -48,10 +48,13 @@ struct Series2 {
 // 3D problem description.
 struct Grid3 {
   const float* f;
-  int nx, ny, nz, nt;
+  int nx, ny, nz, nt;  // nt: number of steps of the series (a large value while a stream is still open)
   int nxt;
   float qscale;
   int precision;
+  int t_begin = 0, t_end = 0;  // anchors processed by a launch: steps [t_begin, t_end)
+  int f_ring = 0;  // field steps stored as a ring of f_ring steps (step t at slot t % f_ring); 0: step t at t
+  int m_ring = 0;  // same for the puncture masks and the per-segment counts/offsets
 };
 
 struct Out3 {

@@ -57,7 +57,34 @@ def test_stream_2d_vector_and_degenerate():
 def test_stream_3d():
     f = synth.moving_gaussians_3d(30, 20, 18, 5, 8, seed=4)
     r = _stream(f, 3)
+    _same(r, F.track_cp3d(torch.from_numpy(f).to(DEV)))
     assert_full_parity(r, O.track(f, n=3))
+
+
+def test_stream_3d_longer_than_the_window():
+    """The 3D tracker keeps a window of three steps (Sec. 3.2: every simplex lies within two consecutive steps):
+    a series several times longer than the window, with ragged tiles and integer-valued ties, equals the one-shot
+    call and the oracle, and the tracker's device memory does not grow with the number of steps pushed."""
+    f = synth.moving_gaussians_3d(19, 13, 10, 11, 6, seed=8)
+    r = _stream(f, 3)
+    _same(r, F.track_cp3d(torch.from_numpy(f).to(DEV)))
+    assert_full_parity(r, O.track(f, n=3))
+    rng = np.random.default_rng(9)
+    g = (rng.integers(0, 3, size=(9, 5, 6, 7)) * 2.0 ** -19).astype(np.float32)
+    assert_full_parity(_stream(g, 3), O.track(g, n=3))
+    # memory held by the tracker itself (window, masks, offsets) after 3 and after 12 pushed steps of a field
+    # without hits: equal (outputs grow only with the hits)
+    z = torch.zeros((10, 12, 16), device=DEV)  # one step [nz][ny][nx]
+    tr = F.Tracker(3, [16, 12, 10])
+    held = []
+    for t in range(12):
+        tr.push(z)
+        if t in (2, 11):
+            torch.cuda.synchronize()
+            held.append(sum(v.numel() for v in tr.pool.live.values()))
+    tr.finish()
+    tr.close()
+    assert held[0] == held[1]
 
 
 def test_stream_state_errors():
