@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--workload", default="noise1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-post", action="store_true", help="skip the trajectory post-processing timings")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the other configurations' precision and batch reports")
     ap.add_argument("--cpu-steps", type=int, default=0, help="time steps of the oracle sample (0: automatic)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration) and exit")
@@ -92,9 +94,9 @@ def measured_counters(kernel, workload):
         return None
 
 
-def bench_batched(args, F, synth, dev):
-    """Batched form (one persistent launch per stage for all 96 series) against 96 plain calls."""
-    import numpy as np
+def batch_compare(F, synth, dev, steps, warmup):
+    """The 96-series workload: one batched call (one persistent launch per stage for all series) against 96 plain
+    calls, each timed over `steps` repetitions after `warmup`.  Returns (report, fields, tested simplices)."""
     import torch
     t0 = time.time()
     fields = synth.batch_series(count=96, seed0=3, device=dev)
@@ -116,14 +118,14 @@ def bench_batched(args, F, synth, dev):
         return sum(F.track_cp2d(t)["n_hits"] for t in ts)
 
     def timed(fn):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             nh = fn()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t) / args.steps, nh
+        return (time.perf_counter() - t) / steps, nh
 
     tb, nhb = timed(batched)
     tp, nhp = timed(plain)
@@ -132,28 +134,53 @@ def bench_batched(args, F, synth, dev):
     st = F.track_cp2d_batched(ts, profile=1)[0]["stats"]
     torch.cuda.synchronize()
     phases = {"detect2d": round(st["t_detect_ms"], 3), "scan": round(st["t_scan_ms"], 3),
-              "emit2d": round(st["t_emit_ms"], 3), "uf_label": round(st["t_link_ms"], 3)}
+              "emit2d": round(st["t_emit_ms"], 3), "uf_link": round(st["t_link_ms"], 3)}
+    steps_total = sum(f.shape[0] for f in fields)
+    rep = {"workload": WORKLOADS["batch96"], "series": len(fields), "time_steps_total": steps_total,
+           "vertices_total": int(sum(f.size for f in fields)), "n_hits": nhb, "generation_s": round(gen_s, 1),
+           "batched": {"steps_per_s": round(steps_total / tb, 1), "ms_per_batch": round(tb * 1e3, 3),
+                       "phase_ms": phases},
+           "plain": {"steps_per_s": round(steps_total / tp, 1), "ms_per_batch": round(tp * 1e3, 3)},
+           "batched_over_plain": round(tp / tb, 3), "timed_calls": steps}
+    return rep, tested, tb
+
+
+def bench_batched(args, F, synth, dev):
+    """Batched form (one persistent launch per stage for all 96 series) against 96 plain calls."""
+    rep, tested, tb = batch_compare(F, synth, dev, args.steps, args.warmup)
     line = {
         "metric": "spacetime simplices tested/s + HBM roofline frac; batched vs plain steps/s",
         "value": round(tested / tb, 1), "unit": "simplices/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": WORKLOADS["batch96"], "series": len(fields), "time_steps_total": steps_total,
-                   "vertices_total": int(sum(f.size for f in fields)), "n_hits": nhb, "generation_s": round(gen_s, 1)},
-        "batched": {"steps_per_s": round(steps_total / tb, 1), "ms_per_batch": round(tb * 1e3, 3),
-                    "phase_ms": phases},
-        "plain": {"steps_per_s": round(steps_total / tp, 1), "ms_per_batch": round(tp * 1e3, 3)},
-        "batched_over_plain": round(tp / tb, 3),
+        "config": {k: rep[k] for k in ("workload", "series", "time_steps_total", "vertices_total", "n_hits",
+                                       "generation_s")},
+        "batched": rep["batched"], "plain": rep["plain"], "batched_over_plain": rep["batched_over_plain"],
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 
 
 def precision_report(F, field_np, field, kind, n, sample=20000):
-    """FP32 sublocation/classification of sampled hits against the binary64 oracle (per-result errors)."""
+    """Per-result error of the default FP32 path (FP32 sublocation and classification, FP64 only where the FP32
+    type is not certified) against binary64: over every hit against the library's FP64 mode (precision = 1, the
+    oracle's binary64 operation order), and over a sample of hits against the oracle itself."""
     import numpy as np
+    import torch
     from oracle import oracle as O
-    r = F.track_cp2d(field, kind=kind)
+    run = (lambda **kw: F.track_cp2d(field, kind=kind, **kw)) if n == 2 else (lambda **kw: F.track_cp3d(field, **kw))
+    r = run()
+    r64 = run(precision=1)
+    torch.cuda.synchronize()
+    same_faces = r["n_hits"] == r64["n_hits"] and bool(torch.equal(r["face_id"], r64["face_id"]))
+    p32, p64 = r["pos"].double(), r64["pos"].double()
+    rel = (p32 - p64).abs() / p64.abs().clamp(min=1.0)
+    nh = r["n_hits"]
+    all_hits = {"hits": nh, "faces_identical": same_faces,
+                "type_agree": float((r["type"] == r64["type"]).double().mean()) if nh else 1.0,
+                "labels_identical": bool(torch.equal(r["label"], r64["label"])),
+                "pos_rel_err_max": float(rel.max()) if nh else 0.0,
+                "pos_rel_err_mean": float(rel.mean()) if nh else 0.0}
     fid = r["face_id"].cpu().numpy()
     pos = r["pos"].cpu().numpy().astype(np.float64)
     typ = r["type"].cpu().numpy()
@@ -162,11 +189,12 @@ def precision_report(F, field_np, field, kind, n, sample=20000):
     idx = rng.choice(len(fid), min(sample, len(fid)), replace=False)
     ev = O.eval_faces(field_np, fid[idx], n=n, kind=kind)
     err = np.abs(pos[idx] - ev["pos"]) / np.maximum(1.0, np.abs(ev["pos"]))
-    return {"hits": int(len(fid)), "sampled": int(len(idx)), "punctured_agree": bool(np.all(ev["punctured"] == 1)),
-            "type_agree": float(np.mean(typ[idx] == ev["type"])), "pos_rel_err_max": float(err.max()),
-            "pos_rel_err_mean": float(err.mean()), "tolerance": 1e-5,
-            "fp64_fallback_frac": float(np.mean((flg & 2) != 0)),
-            "degenerate_frac": float(np.mean((flg & 1) != 0))}
+    oracle = {"sampled": int(len(idx)), "punctured_agree": bool(np.all(ev["punctured"] == 1)),
+              "type_agree": float(np.mean(typ[idx] == ev["type"])), "pos_rel_err_max": float(err.max()),
+              "pos_rel_err_mean": float(err.mean())}
+    return {"vs_fp64_mode_all_hits": all_hits, "vs_oracle_sample": oracle, "tolerance": 1e-5,
+            "fp64_fallback_frac": float(np.mean((flg & 2) != 0)) if nh else 0.0,
+            "degenerate_frac": float(np.mean((flg & 1) != 0)) if nh else 0.0}
 
 
 def bench_iso(args, F, synth, dev):
@@ -479,7 +507,7 @@ def main():
     V = int(np.prod(dims))
     in_bytes = V * 4 * (n if kind == 1 else 1)
     rec = 22 if n == 2 else 26  # face_id 8 + pos 4*(n+1) + type 1 + flags 1
-    names = ["detect%dd" % n, "scan", "emit%dd" % n, "uf_label"]
+    names = ["detect%dd" % n, "scan", "emit%dd" % n, "uf_label"]  # uf_label: hooking + labels (8 B per hit out)
     alg = [in_bytes, 0, rec * nh, 8 * nh]
     k = int(np.argmax(phase))
     kernel = names[k]
@@ -493,6 +521,9 @@ def main():
         valu_busy = round(counters["valu_insts_per_launch"] / (phase[k] * 1e-3 * VALU_ISSUE_PEAK), 3)
     roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "valu_busy": valu_busy,
+                "traffic_source": (f"profiles/traffic_{kernel}_{wl}.json: rocprofv3 FETCH_SIZE / WRITE_SIZE and SQ "
+                                   f"counters of the committed source (not measured in this run)") if counters else
+                                  "none: the committed counter runs predate this source",
                 "avg_ms": round(float(phase[k]), 4),
                 "phase_ms": {nm: round(float(p), 4) for nm, p in zip(names, phase)},
                 "path_frac": round((in_bytes + (rec + 8) * nh) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -518,8 +549,23 @@ def main():
     post = None if args.no_post else post_report(F, field, n, kind, dims)
 
     precision = None
-    if wl == "vortex4096":
-        precision = precision_report(F, field_np, field, kind, n)
+    if wl in ("vortex4096", "blobs3d256", "noise1024"):
+        precision = {wl: precision_report(F, field_np, field, kind, n)}
+    batch = None
+    if wl == "noise1024" and not args.no_extras:
+        # the other configurations' evidence on the default run: FP32-vs-FP64 errors of the 4096^2 vector series
+        # and the 256^3 3D series, and the 96-series batched-over-plain ratio (outside the timed region)
+        del field
+        torch.cuda.empty_cache()
+        for other in ("vortex4096", "blobs3d256"):
+            o_np = synth.make(other, device=dev)
+            o_dev = torch.from_numpy(o_np).to(dev)
+            precision[other] = precision_report(F, o_np, o_dev, 1 if other == "vortex4096" else 0,
+                                                3 if other == "blobs3d256" else 2,
+                                                sample=20000 if other == "vortex4096" else 2000)
+            del o_np, o_dev
+            torch.cuda.empty_cache()
+        batch, _, _ = batch_compare(F, synth, dev, steps=5, warmup=2)
 
     line = {
         "metric": "spacetime simplices tested/s + HBM roofline frac; batched vs plain steps/s",
@@ -537,6 +583,8 @@ def main():
         line["post"] = post
     if precision is not None:
         line["precision"] = precision
+    if batch is not None:
+        line["batch96"] = batch
     print(json.dumps(line), flush=True)
 
 
