@@ -109,6 +109,11 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
   const int nx = g.nx, ny = g.ny, nt = g.nt;
   const long long plane = (long long)nx * ny;
   unsigned st = 0;
+  unsigned facts = 0x1Fu;  // sign facts of the vectors quantised by this thread since the last plane_facts()
+  auto fact_bits = [](Q a, Q b) -> unsigned {
+    return (a > (Q)0 ? 1u : 0u) | (a < (Q)0 ? 2u : 0u) | (b > (Q)0 ? 4u : 0u) | (b < (Q)0 ? 8u : 0u) |
+           ((a == (Q)0 && b == (Q)0) ? 16u : 0u);
+  };
 
   // Load plane t: scalar input into fs (FH x FW with halo); vector input straight into qs[par] (quantised).
   auto load_plane = [&](int t, int par) {
@@ -125,19 +130,22 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
         fs[e] = v;
       }
     } else {
-      for (int c = 0; c < 2; ++c) {
-        const float* src = g.f + ((long long)fpl(g, t) * 2 + c) * plane;
-        for (int e = tid; e < QH * QW; e += 256) {
-          int ly = e / QW, lx = e - ly * QW;
-          int gx = x0 + lx, gy = y0 + ly;
-          Q q = 0;
-          if (gx < nx && gy < ny) {
-            const float v = src[(long long)gy * nx + gx];
-            if (!isfinite(v)) st |= ST_NONFINITE;
-            q = to_q<WIDE>(quant(v, g.qscale), st);
-          }
-          qs[par][c][e] = q;
+      const float* su = g.f + (long long)fpl(g, t) * 2 * plane;
+      const float* sv = su + plane;
+      for (int e = tid; e < QH * QW; e += 256) {
+        int ly = e / QW, lx = e - ly * QW;
+        int gx = x0 + lx, gy = y0 + ly;
+        Q q0 = 0, q1 = 0;
+        if (gx < nx && gy < ny) {
+          const long long k = (long long)gy * nx + gx;
+          const float v0 = su[k], v1 = sv[k];
+          if (!isfinite(v0) || !isfinite(v1)) st |= ST_NONFINITE;
+          q0 = to_q<WIDE>(quant(v0, g.qscale), st);
+          q1 = to_q<WIDE>(quant(v1, g.qscale), st);
+          facts &= fact_bits(q0, q1);
         }
+        qs[par][0][e] = q0;
+        qs[par][1][e] = q1;
       }
     }
   };
@@ -155,6 +163,7 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
         const float v1 = diff3(r[-FW], r[0], r[FW], gy, ny);
         q0 = to_q<WIDE>(quant(v0, g.qscale), st);
         q1 = to_q<WIDE>(quant(v1, g.qscale), st);
+        facts &= fact_bits(q0, q1);
       }
       qs[par][0][e] = q0;
       qs[par][1][e] = q1;
@@ -227,38 +236,71 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
   __shared__ unsigned short s_lut[8][128];
   for (int i = tid; i < 8 * 128; i += 256) s_lut[i >> 7][i & 127] = kTri2Lut.t[i >> 7][i & 127];
 
-  // prologue: plane t0
+  // Sign facts of a plane's quantised vectors over the tile (anchors and their +1 neighbours, inside the grid):
+  // bit 0 every x component > 0, bit 1 every x < 0, bit 2 every y > 0, bit 3 every y < 0, bit 4 every vector zero.
+  // When a fact holds on both planes of a step, no triangle anchored in the tile at that step is punctured: a
+  // component of one strict sign at all three vertices keeps that sign under the symbolic perturbation (its
+  // entries move by infinitesimals only), so the origin is outside the triangle; and with all vectors zero every
+  // edge determinant takes the perturbation's last, negative term, so the three cofactor signs never agree.  The
+  // edge and triangle passes of such a step are skipped (its masks and counts are zero).
+  __shared__ unsigned s_fact[2];
+  __shared__ int s_ord_ok[2];  // the ordinal edge words of the plane slot have been computed
+  const int wave = tid >> 6, lane = tid & 63;
+  auto plane_facts = [&](int p) {  // block reduction of the facts gathered while the plane was quantised
+    const unsigned bits = facts;
+    facts = 0x1Fu;
+    unsigned wb = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      if (__ballot(!((bits >> k) & 1u)) == 0) wb |= 1u << k;
+    if (lane == 0) atomicAnd(&s_fact[p], wb);
+  };
+
+  // prologue: plane t0 (its ordinal edges are formed when a step first needs them)
+  if (tid == 0) {
+    s_fact[t0 & 1] = 0x1Fu;
+    s_ord_ok[0] = s_ord_ok[1] = 0;
+  }
+  __syncthreads();
   load_plane(t0, t0 & 1);
   __syncthreads();
   quantise_plane(t0 & 1);
-  __syncthreads();
-  ordinal_edges(t0 & 1);
+  plane_facts(t0 & 1);
 
-  const int wave = tid >> 6, lane = tid & 63;
   const int gx = x0 + lane;
   for (int t = t0; t < t1; ++t) {
     const int par = t & 1, nxp = par ^ 1;
     const bool has_next = (t + 1 < nt);
-    __syncthreads();  // previous triangle pass done with ew / fs
+    __syncthreads();  // previous triangle pass done with ew / fs; facts and edge flags of plane t visible
     if (has_next) {
+      if (tid == 0) s_fact[nxp] = 0x1Fu;  // ordered before the atomics by the barrier after the load
       load_plane(t + 1, nxp);
       __syncthreads();
       quantise_plane(nxp);
-      __syncthreads();
-      if constexpr (!WIDE) {
-        fused_edges(par);
-      } else {
-        ordinal_edges(nxp);
-        interval_edges(par);
+      plane_facts(nxp);
+      __syncthreads();  // quantised plane and its facts visible
+    }
+    const bool certified = (s_fact[par] & (has_next ? s_fact[nxp] : 0x1Fu)) != 0u;  // uniform
+    const bool ord_ok = s_ord_ok[par] != 0;
+    if (!certified) {
+      if (!ord_ok) ordinal_edges(par);  // each thread ORs into the words it assigned here
+      if (has_next) {
+        if constexpr (!WIDE) {
+          fused_edges(par);
+        } else {
+          ordinal_edges(nxp);
+          interval_edges(par);
+        }
       }
     }
     __syncthreads();
+    if (tid == 0 && has_next) s_ord_ok[nxp] = certified ? 0 : 1;
 
     // triangle tests: wave w handles rows w, w+4, ...
     for (int ly = wave; ly < TY; ly += 4) {
       const int gy = y0 + ly;
       unsigned m = 0;
-      if (gx < nx && gy < ny) {
+      if (gx < nx && gy < ny && !certified) {
         const int a = ly * EW + lane;
         // word of the anchor and of its neighbours p + e(M1): plane t for M1 in {x, y, xy}, plane t+1 (ordinal
         // bits only) for M1 in {t, xt, yt}
@@ -276,8 +318,8 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
         if (gy == ny - 1) valid &= ~kUseY;
         if (t == nt - 1) valid &= ~kUseT;
         m &= valid;
-        masks[((long long)mpl(g, t) * ny + gy) * nx + gx] = (uint16_t)m;
       }
+      if (gx < nx && gy < ny) masks[((long long)mpl(g, t) * ny + gy) * nx + gx] = (uint16_t)m;
       unsigned c = wave_sum(__popc(m));
       if (lane == 0 && gy < ny) seg_cnt[((long long)mpl(g, t) * ny + gy) * g.nxt + bx] = (int)c;
     }

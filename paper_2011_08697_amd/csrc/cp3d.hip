@@ -248,6 +248,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
   const int t0 = g.t_begin + blockIdx.z * TT, t1 = min(t0 + TT, g.t_end);
   const long long plane = (long long)nx * ny * nz;
   unsigned st = 0;
+  unsigned facts = 0x7Fu;  // sign facts of the gradients quantised by this thread since the last plane_facts()
 
   auto quantise_plane = [&](int tq, int par) {
     const float* src = g.f + fpl3(g, tq) * plane;
@@ -269,6 +270,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
         q0 = to_q3<WIDE>(quant(v0, g.qscale), st);
         q1 = to_q3<WIDE>(quant(v1, g.qscale), st);
         q2 = to_q3<WIDE>(quant(v2, g.qscale), st);
+        facts &= (q0 > (Q)0 ? 1u : 0u) | (q0 < (Q)0 ? 2u : 0u) | (q1 > (Q)0 ? 4u : 0u) | (q1 < (Q)0 ? 8u : 0u) |
+                 (q2 > (Q)0 ? 16u : 0u) | (q2 < (Q)0 ? 32u : 0u) |
+                 ((q0 == (Q)0 && q1 == (Q)0 && q2 == (Q)0) ? 64u : 0u);
       }
       qs[par][0][e] = q0;
       qs[par][1][e] = q1;
@@ -361,21 +365,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
       tris(par, 12, 50, false);
   };
 
-  quantise_plane(t0, t0 & 1);
+  // Sign facts of a plane's quantised gradients over the tile (anchors and their +1 neighbours, inside the grid):
+  // bits 2c / 2c+1: component c > 0 / < 0 at every vertex; bit 6: every vector zero.  When a fact holds on both
+  // planes of a step, no tetrahedron anchored in the tile at that step is punctured: a component of one strict
+  // sign at all four vertices keeps its sign under the symbolic perturbation, so the origin is outside; with all
+  // vectors zero every triangle determinant takes the perturbation's last term (-1), so the four cofactor signs
+  // never agree.  The triangle and tetrahedron passes of such a step are skipped (masks and counts zero).
+  __shared__ unsigned s_fact[2];
+  __shared__ int s_ord_ok[2];  // the ordinal triangle words of the plane slot have been computed
+  const int lane = tid & 63;
+  auto plane_facts = [&](int p) {  // block reduction of the facts gathered while the plane was quantised
+    const unsigned bits = facts;
+    facts = 0x7Fu;
+    unsigned wb = 0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+      if (__ballot(!((bits >> k) & 1u)) == 0) wb |= 1u << k;
+    if (lane == 0) atomicAnd(&s_fact[p], wb);
+  };
+
+  if (tid == 0) {
+    s_fact[0] = s_fact[1] = 0x7Fu;
+    s_ord_ok[0] = s_ord_ok[1] = 0;
+  }
   __syncthreads();
-  ordinal_tris(t0 & 1);
+  quantise_plane(t0, t0 & 1);
+  plane_facts(t0 & 1);
 
   for (int t = t0; t < t1; ++t) {
     const int par = t & 1, nxp = par ^ 1;
     const bool has_next = t + 1 < nt;
-    __syncthreads();
-    if (has_next) {
+    __syncthreads();  // previous tetrahedron pass done; facts and flags of plane t visible
+    if (has_next) {  // s_fact[nxp] was reset at the end of the previous step (or in the prologue)
       quantise_plane(t + 1, nxp);
-      __syncthreads();
-      ordinal_tris(nxp);
-      interval_tris(par);
+      plane_facts(nxp);
+      __syncthreads();  // quantised plane and its facts visible
+    }
+    const bool certified = (s_fact[par] & (has_next ? s_fact[nxp] : 0x7Fu)) != 0u;  // uniform
+    if (!certified) {
+      if (s_ord_ok[par] == 0) ordinal_tris(par);  // each thread ORs into the words it assigned here
+      if (has_next) {
+        ordinal_tris(nxp);
+        interval_tris(par);
+      }
     }
     __syncthreads();
+    if (tid == 0) {
+      if (has_next) s_ord_ok[nxp] = certified ? 0 : 1;
+      s_fact[par] = 0x7Fu;  // plane t's facts are not read again; the slot receives plane t + 2's
+    }
 
     // 60 tetrahedron tests for the TX x TY x TZ anchors, 2 per thread; lanes of a wave: 16 x 4 rows
     for (int a = tid; a < TX3 * TY3 * TZ3; a += 256) {
@@ -383,7 +421,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
       const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
       unsigned long long m = 0;
       const bool in = gx < nx && gy < ny && gz < nz;
-      if (in) {
+      if (in && !certified) {
         const int w0 = (lz * WY + ly) * WX + lx;
         unsigned long long W[16];
 #pragma unroll
@@ -410,8 +448,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
         if (gz == nz - 1) valid &= ~kTetUseZ;
         if (t == nt - 1) valid &= ~kTetUseT;
         m &= valid;
-        masks[((mpl3(g, t) * nz + gz) * ny + gy) * nx + gx] = m;
       }
+      if (in) masks[((mpl3(g, t) * nz + gz) * ny + gy) * nx + gx] = m;
       // count per 16-lane row segment
       unsigned c = (unsigned)__popcll(m);
 #pragma unroll

@@ -120,3 +120,19 @@ def test_zero_at_shared_vertex_goes_to_exactly_one_triangle():
         tr = O.track(u, n=2, kind=1)
         ordinal = [f for f in tr.face_id if f % 12 in (0, 3) and (f // 12) // 9 == 0]
         assert len(ordinal) == 1
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_strictly_signed_component_or_all_zero_is_never_punctured(n):
+    """The facts the detection kernels use to skip a tile-step: if one component has the same strict sign at every
+    vertex of a simplex, the perturbed vectors keep that sign and the origin is outside; if every vector is zero,
+    the cofactor signs never agree.  Checked on the oracle's predicate (the SoS expansion) with ties everywhere in
+    the other components."""
+    rng = np.random.default_rng(20 + n)
+    for _ in range(3000):
+        V = rng.integers(-2, 3, size=(n + 1, n)).astype(np.int64)
+        c = rng.integers(0, n)
+        sign = 1 if rng.random() < 0.5 else -1
+        V[:, c] = sign * rng.integers(1, 3, size=n + 1)
+        assert O.face_punctured(V) == 0
+    assert O.face_punctured(np.zeros((n + 1, n), np.int64)) == 0
