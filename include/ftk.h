@@ -93,9 +93,14 @@ typedef struct {
  * the 2D emission with tiny workgroup-local capacities (union-find chunk and link stage), so that tile steps overflow
  * them and take the global-list paths; results are unchanged.  FTK_DEBUG_INVARIANT makes the 2D emission report a
  * cell with a wrong punctured-side count at time step (debug >> 8), so that tests can check how the error reaches
- * the caller (every form returns FTK_ERR_INVARIANT). */
+ * the caller (every form returns FTK_ERR_INVARIANT).  FTK_DEBUG_TILED_EMIT and FTK_DEBUG_SPARSE_EMIT force the 2D
+ * emission form of the one-shot and batched calls (tiles marching through time, or one wavefront per non-empty row
+ * segment; by default the sparse form runs below one hit per 128 vertices, FTK_DEBUG_SMALL_LDS implies the tiled
+ * form); results are identical. */
 #define FTK_DEBUG_SMALL_LDS 1
 #define FTK_DEBUG_INVARIANT 2
+#define FTK_DEBUG_TILED_EMIT 4
+#define FTK_DEBUG_SPARSE_EMIT 8
 
 typedef struct {
   int64_t simplices_tested; /* n-simplices tested (the throughput numerator) */

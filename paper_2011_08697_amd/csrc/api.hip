@@ -310,6 +310,16 @@ void set_debug(Grid2& g, const ftk_options& o) {
   g.debug_step = (o.debug & FTK_DEBUG_INVARIANT) ? (int)((unsigned)o.debug >> 8) : -1;
 }
 
+// Emission form for a call (or a series of a batch): the sparse one (a wavefront per non-empty row segment) when
+// hits are rare, below one per kSparseVertices vertices, else the tiled one.  Both give identical outputs; the
+// FTK_DEBUG_TILED_EMIT / FTK_DEBUG_SPARSE_EMIT test hooks force either.
+constexpr long long kSparseVertices = 128;
+bool sparse_emission(const Grid2& g, long long n_hits, long long n_vertices) {
+  if (g.debug & FTK_DEBUG_SPARSE_EMIT) return true;
+  if (g.debug & (FTK_DEBUG_TILED_EMIT | FTK_DEBUG_SMALL_LDS)) return false;  // the hook tests the tiled form
+  return n_hits * kSparseVertices < n_vertices;
+}
+
 ftk_status validate_options(const ftk_options& o) {
   if (o.quant_log2 < 0 || o.quant_log2 > 40) return fail(FTK_ERR_ARG, "quant_log2 must be in [0, 40]");
   if (o.precision != 0 && o.precision != 1) return fail(FTK_ERR_ARG, "precision must be 0 or 1");
@@ -428,6 +438,20 @@ __global__ void zero_words(unsigned* p, int n) {
 }
 
 // Clears the control block with a kernel (no memset node, so the sequence is safe under stream capture too).
+// n words set to v (a kernel rather than hipMemsetAsync: the 2D one-shot call may run under graph capture)
+__global__ void fill_words(unsigned* p, unsigned v, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_words(unsigned* p, unsigned v, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  fill_words<<<(unsigned)blocks, 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
 hipError_t clear_ctl(Ctl* d, hipStream_t s) {
   constexpr int n = (int)(sizeof(Ctl) / sizeof(unsigned));
   zero_words<<<1, 64, 0, s>>>((unsigned*)d, n);
@@ -535,9 +559,19 @@ ftk_status track2d_core(const float* field, ftk_field_kind kind, int64_t nx, int
   hipError_t he = hipSuccess;
   ph.mark(3);
   if (nh > 0) {
-    he = launch_emit2d(g, wide, masks, seg_cnt, seg_off, od, &dctl->status, dctl->cnt, s);
+    const bool sparse = sparse_emission(g, nh, V);
+    if (sparse) {
+      he = launch_fill_words(parent, 0xFFFFFFFFu, nh, s);
+      if (he == hipSuccess)
+        he = launch_emit2d_sparse(g, wide, masks, seg_cnt, seg_off, od, &dctl->status, dctl->cnt, s);
+    } else {
+      he = launch_emit2d(g, wide, masks, seg_cnt, seg_off, od, &dctl->status, dctl->cnt, s);
+    }
     ph.mark(4);
-    if (he == hipSuccess) he = launch_uf_hook(parent, work, &dctl->cnt[CNT_WORK], 2 * nh, s);
+    if (he == hipSuccess && sparse) he = launch_uf_compress(parent, nh, s);
+    if (he == hipSuccess)
+      he = sparse ? launch_uf_hook_slots(parent, work, nh, s)
+                  : launch_uf_hook(parent, work, &dctl->cnt[CNT_WORK], 2 * nh, s);
     if (he == hipSuccess) he = launch_uf_label(parent, od.face_id, (long long*)r.label, nh, dctl->cnt, s);
   } else {
     ph.mark(4);
@@ -873,7 +907,28 @@ ftk_status track2d_batched_impl(int nser, const float* const* fields, const int6
   unsigned* parent = sc.get<unsigned>((size_t)total);
   uint2* work = sc.get<uint2>((size_t)total * 2);
   unsigned* dgb = sc.get<unsigned>((size_t)nser + 1);
-  if (!parent || !work || !dgb) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  long long* dpb = sc.get<long long>((size_t)nser + 1);
+  if (!parent || !work || !dgb || !dpb) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  // emission form per series: tiled items (pre_e) for the dense ones, 64-segment blocks (pre_b) for the sparse ones
+  std::vector<long long> pre_b(nser + 1);
+  std::vector<char> sparse(nser);
+  pre_b[0] = 0;
+  for (int i = 0; i < nser; ++i) {
+    const Grid2& g = ser[i].g;
+    sparse[i] = sparse_emission(g, bases[i + 1] - bases[i], (long long)g.nx * g.ny * g.nt) ? 1 : 0;
+    const int items = pre_e[i + 1] - pre_e[i];
+    pre_e[i + 1] = pre_e[i] + (sparse[i] ? 0 : items);
+    pre_b[i + 1] = pre_b[i] + (sparse[i] ? ((long long)g.nt * g.ny * g.nxt + 63) / 64 : 0);
+  }
+  // link slots of the sparse series (one per global hit index; cleared when tiled series leave some unwritten) and
+  // their parents' initial value
+  uint2* slots = nullptr;
+  if (pre_b[nser] > 0) {
+    slots = sc.get<uint2>((size_t)total);
+    if (!slots) return fail(FTK_ERR_OOM, "scratch allocation failed");
+    if (pre_e[nser] > 0) HIP_TRY(hipMemsetAsync(slots, 0, sizeof(uint2) * (size_t)total, s));
+    HIP_TRY(hipMemsetAsync(parent, 0xFF, sizeof(unsigned) * (size_t)total, s));
+  }
   std::vector<unsigned> gb(nser + 1);
   const unsigned outs_mask = o.outputs;
   bool oom = false;
@@ -902,7 +957,7 @@ ftk_status track2d_batched_impl(int nser, const float* const* fields, const int6
     od.flags = r.flags;
     od.label = (long long*)r.label;
     od.parent = parent;
-    od.work = work;
+    od.work = sparse[i] ? slots : work;
     ser[i].wide = wide ? 1 : 0;
   }
   gb[nser] = (unsigned)total;
@@ -915,14 +970,21 @@ ftk_status track2d_batched_impl(int nser, const float* const* fields, const int6
   }
   HIP_TRY(hipMemcpyAsync(dser, ser.data(), sizeof(Series2) * nser, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(dgb, gb.data(), sizeof(unsigned) * (nser + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dpre + nser + 1, pre_e.data(), sizeof(int) * (nser + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dpb, pre_b.data(), sizeof(long long) * (nser + 1), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(dctr, 0, sizeof(int) * 4, s));
   ph.mark(3);
   hipError_t he = hipSuccess;
   if (total > 0) {
-    he = launch_emit2d_batched(dser, dpre + nser + 1, nser, pre_e[nser], wide, dctr, &dctl->status,
-                               &dctl->cnt[CNT_WORK], s);
+    if (pre_e[nser] > 0)
+      he = launch_emit2d_batched(dser, dpre + nser + 1, nser, pre_e[nser], wide, dctr, &dctl->status,
+                                 &dctl->cnt[CNT_WORK], s);
+    if (he == hipSuccess && pre_b[nser] > 0)
+      he = launch_emit2d_sparse_batched(dser, dpb, nser, pre_b[nser], wide, &dctl->status, s);
     ph.mark(4);
-    if (he == hipSuccess) he = launch_uf_hook(parent, work, &dctl->cnt[CNT_WORK], 2 * total, s);
+    if (he == hipSuccess && slots) he = launch_uf_compress(parent, total, s);
+    if (he == hipSuccess && pre_e[nser] > 0) he = launch_uf_hook(parent, work, &dctl->cnt[CNT_WORK], 2 * total, s);
+    if (he == hipSuccess && slots) he = launch_uf_hook_slots(parent, slots, total, s);
     if (he == hipSuccess) he = launch_uf_label_batched(parent, dser, dgb, nser, total, s);
   } else {
     ph.mark(4);

@@ -517,6 +517,129 @@ __device__ __forceinline__ unsigned long long block_sum256(unsigned long long v,
   return s;
 }
 
+// Record of one hit (Eq. 2, Sec. 4.1): exact cofactors of (v0 v1 v2 ; 1 1 1) from the quantised vectors qf of the
+// triangle's vertices, barycentric coordinates mu, position, and the Jacobian type (FP32 with a certified error
+// bound, else FP64); written at output index idx - o.gbase.  J holds the binary32 Jacobian stencil of each vertex.
+template <bool WIDE>
+__device__ __forceinline__ void hit_record2(const Grid2& g, const Out2& o, const float (&qf)[3][2],
+                                            const float (&J)[3][4], bool wide, bool vector, int ax, int y, int t,
+                                            int ty, int dx1, int dy1, int dt1, int dx2, int dy2, int dt2,
+                                            unsigned idx, unsigned long long& n_fp64, unsigned long long& n_deg) {
+  const long long plane = (long long)g.nx * g.ny;
+  // exact cofactors of (v0 v1 v2 ; 1 1 1): C_i = (-1)^i det(columns without i)
+  double Cd[3], Dd;
+  bool degenerate;
+  if (!WIDE) {
+    // |q| < 2^24: every cofactor is an integer below 2^49 and D below 2^51, exact in binary64
+    auto det2d = [](float a0, float a1, float b0, float b1) {
+      const double p = (double)a1 * (double)b0;
+      return __builtin_fma((double)a0, (double)b1, -p);
+    };
+    Cd[0] = det2d(qf[1][0], qf[1][1], qf[2][0], qf[2][1]);
+    Cd[1] = -det2d(qf[0][0], qf[0][1], qf[2][0], qf[2][1]);
+    Cd[2] = det2d(qf[0][0], qf[0][1], qf[1][0], qf[1][1]);
+    Dd = (Cd[0] + Cd[1]) + Cd[2];
+    degenerate = (Dd == 0.0);
+  } else {
+    long long q[3][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      q[i][0] = (long long)qf[i][0];
+      q[i][1] = (long long)qf[i][1];
+    }
+    i128 C[3];
+    C[0] = (i128)q[1][0] * q[2][1] - (i128)q[1][1] * q[2][0];
+    C[1] = -((i128)q[0][0] * q[2][1] - (i128)q[0][1] * q[2][0]);
+    C[2] = (i128)q[0][0] * q[1][1] - (i128)q[0][1] * q[1][0];
+    const i128 D = C[0] + C[1] + C[2];
+    degenerate = (D == 0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Cd[i] = (double)C[i];
+    Dd = (double)D;
+  }
+  unsigned fl = wide ? FL_WIDE : 0u;
+  if (degenerate) {
+    fl |= FL_DEGENERATE;
+    ++n_deg;
+  }
+  float mu32[3];
+  double mu64[3];
+  int type = -1;
+  if (g.precision == 0) {
+    if (degenerate) {
+      mu32[0] = mu32[1] = mu32[2] = 1.0f / 3.0f;
+    } else {
+      // hardware reciprocal (1 ulp): mu carries at most five roundings, inside the classifier's bound
+      const float rD = __builtin_amdgcn_rcpf((float)Dd);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) mu32[i] = (float)Cd[i] * rD;
+    }
+    type = classify2_fp32(mu32, J, vector);
+  }
+  if (g.precision != 0 || type < 0) {
+    if (degenerate) {
+      mu64[0] = mu64[1] = mu64[2] = 1.0 / 3.0;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) mu64[i] = Cd[i] / Dd;
+    }
+    type = classify2_fp64(mu64, J, vector);
+    if (g.precision == 0) {
+      fl |= FL_FP64;
+      ++n_fp64;
+    }
+  }
+  float pos[3], muo[3];
+  const float cx0 = (float)ax, cy0 = (float)y, ct0 = (float)t;
+  if (g.precision == 0) {
+    float sx = mu32[0] * cx0;
+    sx = sx + mu32[1] * (cx0 + dx1);
+    sx = sx + mu32[2] * (cx0 + dx2);
+    float sy = mu32[0] * cy0;
+    sy = sy + mu32[1] * (cy0 + dy1);
+    sy = sy + mu32[2] * (cy0 + dy2);
+    float stt = mu32[0] * ct0;
+    stt = stt + mu32[1] * (ct0 + dt1);
+    stt = stt + mu32[2] * (ct0 + dt2);
+    pos[0] = sx;
+    pos[1] = sy;
+    pos[2] = stt;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) muo[i] = mu32[i];
+  } else {
+    const double X = ax, Y = y, T = t;
+    double sx = mu64[0] * X;
+    sx = sx + mu64[1] * (X + dx1);
+    sx = sx + mu64[2] * (X + dx2);
+    double sy = mu64[0] * Y;
+    sy = sy + mu64[1] * (Y + dy1);
+    sy = sy + mu64[2] * (Y + dy2);
+    double stt = mu64[0] * T;
+    stt = stt + mu64[1] * (T + dt1);
+    stt = stt + mu64[2] * (T + dt2);
+    pos[0] = (float)sx;
+    pos[1] = (float)sy;
+    pos[2] = (float)stt;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) muo[i] = (float)mu64[i];
+  }
+  const long long agid = (long long)t * plane + (long long)y * g.nx + ax;
+  const size_t oi = idx - o.gbase;
+  o.face_id[oi] = agid * 12 + ty;
+  if (o.pos) {
+    o.pos[oi * 3 + 0] = pos[0];
+    o.pos[oi * 3 + 1] = pos[1];
+    o.pos[oi * 3 + 2] = pos[2];
+  }
+  if (o.mu) {
+    o.mu[oi * 3 + 0] = muo[0];
+    o.mu[oi * 3 + 1] = muo[1];
+    o.mu[oi * 3 + 2] = muo[2];
+  }
+  if (o.type) o.type[oi] = (uint8_t)type;
+  if (o.flags) o.flags[oi] = (uint8_t)fl;
+}
+
 template <int TY, bool WIDE>
 __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int by, int bz,
                                             const uint16_t* __restrict__ masks, const int* __restrict__ seg_cnt,
@@ -904,118 +1027,8 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           J[i][2] = diff3(xl.y, v.y, xh.y, gxv, nx);
           J[i][3] = diff3(yl.y, v.y, yh.y, gyv, ny);
         }
-        // exact cofactors of (v0 v1 v2 ; 1 1 1): C_i = (-1)^i det(columns without i)
-        double Cd[3], Dd;
-        bool degenerate;
-        if (!WIDE) {
-          // |q| < 2^24: every cofactor is an integer below 2^49 and D below 2^51, exact in binary64
-          auto det2d = [](float a0, float a1, float b0, float b1) {
-            const double p = (double)a1 * (double)b0;
-            return __builtin_fma((double)a0, (double)b1, -p);
-          };
-          Cd[0] = det2d(qf[1][0], qf[1][1], qf[2][0], qf[2][1]);
-          Cd[1] = -det2d(qf[0][0], qf[0][1], qf[2][0], qf[2][1]);
-          Cd[2] = det2d(qf[0][0], qf[0][1], qf[1][0], qf[1][1]);
-          Dd = (Cd[0] + Cd[1]) + Cd[2];
-          degenerate = (Dd == 0.0);
-        } else {
-          long long q[3][2];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            q[i][0] = (long long)qf[i][0];
-            q[i][1] = (long long)qf[i][1];
-          }
-          i128 C[3];
-          C[0] = (i128)q[1][0] * q[2][1] - (i128)q[1][1] * q[2][0];
-          C[1] = -((i128)q[0][0] * q[2][1] - (i128)q[0][1] * q[2][0]);
-          C[2] = (i128)q[0][0] * q[1][1] - (i128)q[0][1] * q[1][0];
-          const i128 D = C[0] + C[1] + C[2];
-          degenerate = (D == 0);
-#pragma unroll
-          for (int i = 0; i < 3; ++i) Cd[i] = (double)C[i];
-          Dd = (double)D;
-        }
-        unsigned fl = wide ? FL_WIDE : 0u;
-        if (degenerate) {
-          fl |= FL_DEGENERATE;
-          ++n_deg;
-        }
-        float mu32[3];
-        double mu64[3];
-        int type = -1;
-        if (g.precision == 0) {
-          if (degenerate) {
-            mu32[0] = mu32[1] = mu32[2] = 1.0f / 3.0f;
-          } else {
-            // hardware reciprocal (1 ulp): mu carries at most five roundings, inside the classifier's bound
-            const float rD = __builtin_amdgcn_rcpf((float)Dd);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) mu32[i] = (float)Cd[i] * rD;
-          }
-          type = classify2_fp32(mu32, J, vector);
-        }
-        if (g.precision != 0 || type < 0) {
-          if (degenerate) {
-            mu64[0] = mu64[1] = mu64[2] = 1.0 / 3.0;
-          } else {
-#pragma unroll
-            for (int i = 0; i < 3; ++i) mu64[i] = Cd[i] / Dd;
-          }
-          type = classify2_fp64(mu64, J, vector);
-          if (g.precision == 0) {
-            fl |= FL_FP64;
-            ++n_fp64;
-          }
-        }
-        float pos[3], muo[3];
-        const float cx0 = (float)ax, cy0 = (float)y, ct0 = (float)t;
-        if (g.precision == 0) {
-          float sx = mu32[0] * cx0;
-          sx = sx + mu32[1] * (cx0 + dx1);
-          sx = sx + mu32[2] * (cx0 + dx2);
-          float sy = mu32[0] * cy0;
-          sy = sy + mu32[1] * (cy0 + dy1);
-          sy = sy + mu32[2] * (cy0 + dy2);
-          float stt = mu32[0] * ct0;
-          stt = stt + mu32[1] * (ct0 + dt1);
-          stt = stt + mu32[2] * (ct0 + dt2);
-          pos[0] = sx;
-          pos[1] = sy;
-          pos[2] = stt;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) muo[i] = mu32[i];
-        } else {
-          const double X = ax, Y = y, T = t;
-          double sx = mu64[0] * X;
-          sx = sx + mu64[1] * (X + dx1);
-          sx = sx + mu64[2] * (X + dx2);
-          double sy = mu64[0] * Y;
-          sy = sy + mu64[1] * (Y + dy1);
-          sy = sy + mu64[2] * (Y + dy2);
-          double stt = mu64[0] * T;
-          stt = stt + mu64[1] * (T + dt1);
-          stt = stt + mu64[2] * (T + dt2);
-          pos[0] = (float)sx;
-          pos[1] = (float)sy;
-          pos[2] = (float)stt;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) muo[i] = (float)mu64[i];
-        }
-        const long long agid = (long long)t * plane + (long long)y * nx + ax;
-        const size_t oi = idx - o.gbase;
-        o.face_id[oi] = agid * 12 + ty;
-        if (o.pos) {
-          o.pos[oi * 3 + 0] = pos[0];
-          o.pos[oi * 3 + 1] = pos[1];
-          o.pos[oi * 3 + 2] = pos[2];
-        }
-        if (o.mu) {
-          o.mu[oi * 3 + 0] = muo[0];
-          o.mu[oi * 3 + 1] = muo[1];
-          o.mu[oi * 3 + 2] = muo[2];
-        }
-        if (o.type) o.type[oi] = (uint8_t)type;
-        if (o.flags) o.flags[oi] = (uint8_t)fl;
+        hit_record2<WIDE>(g, o, qf, J, wide, vector, ax, y, t, ty, dx1, dy1, dt1, dx2, dy2, dt2, idx, n_fp64,
+                          n_deg);
 
         // ---- pass 2 links: each of the (at most two) tetrahedra holding this triangle has exactly one other
         // punctured side.  Each link is recorded by its larger endpoint: inside this tile and chunk it goes to the
@@ -1114,6 +1127,293 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
 }
 
 // ---------------------------------------------------------------------------------------------------------------
+// Sparse emission: one wavefront per non-empty row segment, with no workgroup barriers.  When hits are rare (a few
+// per thousand vertices) the tile-marching emission above pays a fixed cost per tile and step (ring loads, scans
+// and barriers for a handful of hits).  Here a wavefront reads only what its segment's hits need: the hit masks of
+// the five rows that hold the other sides of their cells (steps t-1..t+1 along y = const, rows y-1..y+1 at step
+// t), the first-hit offsets of the three rows that can hold smaller partners (a partner with a smaller face id has
+// an anchor at t-1, y-1, x-1 or at the same anchor), and the field values of each hit vertex's stencils, gathered
+// through the caches.  No counter is shared: every link joins a hit to a smaller partner, so a hit with one or two
+// smaller partners takes the first as its union-find parent (the parents then point to smaller indices and form a
+// forest whose trees are connected parts of a trajectory; a tree's root is a hit with no smaller partner), and a
+// hit with two writes the second to its own slot of the link array ((i, i) when absent), united afterwards by
+// uf_hook_slots.  A trajectory is a path or a loop of hits (each lies in at most two cells), so the slot links
+// (one per local maximum of the index along it) join all its trees.  To keep the trees shallow, a hit takes its
+// partner's parent instead of the partner when that one is already written (parents start as 0xFFFFFFFF).  The
+// records are the same operations as in the tiled form (hit_record2), so both forms give identical outputs.
+// ---------------------------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int kSpW = TX + 2;  // anchors x0-1 .. x0+64
+
+// Per-wavefront LDS of the sparse emission.
+struct SparseWave {
+  unsigned short m[5][kSpW];       // hit masks: rows (t, y), (t, y-1), (t, y+1), (t-1, y), (t+1, y)
+  short x[3][kSpW];                // first hit of each anchor relative to its segment: rows (t,y), (t,y-1), (t-1,y)
+  unsigned b[3];                   // first hit index of the segments of those rows
+  unsigned short map[12 * TX];     // hit j of the segment -> anchor lane | type << 6
+};
+
+// mask row of each neighbour slot, and its offset row (-1: the row only holds larger partners)
+__device__ __forceinline__ int sp_row(int slot) {
+  return slot <= NB_PX ? 0 : (slot == NB_MY ? 1 : (slot == NB_PY ? 2 : (slot == NB_MT ? 3 : 4)));
+}
+
+// Binary32 vector of vertex (x, y) of field plane P (gradient of a scalar by the stencil of pass 1, or the vector
+// itself) and its Jacobian stencil J: the same operations as the staged form.  Coordinates outside the grid are
+// clamped; diff3 never uses those values (one-sided differences at the first and last index).
+__device__ __forceinline__ void vertex_stencil2(const Grid2& g, int x, int y, int t, float2& v, float (&J)[4]) {
+  const int nx = g.nx, ny = g.ny;
+  const long long plane = (long long)nx * ny;
+  auto cx = [&](int i) { return i < 0 ? 0 : (i >= nx ? nx - 1 : i); };
+  auto cy = [&](int i) { return i < 0 ? 0 : (i >= ny ? ny - 1 : i); };
+  float2 xl, xh, yl, yh;
+  if (g.kind == 0) {
+    const float* P = g.f + (long long)fpl(g, t) * plane;
+    auto F = [&](int dx, int dy) { return P[(long long)cy(y + dy) * nx + cx(x + dx)]; };
+    const float f00 = F(0, 0), fm0 = F(-1, 0), fp0 = F(1, 0), f0m = F(0, -1), f0p = F(0, 1);
+    const float fmm0 = F(-2, 0), fpp0 = F(2, 0), f0mm = F(0, -2), f0pp = F(0, 2);
+    const float fmm = F(-1, -1), fpm = F(1, -1), fmp = F(-1, 1), fpp = F(1, 1);
+    const int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+    v.x = diff3(fm0, f00, fp0, x, nx);
+    v.y = diff3(f0m, f00, f0p, y, ny);
+    xl = make_float2(diff3(fmm0, fm0, f00, xm, nx), diff3(fmm, fm0, fmp, y, ny));
+    xh = make_float2(diff3(f00, fp0, fpp0, xp, nx), diff3(fpm, fp0, fpp, y, ny));
+    yl = make_float2(diff3(fmm, f0m, fpm, x, nx), diff3(f0mm, f0m, f00, ym, ny));
+    yh = make_float2(diff3(fmp, f0p, fpp, x, nx), diff3(f00, f0p, f0pp, yp, ny));
+  } else {
+    const float* U = g.f + (long long)fpl(g, t) * 2 * plane;
+    const float* W = U + plane;
+    auto V = [&](int dx, int dy) {
+      const long long k = (long long)cy(y + dy) * nx + cx(x + dx);
+      return make_float2(U[k], W[k]);
+    };
+    v = V(0, 0);
+    xl = V(-1, 0);
+    xh = V(1, 0);
+    yl = V(0, -1);
+    yh = V(0, 1);
+  }
+  J[0] = diff3(xl.x, v.x, xh.x, x, nx);
+  J[1] = diff3(yl.x, v.x, yh.x, y, ny);
+  J[2] = diff3(xl.y, v.y, xh.y, x, nx);
+  J[3] = diff3(yl.y, v.y, yh.y, y, ny);
+}
+
+// One row segment (anchors x0 .. x0+63 of row y, step t) with `total` hits from global index `base`.
+template <bool WIDE>
+__device__ __forceinline__ void emit2d_segment(const Grid2& g, int t, int y, int bx, const uint16_t* __restrict__ masks,
+                                               const long long* __restrict__ seg_off, const Out2& o, SparseWave& W,
+                                               unsigned& st,
+                                               unsigned long long& n_fp64, unsigned long long& n_deg,
+                                               unsigned long long& n_linked) {
+  const int lane = lane_id();
+  const int nx = g.nx, ny = g.ny, nt = g.nt, nxt = g.nxt;
+  const int x0 = bx * TX;
+  const bool vector = g.kind != 0;
+  wave_lds_sync();  // the previous segment's reads of W are done
+  for (int e = lane; e < 5 * kSpW; e += 64) {
+    const int r = e / kSpW, c = e - r * kSpW;
+    const int tt = t + (r == 3 ? -1 : (r == 4 ? 1 : 0));
+    const int yy = y + (r == 1 ? -1 : (r == 2 ? 1 : 0));
+    const int xx = x0 - 1 + c;
+    unsigned m = 0;
+    if (tt >= 0 && tt < nt && yy >= 0 && yy < ny && xx >= 0 && xx < nx)
+      m = masks[((long long)mpl(g, tt) * ny + yy) * nx + xx];
+    W.m[r][c] = (unsigned short)m;
+  }
+  if (lane < 3) {
+    const int tt = lane == 2 ? t - 1 : t, yy = lane == 1 ? y - 1 : y;
+    W.b[lane] = (tt >= 0 && yy >= 0) ? (unsigned)seg_off[((long long)mpl(g, tt) * ny + yy) * nxt + bx] : 0u;
+  }
+  wave_lds_sync();
+  unsigned total = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int r = i == 2 ? 3 : i;
+    const unsigned c = __popc((unsigned)W.m[r][1 + lane]);
+    const unsigned incl = wave_incl_scan(c);
+    W.x[i][1 + lane] = (short)(incl - c);
+    if (lane == 63) W.x[i][kSpW - 1] = (short)incl;
+    if (lane == 0) W.x[i][0] = (short)(-(int)__popc((unsigned)W.m[r][0]));
+    if (i == 0) total = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
+  }
+  {
+    unsigned m = W.m[0][1 + lane];
+    unsigned k = (unsigned)(W.x[0][1 + lane]);
+    while (m) {
+      const unsigned ty = (unsigned)__ffs((int)m) - 1u;
+      m &= m - 1u;
+      W.map[k++] = (unsigned short)((unsigned)lane | (ty << 6));
+    }
+  }
+  wave_lds_sync();
+  const unsigned base = W.b[0];
+  for (unsigned j = lane; j < total; j += 64) {
+    const unsigned ent = W.map[j];
+    const int L = (int)(ent & 63u), ty = (int)(ent >> 6);
+    const unsigned idx = base + j;
+    const int ax = x0 + L;
+    const unsigned pk = kTri2Dev.pack[ty];
+    const int m1 = pk & 15, m2 = pk >> 4;
+    const int dx1 = m1 & 1, dy1 = (m1 >> 1) & 1, dt1 = (m1 >> 2) & 1;
+    const int dx2 = dx1 + (m2 & 1), dy2 = dy1 + ((m2 >> 1) & 1), dt2 = dt1 + ((m2 >> 2) & 1);
+    const int dxs[3] = {0, dx1, dx2}, dys[3] = {0, dy1, dy2}, dts[3] = {0, dt1, dt2};
+    float qf[3][2];
+    float J[3][4];
+    bool wide = false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float2 v;
+      vertex_stencil2(g, ax + dxs[i], y + dys[i], t + dts[i], v, J[i]);
+      qf[i][0] = quant(v.x, g.qscale);
+      qf[i][1] = quant(v.y, g.qscale);
+      if constexpr (WIDE)
+        if (!(fabsf(qf[i][0]) < 2147483648.0f) || !(fabsf(qf[i][1]) < 2147483648.0f)) wide = true;
+    }
+    hit_record2<WIDE>(g, o, qf, J, wide, vector, ax, y, t, ty, dx1, dy1, dt1, dx2, dy2, dt2, idx, n_fp64, n_deg);
+
+    // links (Alg. 1 pass 2): the other punctured side of each tetrahedron holding the triangle; the larger end of
+    // each link records it
+    unsigned sm0 = 0, sm1 = 0;
+    int ns = 0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const unsigned w = kTri2Dev.cof[ty][k];
+      const int rule = w & 3, axis = (w >> 2) & 3;
+      const int pa = axis == 0 ? ax : (axis == 1 ? y : t);
+      const int Na = axis == 0 ? nx : (axis == 1 ? ny : nt);
+      const bool exists = !((rule == 2 && pa < 1) || (rule == 3 && pa + 1 > Na - 1));
+      int found = 0;
+      unsigned other = 0;
+#pragma unroll
+      for (int sdx = 0; sdx < 3; ++sdx) {
+        const unsigned f = (w >> (4 + 7 * sdx)) & 127u;
+        const int slot = f & 7, tt = f >> 3;
+        const int row = sp_row(slot);
+        const int col = L + 1 + (slot == NB_MX ? -1 : (slot == NB_PX ? 1 : 0));
+        const unsigned um = W.m[row][col];
+        const unsigned hit = (um >> tt) & 1u;
+        const int xr = row == 0 ? 0 : (row == 1 ? 1 : (row == 3 ? 2 : -1));
+        const unsigned cand = xr < 0 ? 0xFFFFFFFFu
+                                     : W.b[xr] + (unsigned)(int)W.x[xr][col] + __popc(um & ((1u << tt) - 1u));
+        found += (int)hit;
+        other = hit ? cand : other;
+      }
+      bad = bad || (exists && found != 1);
+      const bool take = exists && found == 1 && other < idx;
+      sm1 = (take && ns == 1) ? other : sm1;
+      sm0 = (take && ns == 0) ? other : sm0;
+      ns += take ? 1 : 0;
+    }
+    if (bad || t == g.debug_step) st |= ST_INVARIANT;
+    n_linked += ns;
+    unsigned par = idx;
+    if (ns > 0) {  // an ancestor of the partner if already written (a stale read only gives a deeper tree)
+      const unsigned q = __hip_atomic_load(o.parent + sm0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      par = q == 0xFFFFFFFFu ? sm0 : q;
+    }
+    __hip_atomic_store(o.parent + idx, par, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    o.work[idx] = make_uint2(idx, ns > 1 ? sm1 : idx);
+  }
+}
+
+// Per-wavefront counters into the call's (or series') counters.
+__device__ __forceinline__ void sparse_flush_counts(unsigned long long* cnt, unsigned long long& n_fp64,
+                                                    unsigned long long& n_deg, unsigned long long& n_linked) {
+  const unsigned long long a = wave_sum64(n_fp64), b = wave_sum64(n_deg), c = wave_sum64(n_linked);
+  if (lane_id() == 0) {
+    if (a) atomicAdd(&cnt[CNT_FP64], a);
+    if (b) atomicAdd(&cnt[CNT_DEGEN], b);
+    if (c) atomicAdd(&cnt[CNT_LINKED], c);
+  }
+  n_fp64 = n_deg = n_linked = 0;
+}
+
+// Segments [64 blk, 64 blk + 64) of the steps [t_begin, t_end): each lane reads one segment's count, the wavefront
+// walks the non-empty ones.
+template <bool WIDE>
+__device__ __forceinline__ void emit2d_sparse_block(const Grid2& g, long long blk, const uint16_t* __restrict__ masks,
+                                                    const int* __restrict__ seg_cnt,
+                                                    const long long* __restrict__ seg_off, const Out2& o,
+                                                    SparseWave& W, unsigned& st, unsigned long long& n_fp64,
+                                                    unsigned long long& n_deg, unsigned long long& n_linked) {
+  const unsigned per_step = (unsigned)g.ny * (unsigned)g.nxt;  // segments per step
+  const long long nseg = (long long)(g.t_end - g.t_begin) * per_step;
+  const long long s0 = blk * 64;
+  // step and in-step segment of the block's first segment; the block's 64 segments span at most a few steps
+  const int tb = (int)(s0 / per_step);
+  const unsigned rb0 = (unsigned)(s0 - (long long)tb * per_step);
+  auto locate = [&](int b, int& t, unsigned& r) {
+    t = tb;
+    r = rb0 + (unsigned)b;
+    while (r >= per_step) {
+      r -= per_step;
+      ++t;
+    }
+    t += g.t_begin;
+  };
+  int c = 0;
+  if (s0 + lane_id() < nseg) {
+    int t;
+    unsigned r;
+    locate(lane_id(), t, r);
+    c = seg_cnt[(long long)mpl(g, t) * per_step + r];
+  }
+  unsigned long long bal = __ballot(c > 0);
+  while (bal) {
+    const int b = __ffsll((long long)bal) - 1;
+    bal &= bal - 1ull;
+    int t;
+    unsigned r;
+    locate(b, t, r);
+    const int y = (int)(r / (unsigned)g.nxt), bx = (int)(r - (unsigned)y * (unsigned)g.nxt);
+    emit2d_segment<WIDE>(g, t, y, bx, masks, seg_off, o, W, st, n_fp64, n_deg, n_linked);
+  }
+}
+
+// Wavefronts of the sparse emission: enough for four per SIMD.  A wavefront takes one 64-segment block per turn, so
+// the blocks in flight span about 4096 x 64 segments (a few steps at most): the partners at step t-1 of a hit are
+// then mostly written already, which keeps the parent trees shallow.
+constexpr int kSparseWaves = 4096;
+
+}  // namespace
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void emit2d_sparse(Grid2 g, const uint16_t* __restrict__ masks,
+                                                     const int* __restrict__ seg_cnt,
+                                                     const long long* __restrict__ seg_off, Out2 o,
+                                                     unsigned* __restrict__ status,
+                                                     unsigned long long* __restrict__ cnt) {
+  __shared__ SparseWave sw[4];
+  __shared__ unsigned long long red[3][4];
+  SparseWave& W = sw[threadIdx.x >> 6];
+  const long long nblk = ((long long)(g.t_end - g.t_begin) * g.ny * g.nxt + 63) / 64;
+  const long long nw = (long long)gridDim.x * 4;
+  unsigned st = 0;
+  unsigned long long n_fp64 = 0, n_deg = 0, n_linked = 0;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform: scalar loop state
+  for (long long blk = (long long)blockIdx.x * 4 + wv; blk < nblk; blk += nw)
+    emit2d_sparse_block<WIDE>(g, blk, masks, seg_cnt, seg_off, o, W, st, n_fp64, n_deg, n_linked);
+  // one counter update per workgroup (same-address atomics serialise)
+  const int w = threadIdx.x >> 6;
+  const unsigned long long a = wave_sum64(n_fp64), b = wave_sum64(n_deg), c = wave_sum64(n_linked);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+    red[2][w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    const unsigned long long v = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+    if (v) atomicAdd(&cnt[k == 0 ? CNT_FP64 : (k == 1 ? CNT_DEGEN : CNT_LINKED)], v);
+  }
+  if (st) atomicOr(status, st);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
 // Batched form: one persistent launch per stage for many independent series.  Workgroups pull (series, tile) items
 // from a device counter; the item -> series map is a binary search over the per-series item prefix.
 // ---------------------------------------------------------------------------------------------------------------
@@ -1172,6 +1472,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
     emit2d_tile<TY, WIDE>(g, TT, bx, by, bz, S[s].masks, S[s].seg_cnt, S[s].seg_off, o, status, S[s].cnt,
                           work_cnt);
   }
+}
+
+// Batched sparse emission: the 64-segment blocks of the series that take the sparse form, concatenated (bprefix:
+// per-series block prefix, zero blocks for the others); a wavefront's block -> series by binary search.
+template <bool WIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void emit2d_sparse_batched(const Series2* __restrict__ S,
+                                                             const long long* __restrict__ bprefix, int nser,
+                                                             unsigned* status) {
+  __shared__ SparseWave sw[4];
+  SparseWave& W = sw[threadIdx.x >> 6];
+  const long long nblk = bprefix[nser];
+  const long long nw = (long long)gridDim.x * 4;
+  unsigned st = 0;
+  unsigned long long n_fp64 = 0, n_deg = 0, n_linked = 0;
+  int cur = -1;  // series whose counts are being gathered (flushed when the wavefront moves to another)
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform: scalar loop state
+  for (long long B = (long long)blockIdx.x * 4 + wv; B < nblk; B += nw) {
+    int lo = 0, hi = nser;  // bprefix[lo] <= B < bprefix[lo + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (bprefix[mid] <= B)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    if (lo != cur) {
+      if (cur >= 0) sparse_flush_counts(S[cur].cnt, n_fp64, n_deg, n_linked);
+      cur = lo;
+    }
+    const Grid2 g = S[lo].g;
+    const Out2 o = S[lo].o;
+    emit2d_sparse_block<WIDE>(g, B - bprefix[lo], S[lo].masks, S[lo].seg_cnt, S[lo].seg_off, o, W, st, n_fp64, n_deg,
+                              n_linked);
+  }
+  if (cur >= 0) sparse_flush_counts(S[cur].cnt, n_fp64, n_deg, n_linked);
+  if (st) atomicOr(status, st);
 }
 
 // Emission of single steps (streaming): one step per launch, local union-find per step.
@@ -1244,6 +1580,32 @@ hipError_t launch_emit2d(const Grid2& g, bool wide, const uint16_t* masks, const
     emit2d<TYE, true><<<grid, 256, 0, s>>>(g, TTE, masks, seg_cnt, seg_off, o, status, cnt);
   else
     emit2d<TYE, false><<<grid, 256, 0, s>>>(g, TTE, masks, seg_cnt, seg_off, o, status, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit2d_sparse(const Grid2& g, bool wide, const uint16_t* masks, const int* seg_cnt,
+                                const long long* seg_off, const Out2& o, unsigned* status, unsigned long long* cnt,
+                                hipStream_t s) {
+  const long long nblk = ((long long)(g.t_end - g.t_begin) * g.ny * g.nxt + 63) / 64;
+  long long blocks = (nblk + 3) / 4;
+  if (blocks > kSparseWaves / 4) blocks = kSparseWaves / 4;
+  if (blocks < 1) blocks = 1;
+  if (wide)
+    emit2d_sparse<true><<<(unsigned)blocks, 256, 0, s>>>(g, masks, seg_cnt, seg_off, o, status, cnt);
+  else
+    emit2d_sparse<false><<<(unsigned)blocks, 256, 0, s>>>(g, masks, seg_cnt, seg_off, o, status, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit2d_sparse_batched(const Series2* S, const long long* bprefix, int nser, long long total_blocks,
+                                        bool wide, unsigned* status, hipStream_t s) {
+  long long blocks = (total_blocks + 3) / 4;
+  if (blocks > kSparseWaves / 4) blocks = kSparseWaves / 4;
+  if (blocks < 1) blocks = 1;
+  if (wide)
+    emit2d_sparse_batched<true><<<(unsigned)blocks, 256, 0, s>>>(S, bprefix, nser, status);
+  else
+    emit2d_sparse_batched<false><<<(unsigned)blocks, 256, 0, s>>>(S, bprefix, nser, status);
   return hipGetLastError();
 }
 

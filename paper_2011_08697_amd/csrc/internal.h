@@ -73,6 +73,15 @@ hipError_t launch_emit2d(const Grid2& g, bool wide, const uint16_t* masks, const
                          const long long* seg_off, const Out2& o, unsigned* status, unsigned long long* cnt,
                          hipStream_t s);
 
+// Sparse emission (one wavefront per non-empty row segment): same outputs as launch_emit2d, for fields with few hits
+// per vertex.  The parents must hold 0xFFFFFFFF on entry; each hit writes its parent (its first smaller partner or
+// an ancestor of it, or itself) and its link slot o.work[i] ((i, i) when absent), united by launch_uf_hook_slots.
+hipError_t launch_emit2d_sparse(const Grid2& g, bool wide, const uint16_t* masks, const int* seg_cnt,
+                                const long long* seg_off, const Out2& o, unsigned* status, unsigned long long* cnt,
+                                hipStream_t s);
+hipError_t launch_emit2d_sparse_batched(const Series2* S, const long long* bprefix, int nser, long long total_blocks,
+                                        bool wide, unsigned* status, hipStream_t s);
+
 hipError_t launch_emit2d_steps(const Grid2& g, bool wide, const uint16_t* masks, const int* seg_cnt,
                                const long long* seg_off, const Out2& o, unsigned* status, unsigned long long* cnt,
                                hipStream_t s);
@@ -186,6 +195,10 @@ hipError_t launch_simplify(int n, const float* pos, const long long* order, cons
 // Union-find passes over n hits: extra unions from the work list, then labels = face_id of the root.
 hipError_t launch_uf_hook(unsigned* parent, const uint2* work, const unsigned long long* work_count,
                           long long max_work, hipStream_t s);
+// Compression of a forest whose parents all point to smaller indices (the sparse emission's), in one pass.
+hipError_t launch_uf_compress(unsigned* parent, long long n, hipStream_t s);
+// Unions of a link array with one slot per entry: entries (a, a) are empty.
+hipError_t launch_uf_hook_slots(unsigned* parent, const uint2* slots, long long n_slots, hipStream_t s);
 hipError_t launch_uf_label(unsigned* parent, const long long* face_id, long long* label, long long n,
                            unsigned long long* cnt, hipStream_t s);
 

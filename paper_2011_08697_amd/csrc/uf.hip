@@ -21,6 +21,49 @@ __global__ __launch_bounds__(256) void uf_hook(unsigned* __restrict__ parent, co
   }
 }
 
+// Fixed-slot links (the sparse emission's): (a, a) marks an empty slot.
+__global__ __launch_bounds__(256) void uf_hook_slots(unsigned* __restrict__ parent, const uint2* __restrict__ slots,
+                                                     long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const uint2 e = slots[i];
+    if (e.x != e.y) uf_unite(parent, e.x, e.y);
+  }
+}
+
+// Compression of a forest whose parents point to smaller indices (parent[i] <= i), in one pass: workgroup b takes
+// hits [256 b, 256 b + 256).  A hit whose parent lies in an earlier range takes that parent's root (a short walk:
+// workgroups are dispatched in increasing order, so the earlier range is mostly compressed already; the walk is
+// capped, any ancestor being a valid parent), then pointer jumping inside the range in LDS points every hit at a
+// root or at such an earlier ancestor.  Agent-scope accesses make the earlier ranges' writes visible across XCDs.
+__global__ __launch_bounds__(256) void uf_compress(unsigned* __restrict__ parent, long long n) {
+  __shared__ unsigned lp[2][256];
+  const long long bs = (long long)blockIdx.x * 256;
+  const long long i = bs + threadIdx.x;
+  unsigned p = (unsigned)i;
+  if (i < n) {
+    p = uf_load(parent, (unsigned)i);
+    if ((long long)p < bs) {
+      for (int k = 0; k < 8; ++k) {
+        const unsigned q = uf_load(parent, p);
+        if (q == p) break;
+        p = q;
+      }
+    }
+  }
+  lp[0][threadIdx.x] = p;
+  __syncthreads();
+  int cur = 0;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {  // 2^8 = 256: every in-range chain is resolved
+    const unsigned v = lp[cur][threadIdx.x];
+    const unsigned w = ((long long)v >= bs && (long long)v < bs + 256) ? lp[cur][v - bs] : v;
+    lp[cur ^ 1][threadIdx.x] = w;
+    cur ^= 1;
+    __syncthreads();
+  }
+  if (i < n) __hip_atomic_store(parent + i, lp[cur][threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // grid-stride; one trajectory-count atomic per block
 __global__ __launch_bounds__(256) void uf_label(unsigned* __restrict__ parent, const long long* __restrict__ face_id,
                                                 long long* __restrict__ label, long long n,
@@ -81,6 +124,22 @@ hipError_t launch_uf_hook(unsigned* parent, const uint2* work, const unsigned lo
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
   uf_hook<<<(unsigned)blocks, 256, 0, s>>>(parent, work, work_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_uf_compress(unsigned* parent, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = (n + 255) / 256;
+  if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+  uf_compress<<<(unsigned)blocks, 256, 0, s>>>(parent, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_uf_hook_slots(unsigned* parent, const uint2* slots, long long n_slots, hipStream_t s) {
+  if (n_slots <= 0) return hipSuccess;
+  long long blocks = (n_slots + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  uf_hook_slots<<<(unsigned)blocks, 256, 0, s>>>(parent, slots, n_slots);
   return hipGetLastError();
 }
 

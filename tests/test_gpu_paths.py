@@ -140,3 +140,39 @@ def test_refusing_allocator_gives_oom_and_releases_everything(k):
     assert st == 5, F.last_error()
     assert r.n_hits == 0 and not r.face_id
     assert pool.live == {}
+
+
+TILED, SPARSE = 4, 8  # FTK_DEBUG_TILED_EMIT, FTK_DEBUG_SPARSE_EMIT
+
+
+@pytest.mark.parametrize("name", sorted(FIELDS))
+def test_emission_forms_are_identical(name):
+    """The sparse emission (a wavefront per non-empty row segment, every link through the global list) and the tiled
+    one give the same outputs bit for bit on dense, sparse, degenerate and vector fields, and both equal the
+    oracle."""
+    f, kind = FIELDS[name]()
+    tiled = F.track_cp2d(dev(f), kind=kind, debug=TILED)
+    sparse = F.track_cp2d(dev(f), kind=kind, debug=SPARSE)
+    same(sparse, tiled)
+    assert_full_parity(sparse, O.track(f, n=2, kind=kind))
+
+
+def test_sparse_emission_wide_path_batched_and_invariant():
+    u = wide_field(11)
+    r = F.track_cp2d(dev(u), kind=1, debug=SPARSE)
+    assert r["stats"]["wide_path"] == 1
+    assert_full_parity(r, O.track(u, n=2, kind=1))
+    # batched: every series in one form, or the per-series default (a dense and two sparse series)
+    xs = [FIELDS["noise"]()[0], FIELDS["blobs"]()[0], synth.moving_gaussians_2d(70, 333, 7, 5, seed=9)]
+    one = [F.track_cp2d(dev(x)) for x in xs]
+    for dbg in (TILED, SPARSE, 0):
+        for r, ref in zip(F.track_cp2d_batched([dev(x) for x in xs], debug=dbg), one):
+            same(r, ref)
+    f = synth.moving_gaussians_2d(130, 70, 9, 10, seed=2, noise_std=1e-3)
+    opt = SPARSE | INVARIANT | (4 << 8)
+    with pytest.raises(F.FtkError) as e:
+        F.track_cp2d(dev(f), debug=opt)
+    assert e.value.status == 7
+    with pytest.raises(F.FtkError) as e:
+        F.track_cp2d_batched([dev(f), dev(f[:6])], debug=opt)
+    assert e.value.status == 7
