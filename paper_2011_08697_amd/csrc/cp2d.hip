@@ -115,37 +115,61 @@ __device__ __forceinline__ void detect2d_tile(const Grid2& g, int TT, int bx, in
            ((a == (Q)0 && b == (Q)0) ? 16u : 0u);
   };
 
-  // Load plane t: scalar input into fs (FH x FW with halo); vector input straight into qs[par] (quantised).
+  // Load plane t: scalar input into fs (FH x FW with halo); vector input straight into qs[par] (quantised).  The
+  // loads use clamped (in-grid) addresses and are issued back to back; cells outside the grid are zeroed after.
   auto load_plane = [&](int t, int par) {
     if (g.kind == 0) {
+      constexpr int NL = (FH * FW + 255) / 256;
       const float* src = g.f + (long long)fpl(g, t) * plane;
-      for (int e = tid; e < FH * FW; e += 256) {
-        int ly = e / FW, lx = e - ly * FW;
-        int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        float v = 0.0f;
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-          v = src[(long long)gy * nx + gx];
-          if (!isfinite(v)) st |= ST_NONFINITE;
-        }
-        fs[e] = v;
+      float fv[NL];
+      bool in[NL];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        int e = tid + 256 * i;
+        asm volatile("" : "+v"(e));  // opaque: the index math is redone per plane, not held across steps
+        const int ly = e / FW, lx = e - ly * FW;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        in[i] = e < FH * FW && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        fv[i] = src[(long long)min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)];
+      }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const int e = tid + 256 * i;
+        const float v = in[i] ? fv[i] : 0.0f;
+        if (in[i] && !isfinite(v)) st |= ST_NONFINITE;
+        if (e < FH * FW) fs[e] = v;
       }
     } else {
+      constexpr int NL = (QH * QW + 255) / 256;
       const float* su = g.f + (long long)fpl(g, t) * 2 * plane;
       const float* sv = su + plane;
-      for (int e = tid; e < QH * QW; e += 256) {
-        int ly = e / QW, lx = e - ly * QW;
-        int gx = x0 + lx, gy = y0 + ly;
+      float f0[NL], f1[NL];
+      bool in[NL];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        int e = tid + 256 * i;
+        asm volatile("" : "+v"(e));
+        const int ly = e / QW, lx = e - ly * QW;
+        const int gx = x0 + lx, gy = y0 + ly;
+        in[i] = e < QH * QW && gx < nx && gy < ny;
+        const long long k = (long long)min(gy, ny - 1) * nx + min(gx, nx - 1);
+        f0[i] = su[k];
+        f1[i] = sv[k];
+      }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const int e = tid + 256 * i;
         Q q0 = 0, q1 = 0;
-        if (gx < nx && gy < ny) {
-          const long long k = (long long)gy * nx + gx;
-          const float v0 = su[k], v1 = sv[k];
-          if (!isfinite(v0) || !isfinite(v1)) st |= ST_NONFINITE;
-          q0 = to_q<WIDE>(quant(v0, g.qscale), st);
-          q1 = to_q<WIDE>(quant(v1, g.qscale), st);
+        if (in[i]) {
+          if (!isfinite(f0[i]) || !isfinite(f1[i])) st |= ST_NONFINITE;
+          q0 = to_q<WIDE>(quant(f0[i], g.qscale), st);
+          q1 = to_q<WIDE>(quant(f1[i], g.qscale), st);
           facts &= fact_bits(q0, q1);
         }
-        qs[par][0][e] = q0;
-        qs[par][1][e] = q1;
+        if (e < QH * QW) {
+          qs[par][0][e] = q0;
+          qs[par][1][e] = q1;
+        }
       }
     }
   };

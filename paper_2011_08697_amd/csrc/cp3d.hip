@@ -136,45 +136,51 @@ __device__ __forceinline__ unsigned sos3_positive(const Q* a, const Q* b, const 
   return sos3_tail(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2]);
 }
 
-// The same sequence for narrow entries (below 2^20): every term is an entry or a 2x2 minor below 2^41, exact in
-// 64 bits.  Inlined (no call, so the kernel needs no stack).
-__device__ __forceinline__ unsigned sos3_tail64(long long m00, long long m10, long long m20, long long m01,
-                                                long long m11, long long m21, long long m02, long long m12,
-                                                long long m22) {
-  long long v;
-  v = m11 * m22 - m12 * m21;          // C00
-  if (v != 0) return v > 0;
-  v = -(m01 * m22 - m02 * m21);       // C10
-  if (v != 0) return v > 0;
-  v = m01 * m12 - m02 * m11;          // C20
-  if (v != 0) return v > 0;
-  v = -(m10 * m22 - m12 * m20);       // C01
-  if (v != 0) return v > 0;
-  if (m22 != 0) return m22 < 0;       // -m22
-  if (m12 != 0) return m12 > 0;       // m12
-  v = m00 * m22 - m02 * m20;          // C11
-  if (v != 0) return v > 0;
-  if (m02 != 0) return m02 < 0;       // -m02 (m22 == 0 here)
-  v = -(m00 * m12 - m02 * m10);       // C21
-  if (v != 0) return v > 0;
-  v = m10 * m21 - m11 * m20;          // C02 (m12 == m02 == 0 here)
-  if (v != 0) return v > 0;
-  if (m21 != 0) return m21 > 0;       // m21
-  if (m11 != 0) return m11 < 0;       // -m11
-  if (m20 != 0) return m20 < 0;       // -m20
+// The same sequence in binary64 for narrow entries (integers below 2^20): every term is an entry or a 2x2 minor,
+// whose two products (below 2^40) and difference are exact in binary64.
+__device__ __forceinline__ unsigned sos3_tail_f64(double m00, double m10, double m20, double m01, double m11,
+                                                  double m21, double m02, double m12, double m22) {
+  auto mn = [](double x, double y, double z, double w) { return __builtin_fma(x, y, -(z * w)); };  // exact
+  double v;
+  v = mn(m11, m22, m12, m21);         // C00
+  if (v != 0.0) return v > 0.0;
+  v = -mn(m01, m22, m02, m21);        // C10
+  if (v != 0.0) return v > 0.0;
+  v = mn(m01, m12, m02, m11);         // C20
+  if (v != 0.0) return v > 0.0;
+  v = -mn(m10, m22, m12, m20);        // C01
+  if (v != 0.0) return v > 0.0;
+  if (m22 != 0.0) return m22 < 0.0;   // -m22
+  if (m12 != 0.0) return m12 > 0.0;   // m12
+  v = mn(m00, m22, m02, m20);         // C11
+  if (v != 0.0) return v > 0.0;
+  if (m02 != 0.0) return m02 < 0.0;   // -m02 (m22 == 0 here)
+  v = -mn(m00, m12, m02, m10);        // C21
+  if (v != 0.0) return v > 0.0;
+  v = mn(m10, m21, m11, m20);         // C02 (m12 == m02 == 0 here)
+  if (v != 0.0) return v > 0.0;
+  if (m21 != 0.0) return m21 > 0.0;   // m21
+  if (m11 != 0.0) return m11 < 0.0;   // -m11
+  if (m20 != 0.0) return m20 < 0.0;   // -m20
   return 0u;                          // -1
 }
 
-// Exact 64-bit evaluation (narrow entries below 2^20: minors below 2^41, terms below 2^61), then SoS.
+// Exact evaluation for narrow entries (below 2^20: minors below 2^41, terms below 2^61), then SoS.  A zero column
+// makes the determinant vanish without evaluating it (frequent where gradients underflow the quantum); the
+// sequence that follows runs in binary64, exactly.
 __device__ __forceinline__ unsigned sos3_exact_narrow(float a0, float a1, float a2, float b0, float b1, float b2,
                                                       float c0, float c1, float c2) {
-  const long long A0 = (long long)a0, A1 = (long long)a1, A2 = (long long)a2;
-  const long long B0 = (long long)b0, B1 = (long long)b1, B2 = (long long)b2;
-  const long long C0 = (long long)c0, C1 = (long long)c1, C2 = (long long)c2;
-  const long long m0 = B1 * C2 - B2 * C1, m1 = B0 * C2 - B2 * C0, m2 = B0 * C1 - B1 * C0;
-  const long long d = A0 * m0 - A1 * m1 + A2 * m2;
-  if (d != 0) return d > 0;
-  return sos3_tail64(A0, A1, A2, B0, B1, B2, C0, C1, C2);
+  const bool zero_col = (a0 == 0.0f && a1 == 0.0f && a2 == 0.0f) || (b0 == 0.0f && b1 == 0.0f && b2 == 0.0f) ||
+                        (c0 == 0.0f && c1 == 0.0f && c2 == 0.0f);
+  if (!zero_col) {
+    const long long A0 = (long long)a0, A1 = (long long)a1, A2 = (long long)a2;
+    const long long B0 = (long long)b0, B1 = (long long)b1, B2 = (long long)b2;
+    const long long C0 = (long long)c0, C1 = (long long)c1, C2 = (long long)c2;
+    const long long m0 = B1 * C2 - B2 * C1, m1 = B0 * C2 - B2 * C0, m2 = B0 * C1 - B1 * C0;
+    const long long d = A0 * m0 - A1 * m1 + A2 * m2;
+    if (d != 0) return d > 0;
+  }
+  return sos3_tail_f64(a0, a1, a2, b0, b1, b2, c0, c1, c2);
 }
 
 // Narrow sign of det(a, b, c): the 2x2 minors are exact in binary64 (integers below 2^41); the three products and
@@ -250,33 +256,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
   unsigned st = 0;
   unsigned facts = 0x7Fu;  // sign facts of the gradients quantised by this thread since the last plane_facts()
 
-  auto quantise_plane = [&](int tq, int par) {
+  // Quantised gradients of plane tq into slot par.  fetch(): the thread's share of the plane's field block with a
+  // one-cell halo, from clamped (in-grid) addresses into registers, all loads in flight together; halo cells
+  // outside the grid hold copies of edge values, which diff3 never reads (one-sided differences at the first and
+  // last index).  quantise(par): the block into the LDS of slot par (its previous plane is dead by then), the
+  // stencils from LDS, then the quantised vectors into the slot.  Every thread reaches quantise() (it contains
+  // barriers).
+  constexpr int SX = QX + 2, SY = QY + 2, SZ = QZ + 2, SN = SX * SY * SZ;
+  constexpr int NS = (SN + 255) / 256, NE = (QN + 255) / 256;
+  static_assert(SN * sizeof(float) <= sizeof(qs[0]), "staged field block exceeds the plane slot");
+  float fv[NS];
+  auto fetch = [&](int tq) {
     const float* src = g.f + fpl3(g, tq) * plane;
-    const long long sxy = (long long)nx * ny;
-    for (int e = tid; e < QN; e += 256) {
-      int lx = e % QX, r = e / QX, ly = r % QY, lz = r / QY;
-      int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-      Q q0 = 0, q1 = 0, q2 = 0;
-      if (gx < nx && gy < ny && gz < nz) {
-        const float* c = src + ((long long)gz * ny + gy) * nx + gx;
-        const float c0 = c[0];
-        if (!isfinite(c0)) st |= ST_NONFINITE;
-        const float xl = gx > 0 ? c[-1] : 0.0f, xh = gx < nx - 1 ? c[1] : 0.0f;
-        const float yl = gy > 0 ? c[-nx] : 0.0f, yh = gy < ny - 1 ? c[nx] : 0.0f;
-        const float zl = gz > 0 ? c[-sxy] : 0.0f, zh = gz < nz - 1 ? c[sxy] : 0.0f;
-        float v0 = diff3(xl, c0, xh, gx, nx);
-        float v1 = diff3(yl, c0, yh, gy, ny);
-        float v2 = diff3(zl, c0, zh, gz, nz);
-        q0 = to_q3<WIDE>(quant(v0, g.qscale), st);
-        q1 = to_q3<WIDE>(quant(v1, g.qscale), st);
-        q2 = to_q3<WIDE>(quant(v2, g.qscale), st);
-        facts &= (q0 > (Q)0 ? 1u : 0u) | (q0 < (Q)0 ? 2u : 0u) | (q1 > (Q)0 ? 4u : 0u) | (q1 < (Q)0 ? 8u : 0u) |
-                 (q2 > (Q)0 ? 16u : 0u) | (q2 < (Q)0 ? 32u : 0u) |
-                 ((q0 == (Q)0 && q1 == (Q)0 && q2 == (Q)0) ? 64u : 0u);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      int e = tid + 256 * i;
+      asm volatile("" : "+v"(e));  // opaque: the index math is redone per plane, not held in registers across steps
+      const int lx = e % SX, r = e / SX, ly = r % SY, lz = r / SY;
+      const int cx = min(max(x0 - 1 + lx, 0), nx - 1), cy = min(max(y0 - 1 + ly, 0), ny - 1);
+      const int cz = min(max(z0 - 1 + lz, 0), nz - 1);
+      fv[i] = src[((long long)cz * ny + cy) * nx + cx];
+    }
+  };
+  auto quantise = [&](int par) {
+    float* fb = reinterpret_cast<float*>(&qs[par][0][0]);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int e = tid + 256 * i;
+      if (e < SN) fb[e] = fv[i];
+    }
+    __syncthreads();
+    Q q[NE][3];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      int e = tid + 256 * i;
+      asm volatile("" : "+v"(e));
+      q[i][0] = q[i][1] = q[i][2] = 0;
+      if (e < QN) {
+        const int lx = e % QX, r = e / QX, ly = r % QY, lz = r / QY;
+        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        if (gx < nx && gy < ny && gz < nz) {
+          const float* c = fb + ((lz + 1) * SY + (ly + 1)) * SX + (lx + 1);
+          const float c0 = c[0];
+          if (!isfinite(c0)) st |= ST_NONFINITE;  // every vertex is the centre of some tile's element
+          const float v0 = diff3(c[-1], c0, c[1], gx, nx);
+          const float v1 = diff3(c[-SX], c0, c[SX], gy, ny);
+          const float v2 = diff3(c[-SX * SY], c0, c[SX * SY], gz, nz);
+          q[i][0] = to_q3<WIDE>(quant(v0, g.qscale), st);
+          q[i][1] = to_q3<WIDE>(quant(v1, g.qscale), st);
+          q[i][2] = to_q3<WIDE>(quant(v2, g.qscale), st);
+          facts &= (q[i][0] > (Q)0 ? 1u : 0u) | (q[i][0] < (Q)0 ? 2u : 0u) | (q[i][1] > (Q)0 ? 4u : 0u) |
+                   (q[i][1] < (Q)0 ? 8u : 0u) | (q[i][2] > (Q)0 ? 16u : 0u) | (q[i][2] < (Q)0 ? 32u : 0u) |
+                   ((q[i][0] == (Q)0 && q[i][1] == (Q)0 && q[i][2] == (Q)0) ? 64u : 0u);
+        }
       }
-      qs[par][0][e] = q0;
-      qs[par][1][e] = q1;
-      qs[par][2][e] = q2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + 256 * i;
+      if (e < QN) {
+        qs[par][0][e] = q[i][0];
+        qs[par][1][e] = q[i][1];
+        qs[par][2][e] = q[i][2];
+      }
     }
   };
   // Triangle sign words.  Triangle type ti = (M1, M2) anchored at p has vertices at the unit 4-cube corners
@@ -315,7 +358,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
   auto tris_narrow = [&](int ap, auto list) {
     constexpr int N = decltype(list)::n;
     const int op = ap ^ 1;
-    for (int e = tid; e < WN; e += 256) {
+    for (int e0 = tid; e0 < WN; e0 += 256) {
+      int e = e0;
+      asm volatile("" : "+v"(e));  // opaque: positions are recomputed per pass, not held across steps
       const int wx = e % WX, r = e / WX, wy = r % WY, wz = r / WY;
       const int base = (wz * QY + wy) * QX + wx;
       auto ld = [&](int cm, int comp) -> double {
@@ -389,7 +434,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
     s_ord_ok[0] = s_ord_ok[1] = 0;
   }
   __syncthreads();
-  quantise_plane(t0, t0 & 1);
+  fetch(t0);
+  quantise(t0 & 1);
   plane_facts(t0 & 1);
 
   for (int t = t0; t < t1; ++t) {
@@ -397,7 +443,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
     const bool has_next = t + 1 < nt;
     __syncthreads();  // previous tetrahedron pass done; facts and flags of plane t visible
     if (has_next) {  // s_fact[nxp] was reset at the end of the previous step (or in the prologue)
-      quantise_plane(t + 1, nxp);
+      fetch(t + 1);
+      quantise(nxp);
       plane_facts(nxp);
       __syncthreads();  // quantised plane and its facts visible
     }
@@ -416,7 +463,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
     }
 
     // 60 tetrahedron tests for the TX x TY x TZ anchors, 2 per thread; lanes of a wave: 16 x 4 rows
-    for (int a = tid; a < TX3 * TY3 * TZ3; a += 256) {
+    for (int a0 = tid; a0 < TX3 * TY3 * TZ3; a0 += 256) {
+      int a = a0;
+      asm volatile("" : "+v"(a));
       const int lx = a % TX3, r = a / TX3, ly = r % TY3, lz = r / TY3;
       const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
       unsigned long long m = 0;
