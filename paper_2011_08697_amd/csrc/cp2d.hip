@@ -715,14 +715,27 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   unsigned long long n_fp64 = 0, n_deg = 0, n_linked = 0;
 
 
-  // vector field of plane t into gs[par]
+  // vector field of plane t into gs[par] (field loads from clamped in-grid addresses, all in flight together;
+  // cells outside the grid are zeroed after)
   auto load_plane = [&](int t, int par) {
     if (!vector) {
+      constexpr int NL = (FH * FW + 255) / 256;
       const float* src = g.f + (long long)fpl(g, t) * plane;
-      for (int e = tid; e < FH * FW; e += 256) {
-        int ly = e / FW, lx = e - ly * FW;
-        int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-        fs[e] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? src[(long long)gy * nx + gx] : 0.0f;
+      float fv[NL];
+      bool in[NL];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        int e = tid + 256 * i;
+        asm volatile("" : "+v"(e));  // opaque: the index math is redone per plane, not held across steps
+        const int ly = e / FW, lx = e - ly * FW;
+        const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+        in[i] = e < FH * FW && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        fv[i] = src[(long long)min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1)];
+      }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const int e = tid + 256 * i;
+        if (e < FH * FW) fs[e] = in[i] ? fv[i] : 0.0f;
       }
       __syncthreads();
       for (int e = tid; e < GH * GW; e += 256) {
@@ -737,32 +750,51 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
         gs[par][e] = v;
       }
     } else {
+      constexpr int NL = (GH * GW + 255) / 256;
       const float* su = g.f + (long long)fpl(g, t) * 2 * plane;
       const float* sv = su + plane;
-      for (int e = tid; e < GH * GW; e += 256) {
-        int ly = e / GW, lx = e - ly * GW;
-        int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-          long long k = (long long)gy * nx + gx;
-          v = make_float2(su[k], sv[k]);
-        }
-        gs[par][e] = v;
+      float f0[NL], f1[NL];
+      bool in[NL];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        int e = tid + 256 * i;
+        asm volatile("" : "+v"(e));
+        const int ly = e / GW, lx = e - ly * GW;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        in[i] = e < GH * GW && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        const long long k = (long long)min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1);
+        f0[i] = su[k];
+        f1[i] = sv[k];
+      }
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const int e = tid + 256 * i;
+        if (e < GH * GW) gs[par][e] = in[i] ? make_float2(f0[i], f1[i]) : make_float2(0.0f, 0.0f);
       }
     }
   };
 
   // mask slice of step s (zero outside [0, nt)) into ring slot (s + 3) % 3
   auto load_slice = [&](int s) {
+    constexpr int NL = (RH * RW + 255) / 256;
     const int slot = (s + 3) % 3;
     const bool ok = s >= 0 && s < nt;
     const long long mp = ok ? (long long)mpl(g, s) : 0;
-    for (int e = tid; e < RH * RW; e += 256) {
+    unsigned short mv[NL];
+    bool in[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {  // clamped addresses, loads in flight together
+      int e = tid + 256 * i;
+      asm volatile("" : "+v"(e));
       const int r = e / RW, c = e - r * RW;
       const int y = y0 - 1 + r, x = x0 - 1 + c;
-      unsigned m = 0;
-      if (ok && y >= 0 && y < ny && x >= 0 && x < nx) m = masks[(mp * ny + y) * nx + x];
-      rm[slot][e] = (unsigned short)m;
+      in[i] = ok && e < RH * RW && y >= 0 && y < ny && x >= 0 && x < nx;
+      mv[i] = masks[(mp * ny + min(max(y, 0), ny - 1)) * nx + min(max(x, 0), nx - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int e = tid + 256 * i;
+      if (e < RH * RW) rm[slot][e] = in[i] ? mv[i] : (unsigned short)0;
     }
     if (tid < RH) {
       const int y = y0 - 1 + tid;
