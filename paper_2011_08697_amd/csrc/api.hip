@@ -437,7 +437,6 @@ __global__ void zero_words(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-// Clears the control block with a kernel (no memset node, so the sequence is safe under stream capture too).
 // n words set to v (a kernel rather than hipMemsetAsync: the 2D one-shot call may run under graph capture)
 __global__ void fill_words(unsigned* p, unsigned v, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -452,6 +451,7 @@ hipError_t launch_fill_words(unsigned* p, unsigned v, long long n, hipStream_t s
   return hipGetLastError();
 }
 
+// Clears the control block with a kernel (no memset node, so the sequence is safe under stream capture too).
 hipError_t clear_ctl(Ctl* d, hipStream_t s) {
   constexpr int n = (int)(sizeof(Ctl) / sizeof(unsigned));
   zero_words<<<1, 64, 0, s>>>((unsigned*)d, n);
@@ -762,7 +762,8 @@ ftk_status track3d_impl(const float* field, int64_t nx, int64_t ny, int64_t nz, 
   hipError_t he = hipSuccess;
   ph.mark(3);
   if (nh > 0) {
-    he = launch_emit3d(g, wide, masks, seg_off, nh, od, &dctl->status, dctl->cnt, list, &dctl->cnt[CNT_LIST], s);
+    he = launch_emit3d(g, wide, masks, seg_cnt, seg_off, nh, od, &dctl->status, dctl->cnt, list, &dctl->cnt[CNT_LIST],
+                       s);
     ph.mark(4);
     if (he == hipSuccess) he = launch_uf_hook(parent, work, &dctl->cnt[CNT_WORK], nh, s);
     if (he == hipSuccess) he = launch_uf_label(parent, od.face_id, (long long*)r.label, nh, dctl->cnt, s);
@@ -1276,8 +1277,8 @@ static ftk_status tracker_emit3(ftk_tracker* h, int e, int nt) {
   zero_words<<<1, 64, 0, h->s>>>((unsigned*)&dctl->cnt[CNT_LIST], 2);
   HIP_TRY(hipGetLastError());
   if (step_hits > 0)
-    HIP_TRY(launch_emit3d(g, h->plane_wide[e % 3] != 0, h->mring3, h->oring, step_hits, od, &dctl->status, dctl->cnt,
-                          h->list3, &dctl->cnt[CNT_LIST], h->s));
+    HIP_TRY(launch_emit3d(g, h->plane_wide[e % 3] != 0, h->mring3, h->cring, h->oring, step_hits, od, &dctl->status,
+                          dctl->cnt, h->list3, &dctl->cnt[CNT_LIST], h->s));
   h->emitted = h->total_after[e];
   return FTK_OK;
 }

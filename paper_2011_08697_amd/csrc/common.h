@@ -31,6 +31,16 @@ constexpr int kWave = 64;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Workgroups go to the 8 XCDs round-robin by linear id.  This maps a linear id to a logical tile index so that each
+// XCD takes a contiguous range of tiles: neighbouring tiles then share that XCD's L2 and fetch their common halo
+// once.  A bijection on [0, nb) (ids past the last multiple of 8 map to themselves).  Used by the 3D detection,
+// whose field halos triple its reads otherwise; the 2D kernels keep the interleaved order, under which they ran
+// faster (their concurrent tiles then spread over more memory channels).
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
+  const unsigned per = nb / 8u;
+  return b < per * 8u ? (b % 8u) * per + b / 8u : b;
+}
+
 // Inclusive prefix sum over the 64 lanes with DPP moves (all lanes active): shifts by 1, 2, 4, 8 inside each row
 // of 16 lanes (lanes without a source add 0), then lane 15 of each row added to the next row and lane 31 to
 // rows 2 and 3.

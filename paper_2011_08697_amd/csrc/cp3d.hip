@@ -248,10 +248,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
   if (tid < 50) s_tcor[tid] = (unsigned char)(kTri3.m[tid][0] | ((kTri3.m[tid][0] | kTri3.m[tid][1]) << 4));
   __syncthreads();
   const int nx = g.nx, ny = g.ny, nz = g.nz, nt = g.nt;
-  const int x0 = blockIdx.x * TX3;
-  const int by = blockIdx.y % nyt, bz = blockIdx.y / nyt;
+  // logical tile of this workgroup (XCD-contiguous ranges of tiles, x fastest, then y, z, slab)
+  const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned L = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+  const int bxl = (int)(L % gridDim.x), byz = (int)((L / gridDim.x) % gridDim.y), bsl = (int)(L / (gridDim.x * gridDim.y));
+  const int x0 = bxl * TX3;
+  const int by = byz % nyt, bz = byz / nyt;
   const int y0 = by * TY3, z0 = bz * TZ3;
-  const int t0 = g.t_begin + blockIdx.z * TT, t1 = min(t0 + TT, g.t_end);
+  const int t0 = g.t_begin + bsl * TT, t1 = min(t0 + TT, g.t_end);
   const long long plane = (long long)nx * ny * nz;
   unsigned st = 0;
   unsigned facts = 0x7Fu;  // sign facts of the gradients quantised by this thread since the last plane_facts()
@@ -504,7 +508,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
 #pragma unroll
       for (int d = 8; d >= 1; d >>= 1) c += __shfl_xor(c, d, 16);
       if (lx == 0 && gy < ny && gz < nz)
-        seg_cnt[((mpl3(g, t) * nz + gz) * ny + gy) * g.nxt + blockIdx.x] = (int)c;
+        seg_cnt[((mpl3(g, t) * nz + gz) * ny + gy) * g.nxt + bxl] = (int)c;
     }
   }
   if (st) atomicOr(status, st);
@@ -520,32 +524,58 @@ struct Field3 {
   int nx, ny, nz;
   long long plane;
   int ring;  // steps stored as a ring of `ring` slots (0: step t at t)
-  __device__ __forceinline__ float s(int x, int y, int z, int t) const {
-    return f[(long long)(ring ? t % ring : t) * plane + ((long long)z * ny + y) * nx + x];
-  }
-  __device__ __forceinline__ float grad(int c, int x, int y, int z, int t) const {
-    const int N = c == 0 ? nx : (c == 1 ? ny : nz);
-    const int i = c == 0 ? x : (c == 1 ? y : z);
-    const int dx = c == 0, dy = c == 1, dz = c == 2;
-    float lo = i > 0 ? s(x - dx, y - dy, z - dz, t) : 0.0f;
-    float hi = i < N - 1 ? s(x + dx, y + dy, z + dz, t) : 0.0f;
-    return diff3(lo, s(x, y, z, t), hi, i, N);
-  }
-  // J[a][b] = d grad_a / d x_b, the same stencil on the binary32 gradient, row-major 3x3
-  __device__ __forceinline__ void jac(int x, int y, int z, int t, float J[9]) const {
+  // Binary32 gradient (c) and Jacobian stencil J (row-major 3x3, J[a][b] = d grad_a / d x_b) of vertex (x, y, z, t),
+  // the same operations as the detection's stencils.  The 25 field values of the stencil are read from clamped
+  // (in-grid) addresses, all independent loads; the clamped ones are never used (diff3 takes one-sided differences
+  // at the first and last index).
+  __device__ __forceinline__ void stencil(int x, int y, int z, int t, float c[3], float J[9]) const {
+    const float* P = f + (long long)(ring ? t % ring : t) * plane;
+    auto at = [&](int dx, int dy, int dz) {
+      const int xx = min(max(x + dx, 0), nx - 1), yy = min(max(y + dy, 0), ny - 1), zz = min(max(z + dz, 0), nz - 1);
+      return P[((long long)zz * ny + yy) * nx + xx];
+    };
+    const int N[3] = {nx, ny, nz}, I[3] = {x, y, z};
+    float v[3][3][3];  // v[dz+1][dy+1][dx+1] on the unit neighbourhood (corners unused)
+    float far[3][2];   // f(x -+ 2 e_a)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float c = grad(a, x, y, z, t);
+    for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int N = b == 0 ? nx : (b == 1 ? ny : nz);
-        const int i = b == 0 ? x : (b == 1 ? y : z);
-        const int dx = b == 0, dy = b == 1, dz = b == 2;
-        float lo = i > 0 ? grad(a, x - dx, y - dy, z - dz, t) : 0.0f;
-        float hi = i < N - 1 ? grad(a, x + dx, y + dy, z + dz, t) : 0.0f;
-        J[a * 3 + b] = diff3(lo, c, hi, i, N);
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+          v[dz + 1][dy + 1][dx + 1] = (dx != 0 && dy != 0 && dz != 0) ? 0.0f : at(dx, dy, dz);
+    far[0][0] = at(-2, 0, 0);
+    far[0][1] = at(2, 0, 0);
+    far[1][0] = at(0, -2, 0);
+    far[1][1] = at(0, 2, 0);
+    far[2][0] = at(0, 0, -2);
+    far[2][1] = at(0, 0, 2);
+    // value at offset d (|d|_inf <= 1, at most two nonzero) and at -+2 e_a
+    auto val = [&](int dx, int dy, int dz) { return v[dz + 1][dy + 1][dx + 1]; };
+    // gradient component a at the vertex offset by o = s e_b (s in {-1, 0, 1})
+    auto grad_at = [&](int a, int b, int sgn) -> float {
+      int o[3] = {0, 0, 0};
+      o[b] = sgn;
+      int lo[3] = {o[0], o[1], o[2]}, hi[3] = {o[0], o[1], o[2]};
+      lo[a] -= 1;
+      hi[a] += 1;
+      float fl, fh;
+      if (a == b && sgn != 0) {  // neighbours at o -+ e_a: the centre and the far value
+        fl = sgn < 0 ? far[a][0] : val(0, 0, 0);
+        fh = sgn < 0 ? val(0, 0, 0) : far[a][1];
+      } else {
+        fl = val(lo[0], lo[1], lo[2]);
+        fh = val(hi[0], hi[1], hi[2]);
       }
-    }
+      return diff3(fl, val(o[0], o[1], o[2]), fh, I[a] + o[a], N[a]);
+    };
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[a] = grad_at(a, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        J[a * 3 + b] = diff3(grad_at(a, b, -1), c[a], grad_at(a, b, 1), I[b], N[b]);
   }
 };
 
@@ -596,22 +626,37 @@ __device__ __noinline__ int classify3_fp64(double mu0, double mu1, double mu2, d
 
 }  // namespace
 
-// Wavefronts whose 64 vertices hold hits: a light pass over all masks that lists them (one append per such wave),
-// so the heavy emission kernel (large register footprint, low occupancy) runs only where there is work.
-__global__ __launch_bounds__(256) void emit3d_rows(Grid3 g, const uint64_t* __restrict__ masks, long long nvtx_rows,
+// Row chunks of 64 vertices that hold hits (wavefronts of the emission kernel): a light pass over the per-segment
+// hit counts (one lane per chunk, its four 16-vertex segments) lists them with one append per wavefront, so the
+// heavy emission kernel (large register footprint, low occupancy) runs only where there is work.
+__global__ __launch_bounds__(256) void emit3d_rows(Grid3 g, const int* __restrict__ seg_cnt, long long nvtx_rows,
                                                    long long* __restrict__ list,
                                                    unsigned long long* __restrict__ list_n) {
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ny = g.ny, nz = g.nz, nxt = g.nxt;
+  const int xblocks = (g.nx + 63) / 64;
+  const long long chunk = (long long)blockIdx.x * 256 + threadIdx.x;
+  bool has = false;
+  if (chunk < nvtx_rows * xblocks) {
+    const long long r = chunk / xblocks;
+    const int xb = (int)(chunk - r * xblocks);
+    const int y = (int)(r % ny), z = (int)((r / ny) % nz), t = g.t_begin + (int)(r / ((long long)ny * nz));
+    const long long sb = ((mpl3(g, t) * nz + z) * ny + y) * nxt;
+#pragma unroll
+    for (int k = 0; k < 64 / SEG3; ++k) {
+      const int sx = xb * (64 / SEG3) + k;
+      if (sx < nxt && seg_cnt[sb + sx] > 0) has = true;
+    }
+  }
+  const unsigned long long bal = __ballot(has);
+  if (bal == 0) return;
   const int lane = threadIdx.x & 63;
-  const int xblocks = (nx + 63) / 64;
-  if (row >= nvtx_rows * xblocks) return;
-  const long long r = row / xblocks;
-  const int x = (int)(row - r * xblocks) * 64 + lane;
-  const int y = (int)(r % ny), z = (int)((r / ny) % nz), t = g.t_begin + (int)(r / ((long long)ny * nz));
-  const long long plane = (long long)nx * ny * nz;
-  const unsigned long long m = x < nx ? masks[mpl3(g, t) * plane + ((long long)z * ny + y) * nx + x] : 0ull;
-  if (__ballot(m != 0) != 0 && lane == 0) list[atomicAdd(list_n, 1ull)] = row;
+  const int leader = __ffsll((long long)bal) - 1;
+  unsigned long long pos = 0;
+  if (lane == leader) pos = atomicAdd(list_n, (unsigned long long)__popcll(bal));
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)pos, leader);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(pos >> 32), leader);
+  pos = ((unsigned long long)hi << 32) | lo;
+  if (has) list[pos + (unsigned long long)__popcll(bal & ((1ull << lane) - 1ull))] = chunk;
 }
 
 template <bool WIDE>
@@ -647,7 +692,13 @@ __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restric
     const long long seg = ((mpl3(g, ut) * nz + uz) * ny + uy) * nxt + ux / SEG3;
     unsigned off = (unsigned)seg_off[seg];
     const long long ub = mpl3(g, ut) * plane + ((long long)uz * ny + uy) * nx;
-    for (int xx = (ux / SEG3) * SEG3; xx < ux; ++xx) off += (unsigned)__popcll(masks[ub + xx]);
+    const int x0s = (ux / SEG3) * SEG3;
+#pragma unroll
+    for (int k = 0; k < SEG3 - 1; ++k) {  // independent loads (clamped index), counted below ux only
+      const int xx = x0s + k;
+      const unsigned long long mk = masks[ub + min(xx, nx - 1)];
+      off += xx < ux ? (unsigned)__popcll(mk) : 0u;
+    }
     return off;
   };
   auto mask_at = [&](int ux, int uy, int uz, int ut) -> unsigned long long {
@@ -675,15 +726,19 @@ __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restric
         vt[i] = t + ((cm[i] >> 3) & 1);
       }
       long long q[4][3];
+      float J[4][9];
       bool wide = false;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        float gr[3];
+        F.stencil(vx[i], vy[i], vz[i], vt[i], gr, J[i]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float rq = quant(F.grad(c, vx[i], vy[i], vz[i], vt[i]), g.qscale);
+          const float rq = quant(gr[c], g.qscale);
           if (!(fabsf(rq) < 1048576.0f)) wide = true;
           q[i][c] = (long long)rq;
         }
+      }
       // exact cofactors C_i = (-1)^(3+i) det(columns without i)
       i128 C[4];
       C[0] = -det3x<WIDE, long long>(q[1], q[2], q[3]);
@@ -703,9 +758,6 @@ __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restric
 #pragma unroll
         for (int i = 0; i < 4; ++i) mu64[i] = (double)C[i] / dD;
       }
-      float J[4][9];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) F.jac(vx[i], vy[i], vz[i], vt[i], J[i]);
       const int type = classify3_fp64(mu64[0], mu64[1], mu64[2], mu64[3], J[0], J[1], J[2], J[3]);
       float pos[4], muo[4];
       if (g.precision == 0) {
@@ -855,12 +907,12 @@ hipError_t launch_detect3d(const Grid3& g, int tt, bool wide, uint64_t* masks, i
   return hipGetLastError();
 }
 
-hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const long long* seg_off, long long n_hits,
-                         const Out3& o, unsigned* status, unsigned long long* cnt, long long* list,
-                         unsigned long long* list_n, hipStream_t s) {
+hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const int* seg_cnt,
+                         const long long* seg_off, long long n_hits, const Out3& o, unsigned* status,
+                         unsigned long long* cnt, long long* list, unsigned long long* list_n, hipStream_t s) {
   const long long rows = (long long)(g.t_end - g.t_begin) * g.nz * g.ny;
   const long long waves = rows * ((g.nx + 63) / 64);
-  emit3d_rows<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(g, masks, rows, list, list_n);
+  emit3d_rows<<<(unsigned)((waves + 255) / 256), 256, 0, s>>>(g, seg_cnt, rows, list, list_n);
   // at most one listed wavefront per hit
   const long long lw = n_hits < waves ? n_hits : waves;
   const unsigned blocks = (unsigned)((lw + 3) / 4 > 0 ? (lw + 3) / 4 : 1);

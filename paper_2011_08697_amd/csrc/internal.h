@@ -95,9 +95,9 @@ hipError_t launch_uf_label_batched(unsigned* parent, const Series2* S, const uns
 
 hipError_t launch_detect3d(const Grid3& g, int tt, bool wide, uint64_t* masks, int* seg_cnt, unsigned* status,
                            hipStream_t s);
-hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const long long* seg_off, long long n_hits,
-                         const Out3& o, unsigned* status, unsigned long long* cnt, long long* list,
-                         unsigned long long* list_n, hipStream_t s);
+hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const int* seg_cnt,
+                         const long long* seg_off, long long n_hits, const Out3& o, unsigned* status,
+                         unsigned long long* cnt, long long* list, unsigned long long* list_n, hipStream_t s);
 
 // Exclusive scan of n int32 counts into int64 offsets; total written to *total (device).  tmp must hold
 // scan_tmp_elems(n) int64 values.
