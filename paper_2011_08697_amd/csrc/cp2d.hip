@@ -1267,21 +1267,34 @@ __device__ __forceinline__ void emit2d_segment(const Grid2& g, int t, int y, int
   const int nx = g.nx, ny = g.ny, nt = g.nt, nxt = g.nxt;
   const int x0 = bx * TX;
   const bool vector = g.kind != 0;
-  wave_lds_sync();  // the previous segment's reads of W are done
-  for (int e = lane; e < 5 * kSpW; e += 64) {
+  // the five mask rows (clamped addresses: all loads in flight together; cells outside the grid zeroed after)
+  constexpr int NR = (5 * kSpW + 63) / 64;
+  unsigned short mv[NR];
+  bool in[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int e = lane + 64 * i;
     const int r = e / kSpW, c = e - r * kSpW;
     const int tt = t + (r == 3 ? -1 : (r == 4 ? 1 : 0));
     const int yy = y + (r == 1 ? -1 : (r == 2 ? 1 : 0));
     const int xx = x0 - 1 + c;
-    unsigned m = 0;
-    if (tt >= 0 && tt < nt && yy >= 0 && yy < ny && xx >= 0 && xx < nx)
-      m = masks[((long long)mpl(g, tt) * ny + yy) * nx + xx];
-    W.m[r][c] = (unsigned short)m;
+    in[i] = e < 5 * kSpW && tt >= 0 && tt < nt && yy >= 0 && yy < ny && xx >= 0 && xx < nx;
+    const int tc = min(max(tt, 0), nt - 1), yc = min(max(yy, 0), ny - 1), xc = min(max(xx, 0), nx - 1);
+    mv[i] = masks[((long long)mpl(g, tc) * ny + yc) * nx + xc];
   }
+  unsigned bv = 0;
   if (lane < 3) {
     const int tt = lane == 2 ? t - 1 : t, yy = lane == 1 ? y - 1 : y;
-    W.b[lane] = (tt >= 0 && yy >= 0) ? (unsigned)seg_off[((long long)mpl(g, tt) * ny + yy) * nxt + bx] : 0u;
+    bv = (unsigned)seg_off[((long long)mpl(g, max(tt, 0)) * ny + max(yy, 0)) * nxt + bx];
+    if (tt < 0 || yy < 0) bv = 0u;
   }
+  wave_lds_sync();  // the previous segment's reads of W are done
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int e = lane + 64 * i;
+    if (e < 5 * kSpW) (&W.m[0][0])[e] = in[i] ? mv[i] : (unsigned short)0;
+  }
+  if (lane < 3) W.b[lane] = bv;
   wave_lds_sync();
   unsigned total = 0;
 #pragma unroll
