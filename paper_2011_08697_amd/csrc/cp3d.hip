@@ -248,7 +248,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
   if (tid < 50) s_tcor[tid] = (unsigned char)(kTri3.m[tid][0] | ((kTri3.m[tid][0] | kTri3.m[tid][1]) << 4));
   __syncthreads();
   const int nx = g.nx, ny = g.ny, nz = g.nz, nt = g.nt;
-  // logical tile of this workgroup (XCD-contiguous ranges of tiles, x fastest, then y, z, slab)
+  // logical tile of this workgroup (XCD-contiguous ranges of tiles, x fastest, then y, z, slab; an x, z, y order
+  // read 14% less but ran 9% slower)
   const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
   const unsigned L = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
   const int bxl = (int)(L % gridDim.x), byz = (int)((L / gridDim.x) % gridDim.y), bsl = (int)(L / (gridDim.x * gridDim.y));
