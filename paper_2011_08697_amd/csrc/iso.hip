@@ -135,13 +135,19 @@ __device__ __forceinline__ void corner_bits(const IsoGrid& g, int x, int y, int 
                                             unsigned& valid) {
   above = 0;
   valid = 0;
+  unsigned long long w[16];
+#pragma unroll
+  for (int cm = 0; cm < 16; ++cm) {  // clamped (in-grid) word addresses: the 16 loads are independent
+    const int cx = min(x + (cm & 1), g.nx - 1), cy = min(y + ((cm >> 1) & 1), g.ny - 1);
+    const int cz = min(z + ((cm >> 2) & 1), g.nz - 1), ct = min(t + ((cm >> 3) & 1), g.nt - 1);
+    w[cm] = g.bits[(((long long)ct * g.nz + cz) * g.ny + cy) * g.nwx + (cx >> 6)];
+  }
 #pragma unroll
   for (int cm = 0; cm < 16; ++cm) {
     const int cx = x + (cm & 1), cy = y + ((cm >> 1) & 1), cz = z + ((cm >> 2) & 1), ct = t + ((cm >> 3) & 1);
     if (cx < g.nx && cy < g.ny && cz < g.nz && ct < g.nt) {
-      const unsigned long long w = g.bits[(((long long)ct * g.nz + cz) * g.ny + cy) * g.nwx + (cx >> 6)];
       valid |= 1u << cm;
-      above |= (unsigned)((w >> (cx & 63)) & 1ull) << cm;
+      above |= (unsigned)((w[cm] >> (cx & 63)) & 1ull) << cm;
     }
   }
 }
