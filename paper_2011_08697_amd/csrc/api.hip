@@ -696,7 +696,9 @@ ftk_status track3d_impl(const float* field, int64_t nx, int64_t ny, int64_t nz, 
   long long* seg_off = sc.get<long long>((size_t)nseg);
   long long* scan_tmp = sc.get<long long>(scan_tmp_elems(nseg));
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!masks || !seg_cnt || !seg_off || !scan_tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  g.cert = sc.get<unsigned char>((size_t)(nt * cert3_plane(g)));
+  if (!masks || !seg_cnt || !seg_off || !scan_tmp || !dctl || !g.cert)
+    return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   int tt = o.slab_depth ? o.slab_depth : 8;
   if (tt > g.nt) tt = g.nt;
@@ -1053,6 +1055,7 @@ struct ftk_tracker {
   uint16_t* mring = nullptr;
   uint64_t* mring3 = nullptr;
   long long* list3 = nullptr;  // 3D emission: 64-vertex row chunks with hits of the emitted step
+  unsigned char* cert3 = nullptr;  // 3D: certified detection tile-steps (ring of 3 planes)
   int* cring = nullptr;
   long long* oring = nullptr;
   long long* scan_tmp = nullptr;
@@ -1080,13 +1083,14 @@ static Alloc tracker_alloc(ftk_tracker* h) { return make_alloc(h->o, h->s); }
 static void tracker_free_all(ftk_tracker* h) {
   const Alloc al = tracker_alloc(h);
   (void)hipStreamSynchronize(h->s);
-  void* ps[] = {h->fring, h->mring, h->mring3, h->list3, h->cring, h->oring, h->scan_tmp, h->dctl, h->dplane,
-                h->face_id, h->pos, h->mu, h->type, h->flags, h->parent, h->work};
+  void* ps[] = {h->fring, h->mring, h->mring3, h->list3, h->cert3, h->cring, h->oring, h->scan_tmp, h->dctl,
+                h->dplane, h->face_id, h->pos, h->mu, h->type, h->flags, h->parent, h->work};
   for (void* p : ps) al.put(p);
   h->fring = nullptr;
   h->mring = nullptr;
   h->mring3 = nullptr;
   h->list3 = nullptr;
+  h->cert3 = nullptr;
   h->cring = nullptr;
   h->oring = nullptr;
   h->scan_tmp = nullptr;
@@ -1227,6 +1231,7 @@ static Grid3 tracker_grid3(ftk_tracker* h, int t_begin, int nt) {
   g.t_end = t_begin + 1;
   g.f_ring = 3;
   g.m_ring = 3;
+  g.cert = h->cert3;
   return g;
 }
 
@@ -1318,13 +1323,19 @@ extern "C" ftk_status ftk_cp_create(int32_t n, const int64_t* dims, ftk_field_ki
     } else {
       h->mring3 = (uint64_t*)al.get(sizeof(uint64_t) * 3 * plane);
       h->list3 = (long long*)al.get(sizeof(long long) * h->nz * h->ny * ((h->nx + 63) / 64));
+      ftk::Grid3 gd;
+      gd.nx = (int)h->nx;
+      gd.ny = (int)h->ny;
+      gd.nz = (int)h->nz;
+      h->cert3 = (unsigned char*)al.get((size_t)(3 * ftk::cert3_plane(gd)));
     }
     h->cring = (int*)al.get(sizeof(int) * 3 * h->nseg_plane);
     h->oring = (long long*)al.get(sizeof(long long) * 3 * h->nseg_plane);
     h->scan_tmp = (long long*)al.get(sizeof(long long) * ftk::scan_tmp_elems(h->nseg_plane));
     h->dctl = al.get(sizeof(Ctl));
     h->dplane = (long long*)al.get(sizeof(long long));
-    const bool ring_ok = n == 2 ? h->mring != nullptr : (h->mring3 != nullptr && h->list3 != nullptr);
+    const bool ring_ok =
+        n == 2 ? h->mring != nullptr : (h->mring3 != nullptr && h->list3 != nullptr && h->cert3 != nullptr);
     if (!h->fring || !ring_ok || !h->cring || !h->oring || !h->scan_tmp || !h->dctl || !h->dplane) {
       ftk::tracker_free_all(h);
       delete h;

@@ -465,6 +465,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
     if (tid == 0) {
       if (has_next) s_ord_ok[nxp] = certified ? 0 : 1;
       s_fact[par] = 0x7Fu;  // plane t's facts are not read again; the slot receives plane t + 2's
+      g.cert[((mpl3(g, t) * ((nz + TZ3 - 1) / TZ3) + bz) * nyt + by) * gridDim.x + bxl] = certified ? 1 : 0;
     }
 
     // 60 tetrahedron tests for the TX x TY x TZ anchors, 2 per thread; lanes of a wave: 16 x 4 rows
@@ -503,7 +504,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 2 : 
         if (t == nt - 1) valid &= ~kTetUseT;
         m &= valid;
       }
-      if (in) masks[((mpl3(g, t) * nz + gz) * ny + gy) * nx + gx] = m;
+      if (in && !certified) masks[((mpl3(g, t) * nz + gz) * ny + gy) * nx + gx] = m;  // certified: read as zero
       // count per 16-lane row segment
       unsigned c = (unsigned)__popcll(m);
 #pragma unroll
@@ -682,7 +683,12 @@ __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restric
   const long long plane = (long long)nx * ny * nz;
   const long long vofs = ((long long)z * ny + y) * nx + x;
   const long long gidx = (long long)t * plane + vofs;  // global vertex index (face ids)
-  const unsigned long long m = in ? masks[mpl3(g, t) * plane + vofs] : 0ull;
+  // the puncture mask of vertex u: zero where its detection tile-step was certified (those masks are not written)
+  const long long ntx = (nx + TX3 - 1) / TX3, nty = (ny + TY3 - 1) / TY3, ntz = (nz + TZ3 - 1) / TZ3;
+  auto certified_at = [&](int ux, int uy, int uz, int ut) -> bool {
+    return g.cert[((mpl3(g, ut) * ntz + uz / TZ3) * nty + uy / TY3) * ntx + ux / TX3] != 0;
+  };
+  const unsigned long long m = (in && !certified_at(x, y, z, t)) ? masks[mpl3(g, t) * plane + vofs] : 0ull;
   if (__ballot(m != 0) == 0) return;
   unsigned st = 0;
   unsigned long long n_deg = 0, n_linked = 0;
@@ -703,6 +709,7 @@ __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restric
     return off;
   };
   auto mask_at = [&](int ux, int uy, int uz, int ut) -> unsigned long long {
+    if (certified_at(ux, uy, uz, ut)) return 0ull;
     return masks[mpl3(g, ut) * plane + ((long long)uz * ny + uy) * nx + ux];
   };
 
@@ -898,6 +905,7 @@ __global__ __launch_bounds__(256) void emit3d(Grid3 g, const uint64_t* __restric
 
 hipError_t launch_detect3d(const Grid3& g, int tt, bool wide, uint64_t* masks, int* seg_cnt, unsigned* status,
                            hipStream_t s) {
+  if (!g.cert) return hipErrorInvalidValue;  // the kernel records its certified tile-steps there
   const int nyt = (g.ny + TY3 - 1) / TY3, nzt = (g.nz + TZ3 - 1) / TZ3;
   dim3 grid((unsigned)((g.nx + TX3 - 1) / TX3), (unsigned)(nyt * nzt),
             (unsigned)((g.t_end - g.t_begin + tt - 1) / tt));
@@ -911,6 +919,7 @@ hipError_t launch_detect3d(const Grid3& g, int tt, bool wide, uint64_t* masks, i
 hipError_t launch_emit3d(const Grid3& g, bool wide, const uint64_t* masks, const int* seg_cnt,
                          const long long* seg_off, long long n_hits, const Out3& o, unsigned* status,
                          unsigned long long* cnt, long long* list, unsigned long long* list_n, hipStream_t s) {
+  if (!g.cert) return hipErrorInvalidValue;  // the certified-tile flags are read with the masks
   const long long rows = (long long)(g.t_end - g.t_begin) * g.nz * g.ny;
   const long long waves = rows * ((g.nx + 63) / 64);
   emit3d_rows<<<(unsigned)((waves + 255) / 256), 256, 0, s>>>(g, seg_cnt, rows, list, list_n);

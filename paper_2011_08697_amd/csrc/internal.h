@@ -55,7 +55,14 @@ struct Grid3 {
   int t_begin = 0, t_end = 0;  // anchors processed by a launch: steps [t_begin, t_end)
   int f_ring = 0;  // field steps stored as a ring of f_ring steps (step t at slot t % f_ring); 0: step t at t
   int m_ring = 0;  // same for the puncture masks and the per-segment counts/offsets
+  // One byte per detection tile-step (16 x 8 x 4 anchors at one step; stored like the masks, ring slots included):
+  // 1 when the sign certificate proved the tile-step empty, whose masks are then not written (read them as zero).
+  unsigned char* cert = nullptr;
 };
+// Number of detection tiles per step (cert entries per plane).
+inline long long cert3_plane(const Grid3& g) {
+  return (long long)((g.nx + 15) / 16) * ((g.ny + 7) / 8) * ((g.nz + 3) / 4);
+}
 
 struct Out3 {
   long long* face_id;
