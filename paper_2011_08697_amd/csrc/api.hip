@@ -1916,23 +1916,25 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   const Alloc al = make_alloc(o, s);
   Scratch sc(al);
   const long long V = nx * ny * nz * nt;
+  const long long G = (V + 15) / 16;  // groups of 16 vertices (offsets: one base per group)
   unsigned short* emask = sc.get<unsigned short>((size_t)V);
-  unsigned char* hcnt = sc.get<unsigned char>((size_t)V);
-  unsigned char* tcnt = sc.get<unsigned char>((size_t)V);
-  long long* hoff = sc.get<long long>((size_t)V);
-  long long* toff = sc.get<long long>((size_t)V);
-  long long* aoff = sc.get<long long>((size_t)V);
+  unsigned char* hcnt = sc.get<unsigned char>((size_t)G * 16);
+  unsigned char* tcnt = sc.get<unsigned char>((size_t)G * 16);
+  int* gsum = sc.get<int>((size_t)G);
+  long long* hbase = sc.get<long long>((size_t)G);
+  long long* tbase = sc.get<long long>((size_t)G);
+  long long* abase = sc.get<long long>((size_t)G);
   unsigned long long* bits = sc.get<unsigned long long>((size_t)((nx + 63) / 64) * ny * nz * nt);
-  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(V));
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(G));
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!emask || !hcnt || !tcnt || !hoff || !toff || !aoff || !bits || !tmp || !dctl)
+  if (!emask || !hcnt || !tcnt || !gsum || !hbase || !tbase || !abase || !bits || !tmp || !dctl)
     return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   HIP_TRY(ftk::launch_iso_count(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, bits, emask, hcnt, tcnt,
                                 &dctl->status, s));
-  HIP_TRY(ftk::launch_scan_u8(hcnt, hoff, V, &dctl->total, tmp, s));
-  HIP_TRY(ftk::launch_scan_u8(tcnt, toff, V, (long long*)&dctl->cnt[ftk::CNT_LIST], tmp, s));
-  HIP_TRY(ftk::launch_iso_active(tcnt, V, hcnt, aoff, (long long*)&dctl->cnt[ftk::CNT_WORK], tmp, nullptr, false, s));
+  HIP_TRY(ftk::launch_iso_bases(hcnt, V, false, gsum, hbase, &dctl->total, tmp, s));
+  HIP_TRY(ftk::launch_iso_bases(tcnt, V, false, gsum, tbase, (long long*)&dctl->cnt[ftk::CNT_LIST], tmp, s));
+  HIP_TRY(ftk::launch_iso_bases(tcnt, V, true, gsum, abase, (long long*)&dctl->cnt[ftk::CNT_WORK], tmp, s));
   Ctl h;
   ftk_status st = read_ctl(&h, dctl, s);
   if (st) return st;
@@ -1956,13 +1958,12 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   }
   hipError_t he = hipSuccess;
   if (nh > 0) {
-    he = ftk::launch_iso_emit(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, emask, hoff, (long long*)r.edge_id,
-                              r.pos, parent, s);
+    he = ftk::launch_iso_emit(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, emask, hbase, hcnt,
+                              (long long*)r.edge_id, r.pos, parent, s);
+    if (he == hipSuccess) he = ftk::launch_iso_active(tcnt, abase, V, active, s);
     if (he == hipSuccess)
-      he = ftk::launch_iso_active(tcnt, V, hcnt, aoff, nullptr, nullptr, active, true, s);
-    if (he == hipSuccess)
-      he = ftk::launch_iso_unite(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, bits, active, nact, emask, hoff,
-                                 tcnt, toff, parent, (int*)r.tets, &dctl->status, s);
+      he = ftk::launch_iso_unite(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, bits, active, nact, emask, hbase,
+                                 hcnt, tcnt, tbase, parent, (int*)r.tets, &dctl->status, s);
     if (he == hipSuccess)
       he = ftk::launch_uf_label(parent, (const long long*)r.edge_id, (long long*)r.label, nh, dctl->cnt, s);
   }

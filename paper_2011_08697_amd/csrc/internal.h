@@ -163,16 +163,21 @@ hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, floa
                             unsigned short* emask, unsigned char* hcnt, unsigned char* tcnt, unsigned* status,
                             hipStream_t s);
 hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float c, const unsigned short* emask,
-                           const long long* hoff, long long* edge_id, float* pos, unsigned* parent, hipStream_t s);
-// active vertices (a crossed pentachoron in their cube): flags + scan (scatter = false, *total = count), then the
-// ascending list (scatter = true)
-hipError_t launch_iso_active(const unsigned char* tcnt, long long V, unsigned char* flag, long long* off, long long* total,
-                             long long* scan_tmp, long long* list, bool scatter, hipStream_t s);
+                           const long long* hbase, const unsigned char* hcnt, long long* edge_id, float* pos,
+                           unsigned* parent, hipStream_t s);
+// offsets of the byte counts cnt[V] (allocated to a multiple of 16 bytes): base[g] = sum of the counts (nonzero:
+// of the nonzero counts) of the vertices before group g of 16 (gsum, base: ceil(V / 16) entries; *total = sum of all)
+hipError_t launch_iso_bases(const unsigned char* cnt, long long V, bool nonzero, int* gsum, long long* base,
+                            long long* total, long long* scan_tmp, hipStream_t s);
+// ascending list of the vertices with tetrahedra (tcnt > 0), at their offsets from abase (nonzero counts)
+hipError_t launch_iso_active(const unsigned char* tcnt, const long long* abase, long long V, long long* list,
+                             hipStream_t s);
 hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c,
                             const unsigned long long* bits, const long long* active, long long n_active,
-                            const unsigned short* emask, const long long* hoff, const unsigned char* tcnt,
-                            const long long* toff, unsigned* parent, int* tets, unsigned* status,
-                            hipStream_t s);
+                            const unsigned short* emask, const long long* hbase, const unsigned char* hcnt,
+                            const unsigned char* tcnt, const long long* tbase, unsigned* parent, int* tets,
+                            unsigned* status, hipStream_t s);
+
 // Quantum vortex surfaces (vortex.hip): edge signs and positive-triangle masks (tmask, 50 bits) with per-vertex
 // counts; then emission of triangle ids, points and identity parents, and the pentachoron unions.  Grids as iso.
 hipError_t launch_vx_detect(const float* psi, int nx, int ny, int nz, int nt, float qscale, unsigned short* emask,

@@ -112,6 +112,38 @@ __device__ __forceinline__ long long vidx(const IsoGrid& g, int x, int y, int z,
   return (((long long)t * g.nz + z) * g.ny + y) * g.nx + x;
 }
 
+// Offsets of per-vertex byte counts (crossings, tetrahedra, active flags) without full-grid int64 scans: one base
+// per group of 16 vertices (exclusive scan of the group sums, V/16 entries) and, at lookup, the counts of the
+// vertex's earlier group members summed from one 16-byte load.  Count arrays are allocated to a multiple of 16.
+// sum_first: the first k (0..16) bytes of a group; nonzero = count the nonzero bytes instead.
+__device__ __forceinline__ unsigned sum_first(const uint4 q, int k, bool nonzero) {
+  const unsigned w[4] = {q.x, q.y, q.z, q.w};
+  unsigned s = 0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int nb = k - 4 * d;  // bytes of word d that are counted
+    unsigned x = nb >= 4 ? w[d] : (nb <= 0 ? 0u : (w[d] & ((1u << (8 * nb)) - 1u)));
+    if (nonzero) x = ((((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) & 0x80808080u) >> 7;  // 1 per nonzero byte
+    s = __builtin_amdgcn_sad_u8(x, 0u, s);  // + sum of the four bytes
+  }
+  return s;
+}
+
+__device__ __forceinline__ long long off16(const long long* __restrict__ base, const unsigned char* __restrict__ cnt,
+                                           long long v, bool nonzero) {
+  const long long g0 = v & ~15ll;
+  return base[v >> 4] + sum_first(*reinterpret_cast<const uint4*>(cnt + g0), (int)(v - g0), nonzero);
+}
+
+__global__ void iso_group_sums(const unsigned char* __restrict__ cnt, long long V, int* __restrict__ gsum,
+                               bool nonzero) {
+  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long g0 = gi * 16;
+  if (g0 >= V) return;
+  const long long rest = V - g0;
+  gsum[gi] = (int)sum_first(*reinterpret_cast<const uint4*>(cnt + g0), rest < 16 ? (int)rest : 16, nonzero);
+}
+
 // Side of every vertex as one bit (a value equal to the isovalue counts as above), packed per 64 vertices of a row
 // by a wave ballot: the passes that need the 16 corners of a 4-cube read these words (L2-resident, shared by
 // neighbouring lanes) instead of 16 field values.  Non-finite values are reported here.
@@ -186,21 +218,17 @@ __global__ __launch_bounds__(kIsoBX) void iso_count(IsoGrid g, unsigned short* _
   tcnt[v] = (unsigned char)tets;
 }
 
-// list of the vertices whose cube has crossed pentachora (about one in sixteen on smooth fields), so that the
-// pentachoron pass runs on busy lanes only
-__global__ void iso_active_flags(const unsigned char* __restrict__ tcnt, long long V, unsigned char* __restrict__ flag) {
+// list of the vertices whose cube has crossed pentachora (about one in sixteen on smooth fields), in vertex order,
+// so that the pentachoron pass runs on busy lanes only
+__global__ void iso_active_list(const unsigned char* __restrict__ tcnt, const long long* __restrict__ abase,
+                                long long V, long long* __restrict__ list) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < V) flag[v] = tcnt[v] > 0 ? 1 : 0;
-}
-
-__global__ void iso_active_list(const unsigned char* __restrict__ flag, const long long* __restrict__ off, long long V,
-                                long long* __restrict__ list) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < V && flag[v]) list[off[v]] = v;
+  if (v < V && tcnt[v]) list[off16(abase, tcnt, v, true)] = v;
 }
 
 __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned short* __restrict__ emask,
-                                                    const long long* __restrict__ hoff, long long* __restrict__ edge_id,
+                                                    const long long* __restrict__ hbase,
+                                                    const unsigned char* __restrict__ hcnt, long long* __restrict__ edge_id,
                                                     float* __restrict__ pos, unsigned* __restrict__ parent) {
   const int x = blockIdx.x * kIsoBX + threadIdx.x;
   const int y = blockIdx.y;
@@ -210,7 +238,7 @@ __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned sho
   unsigned m = emask[v];
   if (!m) return;
   const float f0 = g.f[v];
-  long long o = hoff[v];
+  long long o = off16(hbase, hcnt, v, false);
   while (m) {
     const int b = __ffs(m) - 1;
     m &= m - 1;
@@ -232,10 +260,11 @@ __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned sho
 
 __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* __restrict__ active,
                                                      long long n_active, const unsigned short* __restrict__ emask,
-                                                     const long long* __restrict__ hoff,
-                                                     const unsigned char* __restrict__ tcnt, const long long* __restrict__ toff,
-                                                     unsigned* __restrict__ parent, int* __restrict__ tets,
-                                                     unsigned* __restrict__ status) {
+                                                     const long long* __restrict__ hbase,
+                                                     const unsigned char* __restrict__ hcnt,
+                                                     const unsigned char* __restrict__ tcnt,
+                                                     const long long* __restrict__ tbase, unsigned* __restrict__ parent,
+                                                     int* __restrict__ tets, unsigned* __restrict__ status) {
   const long long a_i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (a_i >= n_active) return;
   const long long v = active[a_i];
@@ -252,10 +281,10 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* 
 #pragma unroll
   for (int cm = 0; cm < 15; ++cm) {
     const long long w = vidx(g, x + (cm & 1), y + ((cm >> 1) & 1), z + ((cm >> 2) & 1), t + ((cm >> 3) & 1));
-    cb[cm] = hoff[w];
+    cb[cm] = off16(hbase, hcnt, w, false);
     cm_mask[cm] = emask[w];
   }
-  long long o = toff[v];
+  long long o = off16(tbase, tcnt, v, false);
   const long long o_end = o + tcnt[v];
   // Unions: the cube's crossed edges P (local set) grouped by "edges of a common pentachoron" (a group grows from
   // its lowest member through the side sets until it is stable); each member is united once with the group's first.
@@ -371,32 +400,37 @@ hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, floa
 }
 
 hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float c, const unsigned short* emask,
-                           const long long* hoff, long long* edge_id, float* pos, unsigned* parent, hipStream_t s) {
+                           const long long* hbase, const unsigned char* hcnt, long long* edge_id, float* pos,
+                           unsigned* parent, hipStream_t s) {
   const IsoGrid g{f, nx, ny, nz, nt, c, nullptr, (nx + 63) / 64};
-  iso_emit<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hoff, edge_id, pos, parent);
+  iso_emit<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hbase, hcnt, edge_id, pos, parent);
   return hipGetLastError();
 }
 
-hipError_t launch_iso_active(const unsigned char* tcnt, long long V, unsigned char* flag, long long* off, long long* total,
-                             long long* scan_tmp, long long* list, bool scatter, hipStream_t s) {
-  const unsigned b = (unsigned)((V + 255) / 256);
-  if (!scatter) {
-    iso_active_flags<<<b, 256, 0, s>>>(tcnt, V, flag);
-    return launch_scan_u8(flag, off, V, total, scan_tmp, s);
-  }
-  iso_active_list<<<b, 256, 0, s>>>(flag, off, V, list);
+hipError_t launch_iso_bases(const unsigned char* cnt, long long V, bool nonzero, int* gsum, long long* base,
+                            long long* total, long long* scan_tmp, hipStream_t s) {
+  const long long groups = (V + 15) / 16;
+  iso_group_sums<<<(unsigned)((groups + 255) / 256), 256, 0, s>>>(cnt, V, gsum, nonzero);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_scan(gsum, base, groups, total, scan_tmp, s);
+}
+
+hipError_t launch_iso_active(const unsigned char* tcnt, const long long* abase, long long V, long long* list,
+                             hipStream_t s) {
+  iso_active_list<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(tcnt, abase, V, list);
   return hipGetLastError();
 }
 
 hipError_t launch_iso_unite(const float* f, int nx, int ny, int nz, int nt, float c,
                             const unsigned long long* bits, const long long* active, long long n_active,
-                            const unsigned short* emask, const long long* hoff, const unsigned char* tcnt,
-                            const long long* toff, unsigned* parent, int* tets, unsigned* status,
-                            hipStream_t s) {
+                            const unsigned short* emask, const long long* hbase, const unsigned char* hcnt,
+                            const unsigned char* tcnt, const long long* tbase, unsigned* parent, int* tets,
+                            unsigned* status, hipStream_t s) {
   if (n_active == 0) return hipSuccess;
   const IsoGrid g{f, nx, ny, nz, nt, c, bits, (nx + 63) / 64};
-  iso_unite<<<(unsigned)((n_active + kIsoBX - 1) / kIsoBX), kIsoBX, 0, s>>>(g, active, n_active, emask, hoff, tcnt,
-                                                                            toff, parent, tets, status);
+  iso_unite<<<(unsigned)((n_active + kIsoBX - 1) / kIsoBX), kIsoBX, 0, s>>>(g, active, n_active, emask, hbase, hcnt,
+                                                                            tcnt, tbase, parent, tets, status);
   return hipGetLastError();
 }
 
