@@ -276,13 +276,20 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* 
   unsigned above, valid;
   corner_bits(g, x, y, z, t, above, valid);
   // first hit index and crossing mask of every corner that anchors an edge of a pentachoron (all but 1111)
-  long long cb[15];
+  long long cb[16];
   unsigned cm_mask[15];
+  // corners in x pairs (w, w + 1): one group load gives both offsets unless w ends its group of 16
 #pragma unroll
-  for (int cm = 0; cm < 15; ++cm) {
-    const long long w = vidx(g, x + (cm & 1), y + ((cm >> 1) & 1), z + ((cm >> 2) & 1), t + ((cm >> 3) & 1));
-    cb[cm] = off16(hbase, hcnt, w, false);
+  for (int cm = 0; cm < 15; cm += 2) {
+    const long long w = vidx(g, x, y + ((cm >> 1) & 1), z + ((cm >> 2) & 1), t + ((cm >> 3) & 1));
+    const long long g0 = w & ~15ll;
+    const int k = (int)(w - g0);
+    const uint4 q = *reinterpret_cast<const uint4*>(hcnt + g0);
+    cb[cm] = hbase[w >> 4] + sum_first(q, k, false);
+    const unsigned wk = k < 4 ? q.x : (k < 8 ? q.y : (k < 12 ? q.z : q.w));
+    cb[cm + 1] = k < 15 ? cb[cm] + ((wk >> (8 * (k & 3))) & 0xFFu) : hbase[(w + 1) >> 4];
     cm_mask[cm] = emask[w];
+    if (cm + 1 < 15) cm_mask[cm + 1] = emask[w + 1];
   }
   long long o = off16(tbase, tcnt, v, false);
   const long long o_end = o + tcnt[v];
