@@ -14,6 +14,7 @@
 #include "../../include/ftk.h"
 #include "common.h"
 #include "internal.h"
+#include "offsets16.h"
 
 namespace {
 
@@ -1932,9 +1933,9 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   HIP_TRY(ftk::launch_iso_count(field, (int)nx, (int)ny, (int)nz, (int)nt, isovalue, bits, emask, hcnt, tcnt,
                                 &dctl->status, s));
-  HIP_TRY(ftk::launch_iso_bases(hcnt, V, false, gsum, hbase, &dctl->total, tmp, s));
-  HIP_TRY(ftk::launch_iso_bases(tcnt, V, false, gsum, tbase, (long long*)&dctl->cnt[ftk::CNT_LIST], tmp, s));
-  HIP_TRY(ftk::launch_iso_bases(tcnt, V, true, gsum, abase, (long long*)&dctl->cnt[ftk::CNT_WORK], tmp, s));
+  HIP_TRY(ftk::launch_group16_bases(hcnt, V, false, gsum, hbase, &dctl->total, tmp, s));
+  HIP_TRY(ftk::launch_group16_bases(tcnt, V, false, gsum, tbase, (long long*)&dctl->cnt[ftk::CNT_LIST], tmp, s));
+  HIP_TRY(ftk::launch_group16_bases(tcnt, V, true, gsum, abase, (long long*)&dctl->cnt[ftk::CNT_WORK], tmp, s));
   Ctl h;
   ftk_status st = read_ctl(&h, dctl, s);
   if (st) return st;
@@ -2177,16 +2178,18 @@ ftk_status ftk_track_cp_mesh(const ftk_mesh* m, const float* field, int64_t nt, 
   const long long S = 3 * nf + 2 * ne, NF = S * nt;
   const Alloc al = make_alloc(o, s);
   Scratch sc(al);
-  unsigned char* flag = sc.get<unsigned char>((size_t)NF);
-  long long* off = sc.get<long long>((size_t)NF);
-  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(NF));
+  const long long G = (NF + 15) / 16;  // groups of 16 faces: the offsets keep one base per group
+  unsigned char* flag = sc.get<unsigned char>((size_t)G * 16);
+  int* gsum = sc.get<int>((size_t)G);
+  long long* base = sc.get<long long>((size_t)G);
+  long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(G));
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!flag || !off || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  if (!flag || !gsum || !base || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   const float qscale = std::ldexp(1.0f, o.quant_log2);
   HIP_TRY(ftk::launch_pm_test(m->xy, m->tri, m->edge, m->tri_edge, field, nv, nf, ne, (int)nt, qscale, flag,
                               &dctl->status, s));
-  HIP_TRY(ftk::launch_scan_u8(flag, off, NF, &dctl->total, tmp, s));
+  HIP_TRY(ftk::launch_group16_bases(flag, NF, false, gsum, base, &dctl->total, tmp, s));
   Ctl h;
   st = read_ctl(&h, dctl, s);
   if (st) return st;
@@ -2209,7 +2212,7 @@ ftk_status ftk_track_cp_mesh(const ftk_mesh* m, const float* field, int64_t nt, 
   }
   hipError_t hr = hipSuccess;
   if (nh > 0) {
-    hr = ftk::launch_pm_emit(m->xy, m->tri, m->edge, m->tri_edge, field, nv, nf, ne, (int)nt, qscale, flag, off,
+    hr = ftk::launch_pm_emit(m->xy, m->tri, m->edge, m->tri_edge, field, nv, nf, ne, (int)nt, qscale, flag, base,
                              (long long*)r.face_id, r.pos, parent, &dctl->status, s);
     if (hr == hipSuccess)
       hr = ftk::launch_uf_label(parent, (const long long*)r.face_id, (long long*)r.label, nh, dctl->cnt, s);

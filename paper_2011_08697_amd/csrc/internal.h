@@ -165,10 +165,6 @@ hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, floa
 hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float c, const unsigned short* emask,
                            const long long* hbase, const unsigned char* hcnt, long long* edge_id, float* pos,
                            unsigned* parent, hipStream_t s);
-// offsets of the byte counts cnt[V] (allocated to a multiple of 16 bytes): base[g] = sum of the counts (nonzero:
-// of the nonzero counts) of the vertices before group g of 16 (gsum, base: ceil(V / 16) entries; *total = sum of all)
-hipError_t launch_iso_bases(const unsigned char* cnt, long long V, bool nonzero, int* gsum, long long* base,
-                            long long* total, long long* scan_tmp, hipStream_t s);
 // ascending list of the vertices with tetrahedra (tcnt > 0), at their offsets from abase (nonzero counts)
 hipError_t launch_iso_active(const unsigned char* tcnt, const long long* abase, long long V, long long* list,
                              hipStream_t s);
@@ -185,14 +181,15 @@ hipError_t launch_vx_detect(const float* psi, int nx, int ny, int nz, int nt, fl
 hipError_t launch_vx_emit(const float* psi, int nx, int ny, int nz, int nt, float qscale,
                           const unsigned long long* tmask, const long long* hoff, long long* tri_id, float* pos,
                           unsigned* parent, hipStream_t s);
-// Critical points on an extruded triangle mesh (prism.hip): face tests over nt * S faces (flag), then emission and
-// the tetrahedron unions from the scanned flags.
+// Critical points on an extruded triangle mesh (prism.hip): face tests over nt * S faces (flag, allocated to a
+// multiple of 16 bytes), then emission and the tetrahedron unions, with the hit offsets from the group bases of the
+// flags (offsets16.h).
 hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
                           long long nv, long long nf, long long ne, int nt, float qscale, unsigned char* flag,
                           unsigned* status, hipStream_t s);
 hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
                           long long nv, long long nf, long long ne, int nt, float qscale, const unsigned char* flag,
-                          const long long* off, long long* face_id, float* pos, unsigned* parent, unsigned* status,
+                          const long long* base, long long* face_id, float* pos, unsigned* parent, unsigned* status,
                           hipStream_t s);
 // Type smoothing and run simplification along an order (head/heads: [n_hits] int / int64 scratch).
 hipError_t launch_smooth(const long long* order, const long long* offsets, const int* n_ends, long long n_traj,

@@ -19,6 +19,7 @@
 //                the neighbouring pentachoron.
 // Labels (smallest edge id of each isovolume) come from the shared union-find label kernel.
 #include "common.h"
+#include "offsets16.h"
 #include "internal.h"
 #include "kuhn.h"
 #include "uf_cached.h"
@@ -110,38 +111,6 @@ struct IsoGrid {
 
 __device__ __forceinline__ long long vidx(const IsoGrid& g, int x, int y, int z, int t) {
   return (((long long)t * g.nz + z) * g.ny + y) * g.nx + x;
-}
-
-// Offsets of per-vertex byte counts (crossings, tetrahedra, active flags) without full-grid int64 scans: one base
-// per group of 16 vertices (exclusive scan of the group sums, V/16 entries) and, at lookup, the counts of the
-// vertex's earlier group members summed from one 16-byte load.  Count arrays are allocated to a multiple of 16.
-// sum_first: the first k (0..16) bytes of a group; nonzero = count the nonzero bytes instead.
-__device__ __forceinline__ unsigned sum_first(const uint4 q, int k, bool nonzero) {
-  const unsigned w[4] = {q.x, q.y, q.z, q.w};
-  unsigned s = 0;
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    const int nb = k - 4 * d;  // bytes of word d that are counted
-    unsigned x = nb >= 4 ? w[d] : (nb <= 0 ? 0u : (w[d] & ((1u << (8 * nb)) - 1u)));
-    if (nonzero) x = ((((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) & 0x80808080u) >> 7;  // 1 per nonzero byte
-    s = __builtin_amdgcn_sad_u8(x, 0u, s);  // + sum of the four bytes
-  }
-  return s;
-}
-
-__device__ __forceinline__ long long off16(const long long* __restrict__ base, const unsigned char* __restrict__ cnt,
-                                           long long v, bool nonzero) {
-  const long long g0 = v & ~15ll;
-  return base[v >> 4] + sum_first(*reinterpret_cast<const uint4*>(cnt + g0), (int)(v - g0), nonzero);
-}
-
-__global__ void iso_group_sums(const unsigned char* __restrict__ cnt, long long V, int* __restrict__ gsum,
-                               bool nonzero) {
-  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long g0 = gi * 16;
-  if (g0 >= V) return;
-  const long long rest = V - g0;
-  gsum[gi] = (int)sum_first(*reinterpret_cast<const uint4*>(cnt + g0), rest < 16 ? (int)rest : 16, nonzero);
 }
 
 // Side of every vertex as one bit (a value equal to the isovalue counts as above), packed per 64 vertices of a row
@@ -412,15 +381,6 @@ hipError_t launch_iso_emit(const float* f, int nx, int ny, int nz, int nt, float
   const IsoGrid g{f, nx, ny, nz, nt, c, nullptr, (nx + 63) / 64};
   iso_emit<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hbase, hcnt, edge_id, pos, parent);
   return hipGetLastError();
-}
-
-hipError_t launch_iso_bases(const unsigned char* cnt, long long V, bool nonzero, int* gsum, long long* base,
-                            long long* total, long long* scan_tmp, hipStream_t s) {
-  const long long groups = (V + 15) / 16;
-  iso_group_sums<<<(unsigned)((groups + 255) / 256), 256, 0, s>>>(cnt, V, gsum, nonzero);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_scan(gsum, base, groups, total, scan_tmp, s);
 }
 
 hipError_t launch_iso_active(const unsigned char* tcnt, const long long* abase, long long V, long long* list,

@@ -13,6 +13,7 @@
 //   pm_emit  -- face ids, points from the exact cofactors (Eq. 2) in (x, y, t), identity parents.
 //   pm_unite -- one lane per (prism, step): the two punctured faces of each of its three tetrahedra are united.
 #include "common.h"
+#include "offsets16.h"
 #include "internal.h"
 #include "uf_cached.h"
 
@@ -102,7 +103,7 @@ __global__ void pm_test(PmMesh m, unsigned char* __restrict__ flag, unsigned* __
   if (st && f < m.nf) atomicOr(status, st);
 }
 
-__global__ void pm_emit(PmMesh m, const unsigned char* __restrict__ flag, const long long* __restrict__ off,
+__global__ void pm_emit(PmMesh m, const unsigned char* __restrict__ flag, const long long* __restrict__ base,
                         long long* __restrict__ face_id, float* __restrict__ pos, unsigned* __restrict__ parent) {
   const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
@@ -125,7 +126,7 @@ __global__ void pm_emit(PmMesh m, const unsigned char* __restrict__ flag, const 
     mu[1] = (double)C1 / D;
     mu[2] = (double)C2 / D;
   }
-  const long long o = off[id];
+  const long long o = off16(base, flag, id, false);
   face_id[o] = id;
   if (pos) {
     double p[3] = {0.0, 0.0, 0.0};
@@ -142,7 +143,7 @@ __global__ void pm_emit(PmMesh m, const unsigned char* __restrict__ flag, const 
   parent[o] = (unsigned)o;
 }
 
-__global__ void pm_unite(PmMesh m, const unsigned char* __restrict__ flag, const long long* __restrict__ off,
+__global__ void pm_unite(PmMesh m, const unsigned char* __restrict__ flag, const long long* __restrict__ gbase,
                          unsigned* __restrict__ parent, unsigned* __restrict__ status) {
   const long long T = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
@@ -160,7 +161,7 @@ __global__ void pm_unite(PmMesh m, const unsigned char* __restrict__ flag, const
     int n = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (flag[tet[k][j]]) h[n++] = off[tet[k][j]];
+      if (flag[tet[k][j]]) h[n++] = off16(gbase, flag, tet[k][j], false);
     if (n == 2)
       uf_unite_cached(parent, (unsigned)h[0], (unsigned)h[1]);
     else if (n != 0)
@@ -180,12 +181,12 @@ hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, cons
 
 hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
                           long long nv, long long nf, long long ne, int nt, float qscale, const unsigned char* flag,
-                          const long long* off, long long* face_id, float* pos, unsigned* parent, unsigned* status,
+                          const long long* base, long long* face_id, float* pos, unsigned* parent, unsigned* status,
                           hipStream_t s) {
   const PmMesh m{xy, tri, edge, tri_edge, field, nv, nf, ne, nf + 2 * ne + 2 * nf, nt, qscale};
-  pm_emit<<<dim3((unsigned)((m.S + 255) / 256), (unsigned)nt), 256, 0, s>>>(m, flag, off, face_id, pos, parent);
+  pm_emit<<<dim3((unsigned)((m.S + 255) / 256), (unsigned)nt), 256, 0, s>>>(m, flag, base, face_id, pos, parent);
   if (nt > 1)
-    pm_unite<<<dim3((unsigned)((nf + 255) / 256), (unsigned)(nt - 1)), 256, 0, s>>>(m, flag, off, parent, status);
+    pm_unite<<<dim3((unsigned)((nf + 255) / 256), (unsigned)(nt - 1)), 256, 0, s>>>(m, flag, base, parent, status);
   return hipGetLastError();
 }
 
