@@ -84,13 +84,18 @@ __global__ __launch_bounds__(kVxBX) void vx_edges(VxGrid g, unsigned short* __re
   long long q0[2];
   vx_q(g, x, y, z, t, q0, st);
   unsigned m = 0;
+  // the 15 corner vectors from clamped (in-grid) addresses, all loads in flight together; corners outside the grid
+  // are dropped after
+  long long q1[16][2];
+#pragma unroll
   for (unsigned M = 1; M < 16; ++M) {
-    if (!vx_corner_ok(g, x, y, z, t, M)) continue;
-    long long q1[2];
     unsigned st1 = 0;  // each vertex reports its own values
-    vx_q(g, x + (M & 1u), y + ((M >> 1) & 1u), z + ((M >> 2) & 1u), t + ((M >> 3) & 1u), q1, st1);
-    m |= vx_sos2(q0, q1) << (M - 1);
+    vx_q(g, min(x + (int)(M & 1u), g.nx - 1), min(y + (int)((M >> 1) & 1u), g.ny - 1),
+         min(z + (int)((M >> 2) & 1u), g.nz - 1), min(t + (int)((M >> 3) & 1u), g.nt - 1), q1[M], st1);
   }
+#pragma unroll
+  for (unsigned M = 1; M < 16; ++M)
+    if (vx_corner_ok(g, x, y, z, t, M)) m |= vx_sos2(q0, q1[M]) << (M - 1);
   emask[vx_vidx(g, x, y, z, t)] = (unsigned short)m;
   if (st) atomicOr(status, st);
 }
