@@ -424,6 +424,26 @@ constexpr Tri2Tables build_tri2_tables() {
 constexpr Tri2Tables kTri2Tab = build_tri2_tables();
 __constant__ Tri2Tables kTri2Dev = kTri2Tab;  // read per hit with a lane-dependent type (cached, no LDS)
 
+// The same tables as 24 words for an LDS copy: word 2 ty + k = cof[ty][k] (bits 0-24), and pack[ty] in bits 25-31
+// of word 2 ty.  Per-hit reads from LDS leave the vector memory counter to the stores, which a global table read
+// would have to wait for.
+struct Tri2Words {
+  unsigned w[24];
+};
+constexpr Tri2Words build_tri2_words() {
+  Tri2Words r{};
+  for (int ty = 0; ty < 12; ++ty) {
+    r.w[2 * ty] = kTri2Tab.cof[ty][0] | ((unsigned)kTri2Tab.pack[ty] << 25);
+    r.w[2 * ty + 1] = kTri2Tab.cof[ty][1];
+  }
+  return r;
+}
+static_assert(build_tri2_words().w[0] >> 25 == kTri2Tab.pack[0], "pack field");
+__constant__ Tri2Words kTri2WordsDev = build_tri2_words();
+
+// Neighbour anchor slots (SELF, MX, PX, MY, PY, MT, PT) in 2-bit fields: column + 1 and row + 1 of the anchor.
+constexpr unsigned kSlotCol = 0x1561u, kSlotRow = 0x1615u;
+
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -496,7 +516,7 @@ __device__ __forceinline__ void wg_unite(unsigned* parent, unsigned a, unsigned 
 
 // Edge list staging: links that leave the tile/chunk are collected in LDS and appended to the global list in
 // batches (one global atomic per batch; same-address atomics serialise at one L2 channel).
-constexpr int kEdgeStage = 512;
+constexpr int kEdgeStage = 496;
 
 // Wave-aggregated append of (idx, partner) for the active lanes with want == true: one LDS add reserves the
 // wave's slots; slots past the stage capacity go straight to the global list (one global add for them).
@@ -700,6 +720,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   __shared__ uint2 s_stage[kEdgeStage];
   __shared__ int s_stage_n;
   __shared__ unsigned long long s_red[4];
+  __shared__ unsigned s_cof[24];  // triangle side words (Tri2Words)
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int x0 = bx * TX, y0 = by * TY;
@@ -924,6 +945,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
     s_have[0] = s_have[1] = -1;
     s_slice[0] = s_slice[1] = s_slice[2] = -2;
   }
+  if (tid < 24) s_cof[tid] = kTri2WordsDev.w[tid];
   // hit counts and offsets of this tile's row segments for all its steps, read once: empty steps are skipped
   // without touching their masks
   for (int i = tid; i < (t1 - t0) * TY; i += 256) {
@@ -1036,6 +1058,16 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       const unsigned base = s_ro[t - t0][ly];
       const unsigned row_lbase = plane_global ? 0u : lbase[t - t0][ly];
       const int cur = t % 3;
+      // ring slot of each neighbour anchor slot (2-bit fields, as kSlotCol)
+      const unsigned rsw = (unsigned)cur * 0x155u | (unsigned)((t + 2) % 3) << 10 | (unsigned)((t + 1) % 3) << 12;
+      // local id of a smaller partner = its hit index + (local base - first hit index) of its row segment: the
+      // same anchor or x - 1 (this row), y - 1, or step t - 1 (read only when that segment is in this chunk)
+      const unsigned d_self = row_lbase - base;
+      const unsigned d_my = (!plane_global && ly > 0) ? lbase[t - t0][ly - 1] - s_ro[t - t0][ly - 1] : 0u;
+      const unsigned d_mt = (!plane_global && t - 1 >= chunk_t0) ? lbase[t - 1 - t0][ly] - s_ro[t - 1 - t0][ly] : 0u;
+      // link class per smaller-partner slot (2-bit fields): 0 united here, 1 global list, 2 staged for the flush
+      const unsigned cls_mt = t - 1 >= chunk_t0 ? 0u : (t - 1 >= t0 ? 2u : 1u);
+      const unsigned clw = (ly == 0 ? 1u << (2 * NB_MY) : 0u) | cls_mt << (2 * NB_MT);
 
       // hit -> (anchor lane, type) map of this row segment (wavefront-private)
       {
@@ -1055,7 +1087,8 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
         const int L = (int)(ent & 63u), ty = (int)(ent >> 6);
         const unsigned idx = base + j;
         const int ax = x0 + L;
-        const unsigned pk = kTri2Dev.pack[ty];
+        const unsigned w0 = s_cof[2 * ty], w1 = s_cof[2 * ty + 1];
+        const unsigned pk = w0 >> 25;
         const int m1 = pk & 15, m2 = pk >> 4;
         // vertex offsets along x, y, t of v1 and v2
         const int dx1 = m1 & 1, dy1 = (m1 >> 1) & 1, dt1 = (m1 >> 2) & 1;
@@ -1096,7 +1129,7 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-          const unsigned w = kTri2Dev.cof[ty][k];
+          const unsigned w = k == 0 ? w0 : w1;
           const int rule = w & 3, axis = (w >> 2) & 3;
           const int pa = axis == 0 ? ax : (axis == 1 ? y : t);
           const int Na = axis == 0 ? nx : (axis == 1 ? ny : nt);
@@ -1107,10 +1140,11 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           for (int sdx = 0; sdx < 3; ++sdx) {
             const unsigned f = (w >> (4 + 7 * sdx)) & 127u;
             const int slot = f & 7, tt = f >> 3;
-            // ring slot, slice row and column of the neighbour anchor
-            const int rs = slot == NB_MT ? (t + 2) % 3 : (slot == NB_PT ? (t + 1) % 3 : cur);
-            const int rr = ly + 1 + (slot == NB_MY ? -1 : (slot == NB_PY ? 1 : 0));
-            const int rc = L + 1 + (slot == NB_MX ? -1 : (slot == NB_PX ? 1 : 0));
+            // ring slot, slice row and column of the neighbour anchor (bit fields: no branch on the slot)
+            const unsigned s2 = (unsigned)slot * 2u;
+            const int rs = (int)((rsw >> s2) & 3u);
+            const int rr = ly + (int)((kSlotRow >> s2) & 3u);
+            const int rc = L + (int)((kSlotCol >> s2) & 3u);
             const unsigned um = rm[rs][rr * RW + rc];
             const unsigned hit = (um >> tt) & 1u;
             const unsigned cand = rb[rs][rr] + (unsigned)(int)rx[rs][rr * RW + rc] + __popc(um & ((1u << tt) - 1u));
@@ -1138,19 +1172,17 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           c1 = ns > 1 ? 1 : -1;
         } else {
           const unsigned li = row_lbase + j;
-          auto link_class = [&](int sl) -> int {
-            if (sl == NB_MT && t - 1 < chunk_t0) return t - 1 >= t0 ? 2 : 1;
-            return ((sl == NB_MX && L == 0) || (sl == NB_MY && ly == 0)) ? 1 : 0;
-          };
+          const unsigned clw_l = clw | (L == 0 ? 1u << (2 * NB_MX) : 0u);
+          auto link_class = [&](int sl) -> int { return (int)((clw_l >> (2 * sl)) & 3u); };
           auto local_id = [&](unsigned other, int sl) -> unsigned {
-            const int prow = sl == NB_MY ? ly - 1 : ly;
-            const int pstep = (sl == NB_MT ? t - 1 : t) - t0;
-            return lbase[pstep][prow] + (other - s_ro[pstep][prow]);
+            return other + (sl == NB_MY ? d_my : (sl == NB_MT ? d_mt : d_self));
           };
           c0 = ns > 0 ? link_class(sl0) : -1;
           c1 = ns > 1 ? link_class(sl1) : -1;
-          if (c0 == 0) lunite(lpar, li, local_id(sm0, sl0));
-          if (c1 == 0) lunite(lpar, li, local_id(sm1, sl1));
+          unsigned l0 = local_id(sm0, sl0), l1 = local_id(sm1, sl1);
+          asm volatile("" : "+v"(l0), "+v"(l1));  // selected here, not inside the branches below
+          if (c0 == 0) lunite(lpar, li, l0);
+          if (c1 == 0) lunite(lpar, li, l1);
         }
         append_edge(c0 > 0, c0 == 2 ? sm0 : idx, c0 == 2 ? idx : sm0, s_stage, &s_stage_n, scap, o.work, work_cnt);
         append_edge(c1 > 0, c1 == 2 ? sm1 : idx, c1 == 2 ? idx : sm1, s_stage, &s_stage_n, scap, o.work, work_cnt);
