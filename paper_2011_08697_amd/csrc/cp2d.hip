@@ -861,6 +861,33 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
   auto flush = [&]() {
     __syncthreads();  // parents written so far by this workgroup are visible to it
     const int n = s_chunk_n, nseg = s_nseg;
+    {
+      // The chunk's local links: the hit loop made each hit's first smaller partner its parent (a forest: parents
+      // point to smaller local ids) and left a second one in the entry's high half.  Take those out, point every
+      // entry at its root (path halving), then unite the second partners through the shallow trees.
+      unsigned sec[CAP / 256];
+#pragma unroll
+      for (int k = 0; k < CAP / 256; ++k) {
+        const int i = tid + 256 * k;
+        sec[k] = 0u;
+        if (i < n) {
+          const unsigned e = lpar[i];
+          sec[k] = e >> 16;
+          if (sec[k]) lpar[i] = e & 0xFFFFu;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < CAP / 256; ++k) {
+        const int i = tid + 256 * k;
+        if (i < n) lpar[i] = lfind(lpar, (unsigned)i);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < CAP / 256; ++k)
+        if (sec[k]) lunite(lpar, (unsigned)(tid + 256 * k), sec[k] - 1u);
+      __syncthreads();
+    }
     const int nst = s_stage_n < scap ? s_stage_n : scap;
     for (int i = tid; i < nst; i += 256) {
       const uint2 e = s_stage[i];
@@ -1179,10 +1206,11 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
           };
           c0 = ns > 0 ? link_class(sl0) : -1;
           c1 = ns > 1 ? link_class(sl1) : -1;
-          unsigned l0 = local_id(sm0, sl0), l1 = local_id(sm1, sl1);
-          asm volatile("" : "+v"(l0), "+v"(l1));  // selected here, not inside the branches below
-          if (c0 == 0) lunite(lpar, li, l0);
-          if (c1 == 0) lunite(lpar, li, l1);
+          // The first smaller partner of this chunk becomes the parent (parents point to smaller local ids: a
+          // forest); a second one waits in the high half of the entry for the chunk's flush.  Only this lane writes
+          // the entry, and nothing reads the chunk's entries before the flush.
+          const unsigned l0 = local_id(sm0, sl0), l1 = local_id(sm1, sl1);
+          lpar[li] = (c0 == 0 ? l0 : li) | (c1 == 0 ? (l1 + 1u) << 16 : 0u);
         }
         append_edge(c0 > 0, c0 == 2 ? sm0 : idx, c0 == 2 ? idx : sm0, s_stage, &s_stage_n, scap, o.work, work_cnt);
         append_edge(c1 > 0, c1 == 2 ? sm1 : idx, c1 == 2 ? idx : sm1, s_stage, &s_stage_n, scap, o.work, work_cnt);
