@@ -842,6 +842,10 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
       x = p;
     }
   };
+  // Before the parents are written, each remaining local root r of segment k holds kRootTag + k (above every local
+  // id and stage marker), so that its hit index s_segg[k] + (r - s_segl[k]) needs no search.
+  constexpr unsigned kRootTag = 0x8000u;
+  static_assert(CAP + kEdgeStage <= (int)kRootTag, "root tags above local ids and stage markers");
   // local id of a hit of the current chunk from its global index (segments are in increasing global order)
   auto seg_search = [&](const unsigned* key, unsigned v) -> int {
     int lo = 0, hi = s_nseg;  // last segment with key <= v
@@ -892,11 +896,13 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
     for (int i = tid; i < nst; i += 256) {
       const uint2 e = s_stage[i];
       if (e.x >= e.y) continue;  // (hit, smaller partner): for the global list
-      const unsigned R = wg_find(o.parent, e.x);
-      s_stage[i] = make_uint2(R, R);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      // The partner's parent was written by an earlier flush of this workgroup: an ancestor of its set, which
+      // serves as the attachment point (the load is in flight during the local search).
+      const unsigned R = wg_load(o.parent, e.x);
       const int k = seg_search(s_segg, e.y);
       unsigned r = lroot(s_segl[k] + (e.y - s_segg[k]));
+      s_stage[i] = make_uint2(R, R);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       for (;;) {
         if (r >= (unsigned)CAP) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -910,15 +916,25 @@ __device__ __forceinline__ void emit2d_tile(const Grid2& g, int TT, int bx, int 
     }
     __syncthreads();
     for (int k = wave; k < nseg; k += 4) {
+      const unsigned l0 = s_segl[k], l1 = k + 1 < nseg ? s_segl[k + 1] : (unsigned)n;
+      for (unsigned li = l0 + lane; li < l1; li += 64)
+        if (lpar[li] == li) lpar[li] = kRootTag + (unsigned)k;
+    }
+    __syncthreads();
+    for (int k = wave; k < nseg; k += 4) {
       const unsigned l0 = s_segl[k], l1 = k + 1 < nseg ? s_segl[k + 1] : (unsigned)n, g0 = s_segg[k];
       for (unsigned li = l0 + lane; li < l1; li += 64) {
-        const unsigned r = lroot(li);
+        unsigned x = li, p = lpar[li];
+        while (p < (unsigned)CAP) {
+          x = p;
+          p = lpar[x];
+        }
         unsigned target;
-        if (r >= (unsigned)CAP) {
-          target = s_stage[r - CAP].x;
+        if (p >= kRootTag) {
+          const unsigned kr = p - kRootTag;
+          target = s_segg[kr] + (x - s_segl[kr]);
         } else {
-          const int kr = seg_search(s_segl, r);
-          target = s_segg[kr] + (r - s_segl[kr]);
+          target = s_stage[p - CAP].x;
         }
         o.parent[g0 + (li - l0)] = target;
       }
