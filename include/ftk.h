@@ -72,7 +72,10 @@ typedef enum {
 #define FTK_OUT_ALL 31u
 #define FTK_OUT_DEFAULT 29u /* POS | TYPE | LABEL | FLAGS: the 30-byte record per hit (face_id, pos, type, flags, label) */
 
-/* Device allocator hooks (e.g. a framework's caching allocator).  Both must be stream-ordered on `stream`. */
+/* Device allocator hooks (e.g. a framework's caching allocator).  Both must be stream-ordered on `stream`; alloc
+ * must return memory aligned to at least 16 bytes (hipMalloc and torch's caching allocator align to 256): kernels
+ * write some outputs with 16-byte stores, and a call that receives a misaligned output array fails with
+ * FTK_ERR_ARG rather than writing it. */
 typedef void* (*ftk_alloc_fn)(size_t bytes, ftk_stream_t stream, void* ctx);
 typedef void (*ftk_free_fn)(void* ptr, ftk_stream_t stream, void* ctx);
 

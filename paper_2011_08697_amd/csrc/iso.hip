@@ -18,6 +18,8 @@
 //                split along the three monotone paths (staircase), which matches on the quadrilateral shared with
 //                the neighbouring pentachoron.
 // Labels (smallest edge id of each isovolume) come from the shared union-find label kernel.
+#include <utility>
+
 #include "common.h"
 #include "offsets16.h"
 #include "internal.h"
@@ -227,6 +229,87 @@ __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned sho
   }
 }
 
+// Tessellation of the cube's pentachoron of type TY (Sec. 6.2): with k of its five chain vertices above the level,
+// case I (one vertex on the smaller side) gives the tetrahedron of its four crossed edges, case II (two) the three
+// tetrahedra of the prism between their crossed edges.  The chain corners are compile-time constants, so the
+// corners' first hit indices and crossing masks are read from registers by constant index; the lane-dependent
+// chain positions are bit fields, and every tetrahedron is one 16-byte store.  Returns false after flagging an
+// internal error (a crossed edge the count pass did not record, or more tetrahedra than it counted).
+// Hit index of the crossed edge between chain positions i and j of a pentachoron (chain corners in 4-bit fields of
+// chw; lower end at position min(i, j) <= 3, whose corner's first hit index and crossing mask are b_k and m_k).
+// The values come by value: selecting between references would become a load through a selected address, which
+// keeps them in scratch memory.
+__device__ __forceinline__ int iso_edge(unsigned i, unsigned j, unsigned chw, long long b0, long long b1, long long b2,
+                                        long long b3, unsigned m0, unsigned m1, unsigned m2, unsigned m3, bool& bad) {
+  const unsigned lo = min(i, j), hi = max(i, j);
+  const unsigned a = (chw >> (4u * lo)) & 15u, M = ((chw >> (4u * hi)) & 15u) ^ a;
+  const long long b = lo == 0 ? b0 : (lo == 1 ? b1 : (lo == 2 ? b2 : b3));
+  const unsigned mk = lo == 0 ? m0 : (lo == 1 ? m1 : (lo == 2 ? m2 : m3));
+  bad = bad || !((mk >> (M - 1u)) & 1u);
+  return (int)(b + __popc(mk & ((1u << (M - 1u)) - 1u)));
+}
+
+template <int TY>
+__device__ __forceinline__ bool iso_tess(unsigned above, const long long (&cb)[16], const unsigned (&cm_mask)[15],
+                                         long long& o, long long o_end, int* __restrict__ tets, unsigned* status) {
+  constexpr PenCorners kP = build_pen_corners();
+  constexpr unsigned c0 = kP.c[TY][0], c1 = kP.c[TY][1], c2 = kP.c[TY][2], c3 = kP.c[TY][3], c4 = kP.c[TY][4];
+  constexpr unsigned chw = c0 | c1 << 4 | c2 << 8 | c3 << 12 | c4 << 16;
+  const unsigned lm = ((above >> c0) & 1u) | ((above >> c1) & 1u) << 1 | ((above >> c2) & 1u) << 2 |
+                      ((above >> c3) & 1u) << 3 | ((above >> c4) & 1u) << 4;
+  const int k = __popc(lm);
+  if (k == 0 || k == 5) return true;
+  // chain positions on the smaller side (minority: one or two) and the others, each in increasing order
+  const unsigned mino = k <= 2 ? lm : (~lm & 31u);
+  const int nm = __popc(mino);
+  const unsigned mi0 = (unsigned)__ffs((int)mino) - 1u, mi1 = (unsigned)__ffs((int)(mino & (mino - 1u))) - 1u;
+  unsigned majo = ~mino & 31u;
+  unsigned ma[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ma[q] = (unsigned)__ffs((int)majo) - 1u;
+    majo &= majo - 1u;
+  }
+  // hit index of the crossed edge between chain positions i and j (lower end at position min(i, j) <= 3)
+  const long long cb0 = cb[c0], cb1 = cb[c1], cb2 = cb[c2], cb3 = cb[c3];
+  const unsigned mk0 = cm_mask[c0], mk1 = cm_mask[c1], mk2 = cm_mask[c2], mk3 = cm_mask[c3];
+  bool bad = false;
+  auto edge = [&](unsigned i, unsigned j) -> int {
+    return iso_edge(i, j, chw, cb0, cb1, cb2, cb3, mk0, mk1, mk2, mk3, bad);
+  };
+  const bool two = nm == 2;
+  // case I: (m, a0..a3); case II: (p1, a0..a2), (p2, a0..a2)
+  const int e0 = edge(mi0, ma[0]), e1 = edge(mi0, ma[1]), e2 = edge(mi0, ma[2]);
+  const int e3 = two ? edge(mi1, ma[0]) : edge(mi0, ma[3]);
+  int e4 = 0, e5 = 0;
+  if (two) {
+    e4 = edge(mi1, ma[1]);
+    e5 = edge(mi1, ma[2]);
+  }
+  const int nt_here = two ? 3 : 1;
+  if (bad || o + nt_here > o_end) {
+    atomicOr(status, ST_INVARIANT);
+    return false;
+  }
+  int4* T = reinterpret_cast<int4*>(tets) + o;
+  if (!two) {
+    T[0] = make_int4(e0, e1, e2, e3);
+  } else {
+    T[0] = make_int4(e0, e1, e2, e5);
+    T[1] = make_int4(e0, e1, e4, e5);
+    T[2] = make_int4(e0, e3, e4, e5);
+  }
+  o += nt_here;
+  return true;
+}
+
+template <int... TY>
+__device__ __forceinline__ void iso_tess_all(std::integer_sequence<int, TY...>, unsigned above,
+                                             const long long (&cb)[16], const unsigned (&cm_mask)[15], long long& o,
+                                             long long o_end, int* __restrict__ tets, unsigned* status) {
+  (void)(iso_tess<TY>(above, cb, cm_mask, o, o_end, tets, status) && ...);  // stops at the first error
+}
+
 __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* __restrict__ active,
                                                      long long n_active, const unsigned short* __restrict__ emask,
                                                      const long long* __restrict__ hbase,
@@ -302,64 +385,7 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* 
       }
     }
   }
-  for (int ty = 0; ty < 24; ++ty) {
-    unsigned ch[5];
-    int k = 0;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      ch[i] = kPenDev.c[ty][i];
-      k += (above >> ch[i]) & 1u;
-    }
-    if (k == 0 || k == 5) continue;
-    // hit index of the edge between chain vertices i < j (crossed, so its bit is set; the count pass took the same
-    // decisions, so a clear bit is an internal error and the pentachoron is skipped)
-    bool bad = false;
-    auto edge = [&](int i, int j) -> long long {
-      const unsigned a = ch[i], M = ch[j] ^ ch[i];
-      const unsigned mk = cm_mask[a];
-      if (!((mk >> (M - 1)) & 1u)) bad = true;
-      return cb[a] + __popc(mk & ((1u << (M - 1)) - 1u));
-    };
-    // minority side: the one (case I) or two (case II) chain vertices on the less populated side
-    const unsigned lone_side = k <= 2 ? 1u : 0u;
-    int mi[2] = {0, 0}, ma[4] = {0, 0, 0, 0}, nm = 0, na = 0;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      if (((above >> ch[i]) & 1u) == lone_side) {
-        if (nm < 2) mi[nm++] = i;
-      } else {
-        if (na < 4) ma[na++] = i;
-      }
-    }
-    if (nm + na != 5) {
-      atomicOr(status, ST_INVARIANT);
-      return;
-    }
-    auto pe = [&](int p, int q) { return edge(min(mi[p], ma[q]), max(mi[p], ma[q])); };
-    for (int p = 0; p < nm; ++p)
-      for (int q = 0; q < na; ++q) (void)pe(p, q);
-    if (bad) {
-      atomicOr(status, ST_INVARIANT);
-      return;
-    }
-    // tetrahedra of the crossed edges (the (minority, majority) pairs)
-    const int nt_here = nm == 1 ? 1 : 3;
-    if (o + nt_here > o_end) {
-      atomicOr(status, ST_INVARIANT);
-      return;
-    }
-    int* T = tets + o * 4;
-    if (nm == 1) {
-      for (int q = 0; q < 4; ++q) T[q] = (int)pe(0, q);
-    } else {
-      const long long p1m1 = pe(0, 0), p1m2 = pe(0, 1), p1m3 = pe(0, 2);
-      const long long p2m1 = pe(1, 0), p2m2 = pe(1, 1), p2m3 = pe(1, 2);
-      T[0] = (int)p1m1; T[1] = (int)p1m2; T[2] = (int)p1m3; T[3] = (int)p2m3;
-      T[4] = (int)p1m1; T[5] = (int)p1m2; T[6] = (int)p2m2; T[7] = (int)p2m3;
-      T[8] = (int)p1m1; T[9] = (int)p2m1; T[10] = (int)p2m2; T[11] = (int)p2m3;
-    }
-    o += nt_here;
-  }
+  iso_tess_all(std::make_integer_sequence<int, 24>{}, above, cb, cm_mask, o, o_end, tets, status);
 }
 
 dim3 iso_grid(const IsoGrid& g) { return dim3((unsigned)((g.nx + kIsoBX - 1) / kIsoBX), (unsigned)g.ny, (unsigned)(g.nz * g.nt)); }
