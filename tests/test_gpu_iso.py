@@ -1,6 +1,8 @@
 """GPU parity of isovolume tracking (ftk_track_iso3d through the C ABI) against the oracle (oracle/iso.py): crossed
 edge ids, labels, component counts and tetrahedra bit-exact, intersection points within 1e-5 relative; plus
 errors, the empty case and sampled properties of the full 256^3 x 16 blob series."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -115,3 +117,64 @@ def test_full_size_blobs3d256_sampled():
             pts += [a, a + np.array([(mm >> b) & 1 for b in range(4)])]
         pts = np.array(pts)
         assert np.all(pts.max(0) - pts.min(0) <= 1)
+
+
+class _ShiftPool(F._TorchPool):
+    """torch-backed hooks that record the size of every request and hand out request number `shift` (if any) 4 bytes
+    past a 16-byte boundary."""
+
+    def __init__(self, device, shift=None):
+        super().__init__(device)
+        self.sizes = []
+        self.shift = shift
+        self.shifted = {}
+
+    def alloc(self, nbytes, stream, ctx):
+        self.sizes.append(int(nbytes))
+        if len(self.sizes) - 1 != self.shift:
+            return super().alloc(nbytes, stream, ctx)
+        p = super().alloc(nbytes + 16, stream, ctx)
+        if p is None:
+            return None
+        self.shifted[p + 4] = p
+        return p + 4
+
+    def free(self, ptr, stream, ctx):
+        super().free(self.shifted.pop(ptr, ptr), stream, ctx)
+
+
+def _iso_call(f, c, pool):
+    nt, nz, ny, nx = f.shape
+    o = F._options(pool)
+    r = F.IsoResult()
+    st = F.lib().ftk_track_iso3d(ctypes.c_void_p(f.data_ptr()), nx, ny, nz, nt, ctypes.c_float(c), ctypes.byref(o),
+                                 F._stream_handle(DEV), ctypes.byref(r))
+    torch.cuda.synchronize()
+    return st, r, o
+
+
+def test_misaligned_tetrahedron_array_is_refused():
+    """Tetrahedra are written with 16-byte stores: an allocator that returns a misaligned tetrahedron array gets
+    FTK_ERR_ARG before any kernel runs on it, and every block is handed back.  The tetrahedron request is found in
+    a first call's request sequence as the last of the four consecutive output requests (edge ids, positions,
+    labels, tetrahedra); only that request is shifted in the second call."""
+    f = torch.from_numpy(np.ascontiguousarray(
+        _linear(12, 11, 10, 3, lambda X, Y, Z, T: np.sin(0.7 * X) + np.cos(0.5 * Y) * np.sin(0.3 * Z + 0.4 * T)))
+    ).to(DEV)
+    rec = _ShiftPool(DEV)
+    st, r, o = _iso_call(f, 0.1, rec)
+    assert st == 0, F.last_error()
+    nh, ntets = int(r.n_hits), int(r.n_tets)
+    assert nh > 0 and ntets > 0
+    F.lib().ftk_iso_result_free(ctypes.byref(r), ctypes.byref(o), F._stream_handle(DEV))
+    torch.cuda.synchronize()
+    up = lambda b: (b + 255) & ~255  # noqa: E731
+    outs = [up(8 * nh), up(16 * nh), up(8 * nh), up(16 * ntets)]
+    idx = [i for i in range(3, len(rec.sizes)) if rec.sizes[i - 3:i + 1] == outs]
+    assert len(idx) == 1, rec.sizes
+    pool = _ShiftPool(DEV, shift=idx[0])
+    st, r, _ = _iso_call(f, 0.1, pool)
+    assert st == 1, F.last_error()
+    assert "16 bytes" in F.last_error()
+    assert pool.sizes == rec.sizes[:len(pool.sizes)] and len(pool.sizes) > idx[0]
+    assert pool.shifted == {} and pool.live == {}
