@@ -378,10 +378,11 @@ __global__ __launch_bounds__(kIsoBX) void iso_unite(IsoGrid g, const long long* 
       const int k0 = low_bit128(C);
       const long long h0 = hit(k0);
       C &= ~((u128)1 << k0);
+      unsigned r = C ? uf_find_cached(parent, (unsigned)h0) : 0u;
       while (C) {
         const int k = low_bit128(C);
         C &= ~((u128)1 << k);
-        uf_unite_cached(parent, (unsigned)h0, (unsigned)hit(k));
+        r = uf_unite_into(parent, r, (unsigned)hit(k));
       }
     }
   }

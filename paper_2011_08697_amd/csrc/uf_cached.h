@@ -23,4 +23,14 @@ __device__ __forceinline__ void uf_unite_cached(unsigned* parent, unsigned a, un
   uf_unite(parent, a, b);
 }
 
+// Unions of every member of a group with its first member: r is the group's representative as last found (found
+// from the first member, so an element of its set).  A member whose cached find reaches r is connected already;
+// otherwise the coherent path unites them and r is found again.  Returns the representative for the next member
+// (one find per member instead of two).
+__device__ __forceinline__ unsigned uf_unite_into(unsigned* parent, unsigned r, unsigned b) {
+  if (uf_find_cached(parent, b) == r) return r;
+  uf_unite(parent, r, b);
+  return uf_find_cached(parent, r);
+}
+
 }  // namespace ftk
