@@ -238,6 +238,14 @@ __device__ __forceinline__ int low_bit(u128 m) {
 // spilled) hides more of it than the unconstrained three (14.6 -> 12.9 ms on 512 x 128 x 64 x 8).
 __global__ __launch_bounds__(kVxBX) __attribute__((amdgpu_waves_per_eu(4))) void vx_unite(VxGrid g, const unsigned long long* __restrict__ tmask,
                                                    const long long* __restrict__ hoff, unsigned* __restrict__ parent) {
+  // anchor corner and type of each local triangle, read per union with a lane-dependent index: an LDS copy keeps
+  // a global table read out of the chain of dependent loads (table, hit offset, parents)
+  __shared__ unsigned char s_ci[kCubeTriN], s_ty[kCubeTriN];
+  if (threadIdx.x < kCubeTriN) {
+    s_ci[threadIdx.x] = kCubeTris.ci[threadIdx.x];
+    s_ty[threadIdx.x] = kCubeTris.ty[threadIdx.x];
+  }
+  __syncthreads();
   const int x = blockIdx.x * kVxBX + threadIdx.x;
   const int y = blockIdx.y;
   const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
@@ -257,8 +265,8 @@ __global__ __launch_bounds__(kVxBX) __attribute__((amdgpu_waves_per_eu(4))) void
   for (int k = 0; k < kCubeTriN; ++k)
     if ((tm[kCubeTris.ci[k]] >> kCubeTris.ty[k]) & 1ull) P |= (u128)1 << k;
   auto hit = [&](int k) -> long long {
-    const unsigned a = kCubeTris.ci[k];
-    const int ty = kCubeTris.ty[k];
+    const unsigned a = s_ci[k];
+    const int ty = s_ty[k];
     const long long w = vx_vidx(g, x + (a & 1u), y + ((a >> 1) & 1u), z + ((a >> 2) & 1u), t + ((a >> 3) & 1u));
     return hoff[w] + __popcll(tm[a] & ((1ull << ty) - 1ull));
   };
