@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned sho
   }
 }
 
-// Tessellation of the cube's pentachoron of type TY (Sec. 6.2): with k of its five chain vertices above the level,
+// Tessellation of the cube's pentachoron of type TY (Sec. 6.1): with k of its five chain vertices above the level,
 // case I (one vertex on the smaller side) gives the tetrahedron of its four crossed edges, case II (two) the three
 // tetrahedra of the prism between their crossed edges.  The chain corners are compile-time constants, so the
 // corners' first hit indices and crossing masks are read from registers by constant index; the lane-dependent
