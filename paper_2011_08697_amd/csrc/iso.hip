@@ -48,7 +48,6 @@ constexpr PenCorners build_pen_corners() {
   }
   return r;
 }
-__constant__ PenCorners kPenDev = build_pen_corners();
 
 // The edges of a 4-cube's pentachora are its 65 corner pairs a < a | M (a & M == 0, M != 0).  idx[a][M] is the local
 // index (255 for no edge), ea / eM its anchor corner and mask, side[pt] the 65-bit set (two words) of the 10 edges of
@@ -155,11 +154,20 @@ __device__ __forceinline__ void corner_bits(const IsoGrid& g, int x, int y, int 
   }
 }
 
-__device__ __forceinline__ int pen_above(unsigned above, int ty) {
-  int k = 0;
-#pragma unroll
-  for (int i = 0; i < 5; ++i) k += (above >> kPenDev.c[ty][i]) & 1u;
-  return k;
+// Tetrahedra of the isovolume in the pentachoron of type TY (Sec. 6.1): with k of its five chain vertices above the
+// level, 1 for case I (k = 1 or 4), 3 for case II (k = 2 or 3), 0 otherwise; the chain corners are a compile-time
+// mask, and the count per k is a nibble of 0x13310.
+template <int TY>
+__device__ __forceinline__ int pen_tets(unsigned above) {
+  constexpr PenCorners kP = build_pen_corners();
+  constexpr unsigned chain = 1u << kP.c[TY][0] | 1u << kP.c[TY][1] | 1u << kP.c[TY][2] | 1u << kP.c[TY][3] |
+                             1u << kP.c[TY][4];
+  return (int)((0x13310u >> (4u * (unsigned)__popc(above & chain))) & 15u);
+}
+
+template <int... TY>
+__device__ __forceinline__ int pen_tets_all(std::integer_sequence<int, TY...>, unsigned above) {
+  return (pen_tets<TY>(above) + ...);
 }
 
 __global__ __launch_bounds__(kIsoBX) void iso_count(IsoGrid g, unsigned short* __restrict__ emask,
@@ -177,13 +185,8 @@ __global__ __launch_bounds__(kIsoBX) void iso_count(IsoGrid g, unsigned short* _
   for (int M = 1; M < 16; ++M)
     if (((valid >> M) & 1u) && (((above >> M) ^ above) & 1u)) m |= 1u << (M - 1);
   int tets = 0;
-  if (valid == 0xffffu && above != 0u && above != 0xffffu) {
-#pragma unroll 4
-    for (int ty = 0; ty < 24; ++ty) {
-      const int k = pen_above(above, ty);
-      tets += (k == 1 || k == 4) ? 1 : ((k == 2 || k == 3) ? 3 : 0);
-    }
-  }
+  if (valid == 0xffffu && above != 0u && above != 0xffffu)
+    tets = pen_tets_all(std::make_integer_sequence<int, 24>{}, above);
   emask[v] = (unsigned short)m;
   hcnt[v] = (unsigned char)__popc(m);
   tcnt[v] = (unsigned char)tets;

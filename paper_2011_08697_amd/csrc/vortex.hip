@@ -109,12 +109,13 @@ __global__ __launch_bounds__(kVxBX) void vx_tris(VxGrid g, const unsigned short*
   if (x >= g.nx) return;
   const long long v = vx_vidx(g, x, y, z, t);
   const unsigned e0 = emask[v];
+  // edge words of the 15 other corners from clamped (in-grid) addresses, all loads in flight together; a corner
+  // outside the grid is never read below (a triangle is tested only when its corner b, a superset of a, is inside)
   unsigned ea[16];
 #pragma unroll
   for (unsigned a = 1; a < 16; ++a)
-    ea[a] = vx_corner_ok(g, x, y, z, t, a)
-                ? emask[vx_vidx(g, x + (a & 1u), y + ((a >> 1) & 1u), z + ((a >> 2) & 1u), t + ((a >> 3) & 1u))]
-                : 0u;
+    ea[a] = emask[vx_vidx(g, min(x + (int)(a & 1u), g.nx - 1), min(y + (int)((a >> 1) & 1u), g.ny - 1),
+                          min(z + (int)((a >> 2) & 1u), g.nz - 1), min(t + (int)((a >> 3) & 1u), g.nt - 1))];
   ea[0] = e0;
   unsigned long long m = 0;
 #pragma unroll
