@@ -1957,9 +1957,9 @@ ftk_status ftk_track_iso3d(const float* field, int64_t nx, int64_t ny, int64_t n
     ftk_iso_result_free(&r, opt, stream);
     return fail(FTK_ERR_OOM, "output allocation failed");
   }
-  if (((uintptr_t)r.tets & 15u) != 0) {  // tetrahedra are written with 16-byte stores
+  if ((((uintptr_t)r.tets | (uintptr_t)r.pos) & 15u) != 0) {  // tetrahedra and points: 16-byte stores
     ftk_iso_result_free(&r, opt, stream);
-    return fail(FTK_ERR_ARG, "the allocator returned a tetrahedron array not aligned to 16 bytes");
+    return fail(FTK_ERR_ARG, "the allocator returned a point or tetrahedron array not aligned to 16 bytes");
   }
   hipError_t he = hipSuccess;
   if (nh > 0) {

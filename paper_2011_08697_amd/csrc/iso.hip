@@ -209,26 +209,28 @@ __global__ __launch_bounds__(kIsoBX) void iso_emit(IsoGrid g, const unsigned sho
   const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
   if (x >= g.nx) return;
   const long long v = vidx(g, x, y, z, t);
-  unsigned m = emask[v];
+  const unsigned m = emask[v];
   if (!m) return;
   const float f0 = g.f[v];
-  long long o = off16(hbase, hcnt, v, false);
-  while (m) {
-    const int b = __ffs(m) - 1;
-    m &= m - 1;
-    const int M = b + 1;
+  // the far ends of the 15 edges from clamped (in-grid) addresses, all loads in flight before any store (a load
+  // issued after a store waits for it); crossed edges only reach corners inside the grid
+  float f1[16];
+#pragma unroll
+  for (int M = 1; M < 16; ++M)
+    f1[M] = g.f[vidx(g, min(x + (M & 1), g.nx - 1), min(y + ((M >> 1) & 1), g.ny - 1),
+                     min(z + ((M >> 2) & 1), g.nz - 1), min(t + ((M >> 3) & 1), g.nt - 1))];
+  const long long o0 = off16(hbase, hcnt, v, false);
+#pragma unroll
+  for (int M = 1; M < 16; ++M) {
+    if (!((m >> (M - 1)) & 1u)) continue;
+    const long long o = o0 + __popc(m & ((1u << (M - 1)) - 1u));
     const int dx = M & 1, dy = (M >> 1) & 1, dz = (M >> 2) & 1, dt = (M >> 3) & 1;
-    const float f1 = g.f[vidx(g, x + dx, y + dy, z + dz, t + dt)];
-    const float mu = (g.c - f0) / (f1 - f0);
-    edge_id[o] = v * 15 + b;
-    if (pos) {
-      pos[o * 4 + 0] = (float)x + mu * (float)dx;
-      pos[o * 4 + 1] = (float)y + mu * (float)dy;
-      pos[o * 4 + 2] = (float)z + mu * (float)dz;
-      pos[o * 4 + 3] = (float)t + mu * (float)dt;
-    }
+    const float mu = (g.c - f0) / (f1[M] - f0);
+    edge_id[o] = v * 15 + (M - 1);
+    if (pos)
+      reinterpret_cast<float4*>(pos)[o] = make_float4((float)x + mu * (float)dx, (float)y + mu * (float)dy,
+                                                      (float)z + mu * (float)dz, (float)t + mu * (float)dt);
     parent[o] = (unsigned)o;
-    ++o;
   }
 }
 

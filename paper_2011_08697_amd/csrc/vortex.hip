@@ -151,16 +151,17 @@ __global__ __launch_bounds__(kVxBX) void vx_emit(VxGrid g, const unsigned long l
     vx_q(g, x + (a & 1u), y + ((a >> 1) & 1u), z + ((a >> 2) & 1u), t + ((a >> 3) & 1u), q1, st);
     vx_q(g, x + (b & 1u), y + ((b >> 1) & 1u), z + ((b >> 2) & 1u), t + ((b >> 3) & 1u), q2, st);
     // exact cofactors (each below 2^63); the nonzero ones share the puncture sign, so their sum has no
-    // cancellation and binary64 weights carry one rounding each
+    // cancellation, and binary64 weights from one reciprocal carry a few roundings each (relative error below
+    // 2^-50, far inside the binary32 points written)
     const long long C0 = q1[0] * q2[1] - q1[1] * q2[0];
     const long long C1 = -(q0[0] * q2[1] - q0[1] * q2[0]);
     const long long C2 = q0[0] * q1[1] - q0[1] * q1[0];
     double mu0 = 1.0 / 3.0, mu1 = 1.0 / 3.0, mu2 = 1.0 / 3.0;
     if (C0 != 0 || C1 != 0 || C2 != 0) {
-      const double D = ((double)C0 + (double)C1) + (double)C2;
-      mu0 = (double)C0 / D;
-      mu1 = (double)C1 / D;
-      mu2 = (double)C2 / D;
+      const double rD = 1.0 / (((double)C0 + (double)C1) + (double)C2);
+      mu0 = (double)C0 * rD;
+      mu1 = (double)C1 * rD;
+      mu2 = (double)C2 * rD;
     }
     tri_id[o] = v * 50 + ty;
     if (pos) {
