@@ -367,10 +367,11 @@ __global__ __launch_bounds__(256) void detect2d(Grid2 g, int TT, uint16_t* __res
 // ---------------------------------------------------------------------------------------------------------------
 namespace {
 
-// Side tables of the triangle types, built at compile time (read from constant memory).
+// Side tables of the triangle types, built at compile time.
 // kTri2Pack[ty] = M1 | M2 << 4.  kTri2Cof[ty][k] describes the k-th tetrahedron holding a triangle of type ty
-// (Alg. 1 pass 2, "tet.sides(2)" read backwards): bits 0-1 existence rule (1 always, 2 when p_a >= 1, 3 when
-// p_a + 1 <= N_a - 1), bits 2-3 the axis a, then its three other sides as (anchor slot, type) in 7-bit fields.
+// (Alg. 1 pass 2; the cells holding a triangle, the side-of query of Sec. 3.2): bits 0-1 existence rule (1 always,
+// 2 when p_a >= 1, 3 when p_a + 1 <= N_a - 1), bits 2-3 the axis a, then its three other sides as (anchor slot,
+// type) in 7-bit fields.
 enum { NB_SELF = 0, NB_MX, NB_PX, NB_MY, NB_PY, NB_MT, NB_PT };
 
 struct Tri2Tables {
@@ -422,7 +423,6 @@ constexpr Tri2Tables build_tri2_tables() {
   return r;
 }
 constexpr Tri2Tables kTri2Tab = build_tri2_tables();
-__constant__ Tri2Tables kTri2Dev = kTri2Tab;  // read per hit with a lane-dependent type (cached, no LDS)
 
 // The same tables as 24 words for an LDS copy: word 2 ty + k = cof[ty][k] (bits 0-24), and pack[ty] in bits 25-31
 // of word 2 ty.  Per-hit reads from LDS leave the vector memory counter to the stores, which a global table read
@@ -1284,6 +1284,7 @@ struct SparseWave {
   short x[3][kSpW];                // first hit of each anchor relative to its segment: rows (t,y), (t,y-1), (t-1,y)
   unsigned b[3];                   // first hit index of the segments of those rows
   unsigned short map[12 * TX];     // hit j of the segment -> anchor lane | type << 6
+  unsigned cof[24];                // triangle side words (Tri2Words), read per hit with a lane-dependent type
 };
 
 // mask row of each neighbour slot, and its offset row (-1: the row only holds larger partners)
@@ -1399,7 +1400,8 @@ __device__ __forceinline__ void emit2d_segment(const Grid2& g, int t, int y, int
     const int L = (int)(ent & 63u), ty = (int)(ent >> 6);
     const unsigned idx = base + j;
     const int ax = x0 + L;
-    const unsigned pk = kTri2Dev.pack[ty];
+    const unsigned w0 = W.cof[2 * ty], w1 = W.cof[2 * ty + 1];
+    const unsigned pk = w0 >> 25;
     const int m1 = pk & 15, m2 = pk >> 4;
     const int dx1 = m1 & 1, dy1 = (m1 >> 1) & 1, dt1 = (m1 >> 2) & 1;
     const int dx2 = dx1 + (m2 & 1), dy2 = dy1 + ((m2 >> 1) & 1), dt2 = dt1 + ((m2 >> 2) & 1);
@@ -1425,7 +1427,7 @@ __device__ __forceinline__ void emit2d_segment(const Grid2& g, int t, int y, int
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const unsigned w = kTri2Dev.cof[ty][k];
+      const unsigned w = k == 0 ? w0 : w1;
       const int rule = w & 3, axis = (w >> 2) & 3;
       const int pa = axis == 0 ? ax : (axis == 1 ? y : t);
       const int Na = axis == 0 ? nx : (axis == 1 ? ny : nt);
@@ -1534,6 +1536,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void e
   __shared__ SparseWave sw[4];
   __shared__ unsigned long long red[3][4];
   SparseWave& W = sw[threadIdx.x >> 6];
+  if ((threadIdx.x & 63) < 24) W.cof[threadIdx.x & 63] = kTri2WordsDev.w[threadIdx.x & 63];
+  wave_lds_sync();
   const long long nblk = ((long long)(g.t_end - g.t_begin) * g.ny * g.nxt + 63) / 64;
   const long long nw = (long long)gridDim.x * 4;
   unsigned st = 0;
@@ -1627,6 +1631,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void e
                                                              unsigned* status) {
   __shared__ SparseWave sw[4];
   SparseWave& W = sw[threadIdx.x >> 6];
+  if ((threadIdx.x & 63) < 24) W.cof[threadIdx.x & 63] = kTri2WordsDev.w[threadIdx.x & 63];
+  wave_lds_sync();
   const long long nblk = bprefix[nser];
   const long long nw = (long long)gridDim.x * 4;
   unsigned st = 0;
