@@ -531,7 +531,7 @@ static int cell_sides(const mesh_t* m, int64_t cid, int64_t* fids) {
   return 1;
 }
 
-/* Cells that contain a face (Sec. 3.2 "side_of"): brute force over the cells anchored at the face's anchor or
+/* Cells that contain a face (the side-of query of Sec. 3.2): brute force over the cells anchored at the face's anchor or
  * one step below it along any axis, keeping those whose side list holds the face. */
 static int face_cofaces(const mesh_t* m, int64_t fid, int64_t* cids) {
   int64_t g = fid / m->nface;
