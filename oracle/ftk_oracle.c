@@ -495,8 +495,8 @@ static void eval_face(const mesh_t* m, int64_t fid, int want_details, face_eval_
 }
 
 /* Sides of a cell (its 2-simplex faces, Alg. 1 pass 2; the sides query of Sec. 3.2): drop one vertex of the chain
- * and re-anchor at the lowest remaining vertex; the masks are the differences of consecutive remaining vertices.  Returns face ids, or -1 for a side
- * that leaves the grid (cannot happen for a valid cell). */
+ * and re-anchor at the lowest remaining vertex; the masks are the differences of consecutive remaining vertices.
+ * Returns face ids, or -1 for a side that leaves the grid (cannot happen for a valid cell). */
 static int face_type_of(const mesh_t* m, const int8_t* masks) {
   for (int t = 0; t < m->nface; ++t) {
     int same = 1;
