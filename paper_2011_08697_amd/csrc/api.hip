@@ -2188,10 +2188,11 @@ ftk_status ftk_track_cp_mesh(const ftk_mesh* m, const float* field, int64_t nt, 
   long long* base = sc.get<long long>((size_t)G);
   long long* tmp = sc.get<long long>(ftk::scan_tmp_elems(G));
   Ctl* dctl = sc.get<Ctl>(1);
-  if (!flag || !gsum || !base || !tmp || !dctl) return fail(FTK_ERR_OOM, "scratch allocation failed");
+  float* ft = sc.get<float>((size_t)(2 * nv * nt));
+  if (!flag || !gsum || !base || !tmp || !dctl || !ft) return fail(FTK_ERR_OOM, "scratch allocation failed");
   HIP_TRY(hipMemsetAsync(dctl, 0, sizeof(Ctl), s));
   const float qscale = std::ldexp(1.0f, o.quant_log2);
-  HIP_TRY(ftk::launch_pm_test(m->xy, m->tri, m->edge, m->tri_edge, field, nv, nf, ne, (int)nt, qscale, flag,
+  HIP_TRY(ftk::launch_pm_test(m->xy, m->tri, m->edge, m->tri_edge, field, nv, nf, ne, (int)nt, qscale, ft, flag,
                               &dctl->status, s));
   HIP_TRY(ftk::launch_group16_bases(flag, NF, false, gsum, base, &dctl->total, tmp, s));
   Ctl h;

@@ -184,9 +184,10 @@ hipError_t launch_vx_emit(const float* psi, int nx, int ny, int nz, int nt, floa
 // Critical points on an extruded triangle mesh (prism.hip): face tests over nt * S faces (flag, allocated to a
 // multiple of 16 bytes), then emission and the tetrahedron unions, with the hit offsets from the group bases of the
 // flags (offsets16.h).
+// ft_scratch: 2 nv nt floats (the field copied vertex-major for the test).
 hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
-                          long long nv, long long nf, long long ne, int nt, float qscale, unsigned char* flag,
-                          unsigned* status, hipStream_t s);
+                          long long nv, long long nf, long long ne, int nt, float qscale, float* ft_scratch,
+                          unsigned char* flag, unsigned* status, hipStream_t s);
 hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
                           long long nv, long long nf, long long ne, int nt, float qscale, const unsigned char* flag,
                           const long long* base, long long* face_id, float* pos, unsigned* parent, unsigned* status,

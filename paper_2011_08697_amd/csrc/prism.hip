@@ -8,8 +8,9 @@
 // +1), and the interior faces (v0, v1, v2') and (v0, v1', v2') of T (nf + 2 ne + 2T, +1); interval faces exist for
 // t < nt - 1.
 //
-//   pm_test  -- one lane per (face, step): the puncture test of the quantised 2D vectors at its three vertices in
-//               global order (SoS signs of the three vertex-pair determinants, as in the regular path).
+//   pm_test  -- one lane per face, all steps (on a vertex-major copy of the field): the puncture test of the
+//               quantised 2D vectors at its three vertices in global order (SoS signs of the three vertex-pair
+//               determinants, as in the regular path).
 //   pm_emit  -- face ids, points from the exact cofactors (Eq. 2) in (x, y, t), identity parents.
 //   pm_unite -- one lane per (prism, step): the two punctured faces of each of its three tetrahedra are united.
 #include "common.h"
@@ -81,24 +82,66 @@ __device__ __forceinline__ unsigned pm_sos2(const long long* a, const long long*
   return 0u;
 }
 
-__global__ void pm_test(PmMesh m, unsigned char* __restrict__ flag, unsigned* __restrict__ status) {
-  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int t = blockIdx.y;
-  if (f >= m.S) return;
-  const long long id = (long long)t * m.S + f;
-  if (f >= m.nf && t == m.nt - 1) {  // interval faces need step t + 1
-    flag[id] = 0;
-    return;
+// quantised value of one field component (as pm_q)
+__device__ __forceinline__ long long pm_q1(float v, float qscale, unsigned& st) {
+  const float x = v * qscale;
+  if (!isfinite(x)) {
+    st |= ST_NONFINITE;
+    return 0;
   }
+  if (!(fabsf(x) < 2147483648.0f)) {
+    st |= ST_RANGE;
+    return 0;
+  }
+  return (long long)rintf(x);
+}
+
+// The field vertex-major, [nv][nt] pairs (u, v): a face's vertices are scattered over the mesh, so the test below
+// reads each vertex's values for several steps from one or two cache lines instead of one line per step.
+__global__ void pm_vertex_major(const float* __restrict__ field, long long nv, int nt, float2* __restrict__ ft) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  for (int t = 0; t < nt; ++t)
+    ft[v * nt + t] = make_float2(field[(long long)(2 * t) * nv + v], field[(long long)(2 * t + 1) * nv + v]);
+}
+
+// One lane per local face, all steps: the values of its vertices for a block of 8 steps (and the next step, for
+// the interval faces) are loaded together, then each step's puncture test.
+constexpr int kPmSteps = 8;
+__global__ void pm_test(PmMesh m, const float2* __restrict__ ft, unsigned char* __restrict__ flag,
+                        unsigned* __restrict__ status) {
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= m.S) return;
   int v[3], dt[3];
   pm_face(m, f, v, dt);
   unsigned st = 0;
-  long long q[3][2];
+  for (int tb = 0; tb < m.nt; tb += kPmSteps) {
+    float2 w[3][kPmSteps + 1];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) pm_q(m, v[i], t + dt[i], q[i], st);
-  // cofactor signs +S(1,2), -S(0,2), +S(0,1) agree
-  const unsigned s01 = pm_sos2(q[0], q[1]), s02 = pm_sos2(q[0], q[2]), s12 = pm_sos2(q[1], q[2]);
-  flag[id] = (s12 == s01 && s02 != s01) ? 1 : 0;
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k <= kPmSteps; ++k) w[i][k] = ft[(long long)v[i] * m.nt + min(tb + k, m.nt - 1)];
+#pragma unroll
+    for (int k = 0; k < kPmSteps; ++k) {
+      const int t = tb + k;
+      if (t >= m.nt) break;
+      const long long id = (long long)t * m.S + f;
+      if (f >= m.nf && t == m.nt - 1) {  // interval faces need step t + 1
+        flag[id] = 0;
+        continue;
+      }
+      long long q[3][2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float2 a = dt[i] ? w[i][k + 1] : w[i][k];
+        q[i][0] = pm_q1(a.x, m.qscale, st);
+        q[i][1] = pm_q1(a.y, m.qscale, st);
+      }
+      // cofactor signs +S(1,2), -S(0,2), +S(0,1) agree
+      const unsigned s01 = pm_sos2(q[0], q[1]), s02 = pm_sos2(q[0], q[2]), s12 = pm_sos2(q[1], q[2]);
+      flag[id] = (s12 == s01 && s02 != s01) ? 1 : 0;
+    }
+  }
   // every vertex value is checked by the ordinal faces of its triangles (each vertex belongs to one)
   if (st && f < m.nf) atomicOr(status, st);
 }
@@ -172,10 +215,12 @@ __global__ void pm_unite(PmMesh m, const unsigned char* __restrict__ flag, const
 }  // namespace
 
 hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
-                          long long nv, long long nf, long long ne, int nt, float qscale, unsigned char* flag,
-                          unsigned* status, hipStream_t s) {
+                          long long nv, long long nf, long long ne, int nt, float qscale, float* ft_scratch,
+                          unsigned char* flag, unsigned* status, hipStream_t s) {
   const PmMesh m{xy, tri, edge, tri_edge, field, nv, nf, ne, nf + 2 * ne + 2 * nf, nt, qscale};
-  pm_test<<<dim3((unsigned)((m.S + 255) / 256), (unsigned)nt), 256, 0, s>>>(m, flag, status);
+  float2* ft = reinterpret_cast<float2*>(ft_scratch);
+  pm_vertex_major<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(field, nv, nt, ft);
+  pm_test<<<(unsigned)((m.S + 255) / 256), 256, 0, s>>>(m, ft, flag, status);
   return hipGetLastError();
 }
 
