@@ -391,7 +391,8 @@ typedef struct ftk_mesh ftk_mesh;
 ftk_status ftk_mesh_create(const float* xy, int64_t nv, const int32_t* tri, int64_t nf, ftk_stream_t stream,
                            ftk_mesh** m);
 void ftk_mesh_destroy(ftk_mesh* m);
-/* Tracking on a mesh handle (no host work besides the two count read-backs). */
+/* Tracking on a mesh handle (no host work besides the two count read-backs).  Scratch includes a vertex-major copy
+ * of the field (8 nv nt bytes) besides one flag byte per spacetime face. */
 ftk_status ftk_track_cp_mesh(const ftk_mesh* m, const float* field, int64_t nt, const ftk_options* opt,
                              ftk_stream_t stream, ftk_mesh_result* out);
 /* One-shot form: create, track, destroy. */

@@ -97,12 +97,28 @@ __device__ __forceinline__ long long pm_q1(float v, float qscale, unsigned& st) 
 }
 
 // The field vertex-major, [nv][nt] pairs (u, v): a face's vertices are scattered over the mesh, so the test below
-// reads each vertex's values for several steps from one or two cache lines instead of one line per step.
-__global__ void pm_vertex_major(const float* __restrict__ field, long long nv, int nt, float2* __restrict__ ft) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
-  for (int t = 0; t < nt; ++t)
-    ft[v * nt + t] = make_float2(field[(long long)(2 * t) * nv + v], field[(long long)(2 * t + 1) * nv + v]);
+// reads each vertex's values for several steps from one or two cache lines instead of one line per step.  A
+// workgroup moves a tile of 64 vertices x 16 steps through LDS: reads run along the vertices, writes along the steps
+// of each vertex (128 contiguous bytes).
+constexpr int kPmTV = 64, kPmTT = 16;
+__global__ __launch_bounds__(256) void pm_vertex_major(const float* __restrict__ field, long long nv, int nt,
+                                                       float2* __restrict__ ft) {
+  __shared__ float tile[kPmTT][2][kPmTV + 1];
+  const long long v0 = (long long)blockIdx.x * kPmTV;
+  const int t0 = blockIdx.y * kPmTT;
+  for (int e = threadIdx.x; e < kPmTT * 2 * kPmTV; e += 256) {
+    const int dt = e / (2 * kPmTV), c = (e / kPmTV) & 1, dv = e % kPmTV;
+    const long long v = v0 + dv;
+    const int t = t0 + dt;
+    tile[dt][c][dv] = (v < nv && t < nt) ? field[(long long)(2 * t + c) * nv + v] : 0.0f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kPmTV * kPmTT; e += 256) {
+    const int dv = e / kPmTT, dt = e % kPmTT;
+    const long long v = v0 + dv;
+    const int t = t0 + dt;
+    if (v < nv && t < nt) ft[v * nt + t] = make_float2(tile[dt][0][dv], tile[dt][1][dv]);
+  }
 }
 
 // One lane per local face, all steps: the values of its vertices for a block of 8 steps (and the next step, for
@@ -219,7 +235,8 @@ hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, cons
                           unsigned char* flag, unsigned* status, hipStream_t s) {
   const PmMesh m{xy, tri, edge, tri_edge, field, nv, nf, ne, nf + 2 * ne + 2 * nf, nt, qscale};
   float2* ft = reinterpret_cast<float2*>(ft_scratch);
-  pm_vertex_major<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(field, nv, nt, ft);
+  pm_vertex_major<<<dim3((unsigned)((nv + kPmTV - 1) / kPmTV), (unsigned)((nt + kPmTT - 1) / kPmTT)), 256, 0, s>>>(
+      field, nv, nt, ft);
   pm_test<<<(unsigned)((m.S + 255) / 256), 256, 0, s>>>(m, ft, flag, status);
   return hipGetLastError();
 }
