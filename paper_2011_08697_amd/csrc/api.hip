@@ -2087,6 +2087,7 @@ struct ftk_mesh {
   int* tri = nullptr;       // [nf][3] ascending per row
   int* edge = nullptr;      // [ne][2] a < b, ascending
   int* tri_edge = nullptr;  // [nf][3] edges (v0 v1), (v1 v2), (v0 v2)
+  int* edge_tri = nullptr;  // [ne][2] triangles of each edge (-1: none); null if an edge has more than two
 };
 
 extern "C" {
@@ -2137,6 +2138,18 @@ ftk_status ftk_mesh_create(const float* xy, int64_t nv, const int32_t* tri, int6
   }
   for (size_t k = 0; k < keys.size(); ++k)
     hte[k] = (int)(std::lower_bound(ukeys.begin(), ukeys.end(), keys[k]) - ukeys.begin());
+  std::vector<int> het((size_t)(2 * ne), -1);  // triangles of each edge
+  bool two_per_edge = true;
+  for (long long T = 0; T < nf && two_per_edge; ++T)
+    for (int k = 0; k < 3; ++k) {
+      int* slot = &het[(size_t)(2 * hte[(size_t)(3 * T + k)])];
+      if (slot[0] < 0)
+        slot[0] = (int)T;
+      else if (slot[1] < 0)
+        slot[1] = (int)T;
+      else
+        two_per_edge = false;
+    }
   ftk_mesh* m = new ftk_mesh();
   m->xy = xy;
   m->nv = nv;
@@ -2149,6 +2162,11 @@ ftk_status ftk_mesh_create(const float* xy, int64_t nv, const int32_t* tri, int6
   if (e == hipSuccess) e = hipMemcpyAsync(m->edge, he.data(), sizeof(int) * 2 * (size_t)ne, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(m->tri_edge, hte.data(), sizeof(int) * 3 * (size_t)nf, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && two_per_edge) {
+    e = hipMalloc((void**)&m->edge_tri, sizeof(int) * 2 * (size_t)ne);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(m->edge_tri, het.data(), sizeof(int) * 2 * (size_t)ne, hipMemcpyHostToDevice, s);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors die on return
   if (e != hipSuccess) {
     ftk_mesh_destroy(m);
@@ -2163,6 +2181,7 @@ void ftk_mesh_destroy(ftk_mesh* m) {
   if (m->tri) (void)hipFree(m->tri);
   if (m->edge) (void)hipFree(m->edge);
   if (m->tri_edge) (void)hipFree(m->tri_edge);
+  if (m->edge_tri) (void)hipFree(m->edge_tri);
   delete m;
 }
 
@@ -2217,8 +2236,8 @@ ftk_status ftk_track_cp_mesh(const ftk_mesh* m, const float* field, int64_t nt, 
   }
   hipError_t hr = hipSuccess;
   if (nh > 0) {
-    hr = ftk::launch_pm_emit(m->xy, m->tri, m->edge, m->tri_edge, field, nv, nf, ne, (int)nt, qscale, flag, base,
-                             (long long*)r.face_id, r.pos, parent, &dctl->status, s);
+    hr = ftk::launch_pm_emit(m->xy, m->tri, m->edge, m->tri_edge, m->edge_tri, field, nv, nf, ne, (int)nt, qscale,
+                             flag, base, nh, (long long*)r.face_id, r.pos, parent, &dctl->status, s);
     if (hr == hipSuccess)
       hr = ftk::launch_uf_label(parent, (const long long*)r.face_id, (long long*)r.label, nh, dctl->cnt, s);
   }

@@ -188,10 +188,12 @@ hipError_t launch_vx_emit(const float* psi, int nx, int ny, int nz, int nt, floa
 hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
                           long long nv, long long nf, long long ne, int nt, float qscale, float* ft_scratch,
                           unsigned char* flag, unsigned* status, hipStream_t s);
-hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
-                          long long nv, long long nf, long long ne, int nt, float qscale, const unsigned char* flag,
-                          const long long* base, long long* face_id, float* pos, unsigned* parent, unsigned* status,
-                          hipStream_t s);
+// edge_tri: [ne][2] triangles of each edge (-1: none), or null for a mesh with an edge of more than two triangles
+// (the unions then visit every prism).
+hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const int* edge_tri,
+                          const float* field, long long nv, long long nf, long long ne, int nt, float qscale,
+                          const unsigned char* flag, const long long* base, long long n_hits, long long* face_id,
+                          float* pos, unsigned* parent, unsigned* status, hipStream_t s);
 // Type smoothing and run simplification along an order (head/heads: [n_hits] int / int64 scratch).
 hipError_t launch_smooth(const long long* order, const long long* offsets, const int* n_ends, long long n_traj,
                          long long n_hits, const uint8_t* type_in, int half, int* head, long long* heads,

@@ -12,7 +12,8 @@
 //               quantised 2D vectors at its three vertices in global order (SoS signs of the three vertex-pair
 //               determinants, as in the regular path).
 //   pm_emit  -- face ids, points from the exact cofactors (Eq. 2) in (x, y, t), identity parents.
-//   pm_unite -- one lane per (prism, step): the two punctured faces of each of its three tetrahedra are united.
+//   pm_unite_hits -- one lane per hit: the two punctured faces of each tetrahedron holding it are united (pm_unite,
+//               one lane per (prism, step), for meshes with an edge of more than two triangles).
 #include "common.h"
 #include "offsets16.h"
 #include "internal.h"
@@ -202,18 +203,88 @@ __global__ void pm_emit(PmMesh m, const unsigned char* __restrict__ flag, const 
   parent[o] = (unsigned)o;
 }
 
-__global__ void pm_unite(PmMesh m, const unsigned char* __restrict__ flag, const long long* __restrict__ gbase,
-                         unsigned* __restrict__ parent, unsigned* __restrict__ status) {
-  const long long T = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int t = blockIdx.y;
-  if (T >= m.nf || t >= m.nt - 1) return;
+// Spacetime face ids of the sides of the three tetrahedra a0 a1 a2 b2, a0 a1 b1 b2, a0 b0 b1 b2 of the prism of
+// triangle T between steps t and t + 1 (lower / upper edge and interior faces are +0 / +1).
+__device__ __forceinline__ void pm_prism_tets(const PmMesh& m, long long T, int t, long long (&tet)[3][4]) {
   const long long base = (long long)t * m.S;
   const int* te = m.tri_edge + 3 * T;
   const long long e01 = base + m.nf + 2LL * te[0], e12 = base + m.nf + 2LL * te[1], e02 = base + m.nf + 2LL * te[2];
   const long long in = base + m.nf + 2 * m.ne + 2 * T;
   const long long ord0 = base + T, ord1 = base + m.S + T;
-  // sides of a0 a1 a2 b2, a0 a1 b1 b2, a0 b0 b1 b2 (lower / upper edge and interior faces are +0 / +1)
-  const long long tet[3][4] = {{ord0, in, e02, e12}, {e01, in, in + 1, e12 + 1}, {e01 + 1, e02 + 1, in + 1, ord1}};
+  const long long v[3][4] = {{ord0, in, e02, e12}, {e01, in, in + 1, e12 + 1}, {e01 + 1, e02 + 1, in + 1, ord1}};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tet[k][j] = v[k][j];
+}
+
+// One lane per hit (Alg. 1 pass 2 from the punctured faces' side): each tetrahedron of each prism holding the
+// hit's face has exactly one other punctured side, united with it; any other count is an internal error.  Every
+// tetrahedron with a punctured side is reached from its hits, so this is the all-prism pass below restricted to
+// where it can act.  edge_tri: the (at most two) triangles of each mesh edge, -1 for none.
+__global__ void pm_unite_hits(PmMesh m, const int* __restrict__ edge_tri, const unsigned char* __restrict__ flag,
+                              const long long* __restrict__ gbase, const long long* __restrict__ face_id,
+                              long long n_hits, unsigned* __restrict__ parent, unsigned* __restrict__ status) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_hits) return;
+  const long long id = face_id[i];
+  const int t = (int)(id / m.S);
+  const long long f = id - (long long)t * m.S;
+  long long pT[2] = {0, 0};
+  int pt[2] = {0, 0}, np = 0;
+  if (f < m.nf) {  // a mesh triangle: bottom of the prism above it, top of the one below
+    if (t < m.nt - 1) {
+      pT[np] = f;
+      pt[np++] = t;
+    }
+    if (t >= 1) {
+      pT[np] = f;
+      pt[np++] = t - 1;
+    }
+  } else if (f < m.nf + 2 * m.ne) {  // an edge face: the prisms of the edge's triangles
+    const long long E = (f - m.nf) >> 1;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int T = edge_tri[2 * E + k];
+      if (T >= 0) {
+        pT[np] = T;
+        pt[np++] = t;
+      }
+    }
+  } else {  // an interior face of one prism
+    pT[np] = (f - m.nf - 2 * m.ne) >> 1;
+    pt[np++] = t;
+  }
+  for (int p = 0; p < np; ++p) {
+    long long tet[3][4];
+    pm_prism_tets(m, pT[p], pt[p], tet);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (tet[k][0] != id && tet[k][1] != id && tet[k][2] != id && tet[k][3] != id) continue;
+      int n = 0;
+      long long other = -1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (flag[tet[k][j]]) {
+          ++n;
+          if (tet[k][j] != id) other = tet[k][j];
+        }
+      if (n == 2)
+        uf_unite_cached(parent, (unsigned)i, (unsigned)off16(gbase, flag, other, false));
+      else
+        atomicOr(status, ST_INVARIANT);
+    }
+  }
+}
+
+// One lane per (prism, step), for meshes with an edge of more than two triangles (no edge -> triangle table).
+__global__ void pm_unite(PmMesh m, const unsigned char* __restrict__ flag, const long long* __restrict__ gbase,
+                         unsigned* __restrict__ parent, unsigned* __restrict__ status) {
+  const long long T = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (T >= m.nf || t >= m.nt - 1) return;
+  long long tet[3][4];
+  pm_prism_tets(m, T, t, tet);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     long long h[4];
@@ -241,14 +312,19 @@ hipError_t launch_pm_test(const float* xy, const int* tri, const int* edge, cons
   return hipGetLastError();
 }
 
-hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const float* field,
-                          long long nv, long long nf, long long ne, int nt, float qscale, const unsigned char* flag,
-                          const long long* base, long long* face_id, float* pos, unsigned* parent, unsigned* status,
-                          hipStream_t s) {
+hipError_t launch_pm_emit(const float* xy, const int* tri, const int* edge, const int* tri_edge, const int* edge_tri,
+                          const float* field, long long nv, long long nf, long long ne, int nt, float qscale,
+                          const unsigned char* flag, const long long* base, long long n_hits, long long* face_id,
+                          float* pos, unsigned* parent, unsigned* status, hipStream_t s) {
   const PmMesh m{xy, tri, edge, tri_edge, field, nv, nf, ne, nf + 2 * ne + 2 * nf, nt, qscale};
   pm_emit<<<dim3((unsigned)((m.S + 255) / 256), (unsigned)nt), 256, 0, s>>>(m, flag, base, face_id, pos, parent);
-  if (nt > 1)
+  if (edge_tri) {
+    if (n_hits > 0)
+      pm_unite_hits<<<(unsigned)((n_hits + 255) / 256), 256, 0, s>>>(m, edge_tri, flag, base, face_id, n_hits, parent,
+                                                                    status);
+  } else if (nt > 1) {
     pm_unite<<<dim3((unsigned)((nf + 255) / 256), (unsigned)(nt - 1)), 256, 0, s>>>(m, flag, base, parent, status);
+  }
   return hipGetLastError();
 }
 

@@ -68,6 +68,27 @@ def test_matches_oracle(case):
     assert_pos_close(g["pos"].cpu().numpy(), o.pos)
 
 
+def test_edge_of_three_triangles_matches_oracle():
+    """A mesh with an edge shared by three triangles (one more triangle on an interior edge of a grid mesh): the
+    unions then visit every prism instead of starting from the hits; results equal the oracle's."""
+    xy, tri = synth.kuhn_grid_mesh(9, 7)
+    a, b = (int(v) for v in sorted(tri[len(tri) // 2][:2]))
+    xy = np.concatenate([xy, (0.5 * (xy[a] + xy[b]) + np.array([0.13, 0.29], np.float32))[None]]).astype(np.float32)
+    tri = np.concatenate([tri, np.array([[a, b, len(xy) - 1]], np.int32)])
+    edges = np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [0, 2]]]), axis=1)
+    _, counts = np.unique(edges, axis=0, return_counts=True)
+    assert counts.max() == 3
+    rng = np.random.default_rng(4)
+    for field in (rng.integers(-2, 3, size=(5, 2, len(xy))).astype(np.float32) / 2 ** 20,
+                  _swirl(xy.astype(np.float64), 5, 7)):
+        g = _run(xy, tri, field)
+        o = M.track_cp_mesh(xy, tri, field)
+        assert g["n_hits"] == o.n_hits and g["n_trajectories"] == o.n_traj
+        assert np.array_equal(g["face_id"].cpu().numpy(), o.face_id)
+        assert np.array_equal(g["label"].cpu().numpy(), o.label)
+        assert_pos_close(g["pos"].cpu().numpy(), o.pos)
+
+
 def test_errors():
     xy, tri = synth.delaunay_mesh(20, seed=1)
     field = np.zeros((3, 2, len(xy)), np.float32)
