@@ -117,19 +117,31 @@ __device__ __forceinline__ long long vidx(const IsoGrid& g, int x, int y, int z,
 // Side of every vertex as one bit (a value equal to the isovalue counts as above), packed per 64 vertices of a row
 // by a wave ballot: the passes that need the 16 corners of a 4-cube read these words (L2-resident, shared by
 // neighbouring lanes) instead of 16 field values.  Non-finite values are reported here.
-__global__ __launch_bounds__(kIsoBX) void iso_bits(IsoGrid g, unsigned long long* __restrict__ bits,
-                                                    unsigned* __restrict__ status) {
-  const int x = blockIdx.x * kIsoBX + threadIdx.x;
-  const int y = blockIdx.y;
-  const int z = blockIdx.z % g.nz, t = blockIdx.z / g.nz;
-  bool above = false;
-  if (x < g.nx) {
-    const float v = g.f[vidx(g, x, y, z, t)];
-    if (!isfinite(v)) atomicOr(status, ST_NONFINITE);
-    above = v >= g.c;
+// Word k of the packed sides covers vertices 64 (k mod nwx) .. + 63 of grid row k / nwx (rows in (t, z, y) order).
+// A wavefront packs kBitsWords consecutive words, their loads in flight together.
+constexpr int kBitsWords = 4;
+__global__ __launch_bounds__(256) void iso_bits(IsoGrid g, long long n_words, unsigned long long* __restrict__ bits,
+                                                unsigned* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const long long k0 = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * kBitsWords;
+  float v[kBitsWords];
+  bool in[kBitsWords];
+#pragma unroll
+  for (int j = 0; j < kBitsWords; ++j) {
+    const long long k = min(k0 + j, n_words - 1);
+    const long long row = k / g.nwx;
+    const int x = (int)(k - row * g.nwx) * 64 + lane;
+    in[j] = k0 + j < n_words && x < g.nx;
+    v[j] = g.f[row * g.nx + min(x, g.nx - 1)];
   }
-  const unsigned long long w = __ballot(above);
-  if ((threadIdx.x & 63) == 0 && x < g.nx) bits[((long long)blockIdx.z * g.ny + y) * g.nwx + (x >> 6)] = w;
+  unsigned bad = 0;
+#pragma unroll
+  for (int j = 0; j < kBitsWords; ++j) {
+    if (in[j] && !isfinite(v[j])) bad = ST_NONFINITE;
+    const unsigned long long w = __ballot(in[j] && v[j] >= g.c);
+    if (lane == 0 && k0 + j < n_words) bits[k0 + j] = w;
+  }
+  if (bad) atomicOr(status, bad);
 }
 
 // above bits of the 16 cube corners (bit cm) and their validity (bit cm: corner in the grid)
@@ -402,7 +414,8 @@ hipError_t launch_iso_count(const float* f, int nx, int ny, int nz, int nt, floa
                             unsigned short* emask, unsigned char* hcnt, unsigned char* tcnt, unsigned* status,
                             hipStream_t s) {
   const IsoGrid g{f, nx, ny, nz, nt, c, bits, (nx + 63) / 64};
-  iso_bits<<<iso_grid(g), kIsoBX, 0, s>>>(g, bits, status);
+  const long long n_words = (long long)nt * nz * ny * g.nwx;
+  iso_bits<<<(unsigned)((n_words + 4 * kBitsWords - 1) / (4 * kBitsWords)), 256, 0, s>>>(g, n_words, bits, status);
   iso_count<<<iso_grid(g), kIsoBX, 0, s>>>(g, emask, hcnt, tcnt, status);
   return hipGetLastError();
 }
