@@ -89,3 +89,59 @@ def test_moving_zero_on_a_delaunay_mesh():
     ordinal = (r.face_id % r.S) < r.nf
     steps = r.face_id[ordinal] // r.S
     assert np.array_equal(np.sort(steps), np.arange(nt))
+
+
+def _book_mesh():
+    """A grid mesh with one more triangle on an interior edge (an edge of three triangles)."""
+    xy, tri = synth.kuhn_grid_mesh(7, 6)
+    a, b = (int(v) for v in sorted(tri[len(tri) // 2][:2]))
+    xy = np.concatenate([xy, (0.5 * (xy[a] + xy[b]) + np.array([0.13, 0.29], np.float32))[None]]).astype(np.float32)
+    return xy, np.concatenate([tri, np.array([[a, b, len(xy) - 1]], np.int32)])
+
+
+@pytest.mark.parametrize("mesh", ["delaunay", "book"])
+def test_tetrahedra_reached_from_punctured_faces(mesh):
+    """The unions may start from the punctured faces: a face lies in the prisms of its triangle (a mesh triangle: the
+    prism above it and the one below), of its edge's triangles (edge faces) or of its triangle (interior faces), and
+    the tetrahedra of those prisms that hold it are exactly the tetrahedra with a punctured side (boundary edges
+    with one triangle and an edge with three included)."""
+    xy, tri = synth.delaunay_mesh(40, seed=6) if mesh == "delaunay" else _book_mesh()
+    nt = 4
+    rng = np.random.default_rng(11)
+    field = rng.integers(-1, 2, size=(nt, 2, len(xy))).astype(np.float32) / 2 ** 20
+    r = M.track_cp_mesh(xy, tri, field)
+    tri_s = np.sort(np.asarray(tri, np.int64), axis=1)
+    edges = M.mesh_edges(tri_s)
+    nv, nf, ne = len(xy), r.nf, r.ne
+    edge_index = {(int(a), int(b)): i for i, (a, b) in enumerate(edges)}
+    edge_tris = [[] for _ in range(ne)]
+    for T, (a0, a1, a2) in enumerate(tri_s):
+        for e in ((a0, a1), (a1, a2), (a0, a2)):
+            edge_tris[edge_index[(int(e[0]), int(e[1]))]].append(T)
+
+    def prism_tets(T, t):
+        A = [(int(v), t) for v in tri_s[T]]
+        B = [(v, t + 1) for v, _ in A]
+        return [frozenset([A[0], A[1], A[2], B[2]]), frozenset([A[0], A[1], B[1], B[2]]),
+                frozenset([A[0], B[0], B[1], B[2]])]
+
+    all_tets = {(T, t, k): tet for t in range(nt - 1) for T in range(nf) for k, tet in enumerate(prism_tets(T, t))}
+    hit_faces = {frozenset(_face_vertices(r, f, nv, tri_s, edges)) for f in r.face_id}
+    every = {key for key, tet in all_tets.items() if any(tet - {p} in hit_faces for p in tet)}
+    reached = set()
+    for f in r.face_id:
+        t, loc = divmod(int(f), r.S)
+        if loc < nf:
+            prisms = [(loc, t)] * (t < nt - 1) + [(loc, t - 1)] * (t >= 1)
+        elif loc < nf + 2 * ne:
+            prisms = [(T, t) for T in edge_tris[(loc - nf) // 2]]
+        else:
+            prisms = [((loc - nf - 2 * ne) // 2, t)]
+        face = frozenset(_face_vertices(r, f, nv, tri_s, edges))
+        mine = {(T, tp, k) for T, tp in prisms for k, tet in enumerate(prism_tets(T, tp)) if face <= tet}
+        # each face by itself: its prisms hold every tetrahedron that has it as a side
+        assert mine == {key for key, tet in all_tets.items() if face <= tet}, int(f)
+        reached |= mine
+    assert len(every) > 0 and reached == every
+    if mesh == "book":
+        assert max(len(x) for x in edge_tris) == 3
